@@ -1,0 +1,146 @@
+/*
+ * ofv.h - C ABI of the dense optical-flow velocimetry (OFV) estimator on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The estimator is the one defined in section "Live-Optical Flow
+ * Velocimetry" of Pimienta & Aider, "High Resolution and High-Speed Live
+ * Optical Flow Velocimetry" (arXiv 2509.25924): for every pixel m it finds the
+ * displacement V that minimises the symmetric sum of squared differences
+ *     sum_{k in N(m)} [ I0(k - V/2) - I1(k + V/2) ]^2          (Eq. of_symmetric)
+ * over a square window N(m) of radius KR, with Gauss-Newton iterations at
+ * every level of a Gaussian pyramid, coarse to fine, after a local
+ * intensity normalisation (the six-step pipeline of that section).  The
+ * output is one vector per pixel, in pixels per frame pair.
+ *
+ * Conventions shared by every entry point
+ * ----------------------------------------
+ * - Every function returns an ofv_status; none throws, aborts or exits.
+ * - Pointers named "device" are device memory owned by the caller; the
+ *   library never frees or retains them beyond the call.  All work is
+ *   enqueued on the handle's stream and the call returns without
+ *   synchronising: results are valid once that stream has completed.
+ *   Device faults surface as OFV_ERR_DEVICE from a later call, or at the
+ *   caller's own synchronisation.
+ * - Argument errors are detected on the host before anything is enqueued;
+ *   nothing is written on error.  ofv_last_error() then holds a message.
+ * - The compute entry points never allocate and never synchronise: the
+ *   handle's workspace is sized once by ofv_create().
+ * - Flow fields are planar float32 [2][H][W] (u plane then v plane, rows of
+ *   W elements, no padding).  u is the displacement along +x (columns), v
+ *   along +y (rows); V maps frame0 to frame1 and is defined at the
+ *   midpoint of the two frames (Eq. of_symmetric).
+ * - A handle must not be used from two threads at once.
+ */
+#ifndef OFV_H
+#define OFV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ofv_ctx* ofv_handle;
+
+typedef enum {
+  OFV_OK = 0,
+  OFV_ERR_INVALID_ARG = -1,   /* null pointer, bad size, bad parameter value, aliasing */
+  OFV_ERR_UNSUPPORTED = -2,   /* valid request this build does not implement (e.g. KR > OFV_MAX_KERNEL_RADIUS) */
+  OFV_ERR_CAPACITY = -3,      /* image or batch larger than the handle's workspace */
+  OFV_ERR_OUT_OF_MEMORY = -4, /* device allocation failed in ofv_create */
+  OFV_ERR_DEVICE = -5         /* HIP runtime error (launch failure, device fault) */
+} ofv_status;
+
+typedef enum { OFV_PIX_U8 = 0, OFV_PIX_U16 = 1, OFV_PIX_F32 = 2 } ofv_pixel_type;
+
+/* Storage of the normalised images and their pyramid levels.  Arithmetic is
+ * always float32; F16/BF16 halve the bytes streamed per pixel. */
+typedef enum { OFV_STORE_F32 = 0, OFV_STORE_F16 = 1, OFV_STORE_BF16 = 2 } ofv_storage;
+
+#define OFV_MAX_LEVELS 16
+#define OFV_MAX_KERNEL_RADIUS 12
+#define OFV_MAX_NORM_RADIUS 16
+
+/* One camera frame in device memory. */
+typedef struct {
+  const void* data;   /* device pointer to pixel (0, 0) */
+  int32_t width;      /* >= 1 */
+  int32_t height;     /* >= 1 */
+  int64_t pitch;      /* elements per row, >= width; a crop is an offset pointer with the parent's pitch */
+  int32_t type;       /* ofv_pixel_type */
+  int32_t bit_depth;  /* integer frames: significant bits, 1..8 for U8, 1..16 for U16 (right-aligned);
+                         intensity = value / (2^bit_depth - 1).  Ignored for F32 (used as given). */
+} ofv_image;
+
+/* Estimator parameters (section "Live-Optical Flow Velocimetry"; ranges of
+ * Table tab:OFPIV). */
+typedef struct {
+  int32_t num_levels;    /* pyramid levels in total = PSL + 1, 1..OFV_MAX_LEVELS (1 = no pyramid) */
+  int32_t kernel_radius; /* KR, 1..OFV_MAX_KERNEL_RADIUS: window (2 KR + 1)^2, truncated at the image border */
+  int32_t iterations;    /* IT >= 1 Gauss-Newton iterations at every level */
+  int32_t norm_radius;   /* NR, 0..OFV_MAX_NORM_RADIUS: local z-score window (2 NR + 1)^2; 0 = off */
+  float norm_eps;        /* > 0 typical 1e-4: added to the local variance (intensity units in [0,1], squared) */
+  float reg_rel;         /* >= 0, typical 1e-3: damping lambda = reg_rel * trace(A) + reg_abs */
+  float reg_abs;         /* >= 0, typical 1e-9; reg_rel = reg_abs = 0 gives NaN on textureless windows */
+  int32_t storage;       /* ofv_storage */
+  uint32_t flags;        /* reserved, must be 0 */
+} ofv_params;
+
+/* Fill *p with the defaults: 3 levels, KR 4, IT 3, NR 1, eps 1e-4,
+ * reg_rel 1e-3, reg_abs 1e-9, F32 storage.  p == NULL is ignored. */
+void ofv_default_params(ofv_params* p);
+
+/* Create a handle on HIP device `device` whose workspace holds up to
+ * `max_batch` pairs of up to max_width x max_height pixels.  `stream` is a
+ * hipStream_t (NULL = the default stream) on which all work is enqueued.
+ * Allocates the workspace (pyramids and flow ping-pong buffers, about
+ * 8/3 * 4 + 16 bytes per pixel per pair).  On error *out is set to NULL. */
+ofv_status ofv_create(ofv_handle* out, int device, int max_width, int max_height, int max_batch,
+                      void* stream);
+
+/* Change the stream later calls enqueue on (a hipStream_t, NULL = default). */
+ofv_status ofv_set_stream(ofv_handle h, void* stream);
+
+/* Bytes of device workspace the handle owns (writes *bytes). */
+ofv_status ofv_workspace_bytes(ofv_handle h, size_t* bytes);
+
+/* Dense flow of one pair, starting from zero flow at the coarsest level.
+ * frame0 and frame1 must have equal width and height; flow_out is a device
+ * float32 [2][H][W] buffer that must not overlap either frame. */
+ofv_status ofv_compute_flow(ofv_handle h, const ofv_image* frame0, const ofv_image* frame1,
+                            const ofv_params* params, float* flow_out);
+
+/* As ofv_compute_flow, with an optional initial field flow_init (device
+ * float32 [2][H][W], NULL = zero).  The initial field is restricted to the
+ * coarsest level by REDUCE / 2 per level before any output is written, so
+ * flow_init may alias flow_out (time-resolved warm start). */
+ofv_status ofv_compute_flow_ex(ofv_handle h, const ofv_image* frame0, const ofv_image* frame1,
+                               const ofv_params* params, const float* flow_init, float* flow_out);
+
+/* n pairs, possibly of different sizes, processed together: every stage
+ * runs as one launch over all pairs (per pyramid level and iteration).
+ * frame0, frame1 and flow_out are arrays of n entries; flow_init is NULL or
+ * an array of n pointers (entries may be NULL).  1 <= n <= max_batch.
+ * Results equal n separate ofv_compute_flow_ex calls. */
+ofv_status ofv_compute_flow_batch(ofv_handle h, int n, const ofv_image* frame0, const ofv_image* frame1,
+                                  const ofv_params* params, const float* const* flow_init,
+                                  float* const* flow_out);
+
+/* Release the handle and its workspace.  NULL is accepted.  Synchronises the
+ * handle's stream first. */
+ofv_status ofv_destroy(ofv_handle h);
+
+/* Static description of a status code. */
+const char* ofv_status_string(ofv_status s);
+
+/* Message of the last failing call on h (empty if none); valid until the
+ * next call on h.  h == NULL gives the message of the last failing
+ * ofv_create on this thread. */
+const char* ofv_last_error(ofv_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OFV_H */

@@ -1,0 +1,245 @@
+"""Python entry points of the OFV estimator (thin marshalling over libofv.so).
+
+Every step runs in the HIP kernels of libofv.so; this module only turns
+torch CUDA tensors into the C structs of include/ofv.h and passes the
+current torch stream.  Tensors must live on a ROCm device.
+"""
+from __future__ import annotations
+
+import ctypes
+from ctypes import byref, c_size_t, c_void_p
+from typing import Dict, List, Optional, Sequence
+
+import torch
+
+from . import _lib
+from ._lib import OfvImage, OfvParams, check, load
+
+_PIX = {torch.uint8: _lib.PIX_U8, torch.uint16: _lib.PIX_U16, torch.int16: _lib.PIX_U16,
+        torch.float32: _lib.PIX_F32}
+_STORE_DTYPE = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}
+
+PARAM_KEYS = ("num_levels", "kernel_radius", "iterations", "norm_radius", "norm_eps", "reg_rel", "reg_abs")
+
+
+def _stream_ptr(device: int) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+class Handle:
+    """Owns an ofv_handle: workspace for up to max_batch pairs of max_width x max_height."""
+
+    def __init__(self, max_width: int, max_height: int, max_batch: int = 1, device: Optional[int] = None):
+        lib = load()
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        self.max_width, self.max_height, self.max_batch = int(max_width), int(max_height), int(max_batch)
+        h = c_void_p()
+        check(lib.ofv_create(byref(h), self.device, self.max_width, self.max_height, self.max_batch,
+                             c_void_p(_stream_ptr(self.device))))
+        self._h = h
+
+    @property
+    def ptr(self) -> c_void_p:
+        if self._h is None:
+            raise RuntimeError("handle is closed")
+        return self._h
+
+    def bind_stream(self) -> None:
+        check(load().ofv_set_stream(self.ptr, c_void_p(_stream_ptr(self.device))), self.ptr)
+
+    def workspace_bytes(self) -> int:
+        n = c_size_t()
+        check(load().ofv_workspace_bytes(self.ptr, byref(n)), self.ptr)
+        return n.value
+
+    def fits(self, w: int, h: int, n: int = 1) -> bool:
+        return w <= self.max_width and h <= self.max_height and n <= self.max_batch
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            check(load().ofv_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_default: Dict[int, Handle] = {}
+
+
+def default_handle(w: int, h: int, n: int = 1, device: Optional[int] = None) -> Handle:
+    dev = torch.cuda.current_device() if device is None else int(device)
+    hd = _default.get(dev)
+    if hd is None or not hd.fits(w, h, n):
+        mw, mh, mn = w, h, n
+        if hd is not None:
+            mw, mh, mn = max(w, hd.max_width), max(h, hd.max_height), max(n, hd.max_batch)
+            torch.cuda.synchronize(dev)
+            hd.close()
+        hd = Handle(mw, mh, mn, dev)
+        _default[dev] = hd
+    hd.bind_stream()
+    return hd
+
+
+def image_desc(t: torch.Tensor, bit_depth: Optional[int] = None) -> OfvImage:
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError("frames must be 2-D tensors with unit column stride")
+    if not t.is_cuda:
+        raise ValueError("frames must be device tensors")
+    if t.dtype not in _PIX:
+        raise ValueError(f"unsupported frame dtype {t.dtype}")
+    typ = _PIX[t.dtype]
+    if bit_depth is None:
+        bit_depth = {torch.uint8: 8, torch.uint16: 16, torch.int16: 16}.get(t.dtype, 0)
+    return OfvImage(t.data_ptr(), t.shape[1], t.shape[0], t.stride(0), typ, int(bit_depth))
+
+
+def params_struct(params: Dict) -> OfvParams:
+    p = OfvParams()
+    load().ofv_default_params(byref(p))
+    for k in PARAM_KEYS:
+        if k in params:
+            setattr(p, k, params[k])
+    st = params.get("storage", "f32")
+    p.storage = _lib.STORE[st] if isinstance(st, str) else int(st)
+    return p
+
+
+def compute_flow(frame0: torch.Tensor, frame1: torch.Tensor, params: Dict, flow_init: Optional[torch.Tensor] = None,
+                 bit_depth: Optional[int] = None, out: Optional[torch.Tensor] = None,
+                 handle: Optional[Handle] = None) -> torch.Tensor:
+    """Dense flow [2, H, W] float32 (u, v in px/frame) of one pair."""
+    h, w = frame0.shape
+    hd = handle or default_handle(w, h, 1, frame0.device.index)
+    if handle is not None:
+        hd.bind_stream()
+    if out is None:
+        out = torch.empty((2, h, w), dtype=torch.float32, device=frame0.device)
+    _check_flow(out, h, w, "out")
+    i0, i1 = image_desc(frame0, bit_depth), image_desc(frame1, bit_depth)
+    p = params_struct(params)
+    if flow_init is None:
+        st = load().ofv_compute_flow(hd.ptr, byref(i0), byref(i1), byref(p), c_void_p(out.data_ptr()))
+    else:
+        _check_flow(flow_init, h, w, "flow_init")
+        st = load().ofv_compute_flow_ex(hd.ptr, byref(i0), byref(i1), byref(p), c_void_p(flow_init.data_ptr()),
+                                        c_void_p(out.data_ptr()))
+    check(st, hd.ptr)
+    return out
+
+
+def compute_flow_batch(frames0: Sequence[torch.Tensor], frames1: Sequence[torch.Tensor], params: Dict,
+                       flow_init: Optional[Sequence[Optional[torch.Tensor]]] = None, bit_depth: Optional[int] = None,
+                       outs: Optional[Sequence[torch.Tensor]] = None, handle: Optional[Handle] = None
+                       ) -> List[torch.Tensor]:
+    """Dense flows of n pairs (sizes may differ), each stage one launch over all pairs."""
+    n = len(frames0)
+    if n != len(frames1):
+        raise ValueError("frames0 and frames1 differ in length")
+    mw = max(f.shape[1] for f in frames0)
+    mh = max(f.shape[0] for f in frames0)
+    hd = handle or default_handle(mw, mh, n, frames0[0].device.index)
+    if handle is not None:
+        hd.bind_stream()
+    if outs is None:
+        outs = [torch.empty((2,) + tuple(f.shape), dtype=torch.float32, device=f.device) for f in frames0]
+    arr0 = (OfvImage * n)(*[image_desc(f, bit_depth) for f in frames0])
+    arr1 = (OfvImage * n)(*[image_desc(f, bit_depth) for f in frames1])
+    out_ptrs = (c_void_p * n)(*[o.data_ptr() for o in outs])
+    init_ptrs = None
+    if flow_init is not None:
+        init_ptrs = (c_void_p * n)(*[(t.data_ptr() if t is not None else None) for t in flow_init])
+    p = params_struct(params)
+    check(load().ofv_compute_flow_batch(hd.ptr, n, arr0, arr1, byref(p), init_ptrs, out_ptrs), hd.ptr)
+    return list(outs)
+
+
+def _check_flow(t: torch.Tensor, h: int, w: int, name: str) -> None:
+    if t.dtype != torch.float32 or tuple(t.shape) != (2, h, w) or not t.is_contiguous() or not t.is_cuda:
+        raise ValueError(f"{name} must be a contiguous float32 device tensor of shape (2, {h}, {w})")
+
+
+# ---------------------------------------------------------------- stage entry points (include/ofv_stages.h)
+
+def _plane_check(t: torch.Tensor, dtype=None):
+    if t.dim() != 2 or t.stride(1) != 1 or not t.is_cuda:
+        raise ValueError("planes must be 2-D device tensors with unit column stride")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"expected {dtype}, got {t.dtype}")
+
+
+def _stage_handle(t: torch.Tensor, handle: Optional[Handle]) -> Handle:
+    hd = handle or default_handle(1, 1, 1, t.device.index)
+    hd.bind_stream()
+    return hd
+
+
+def stage_normalize(frame: torch.Tensor, norm_radius: int, norm_eps: float, storage: str = "f32",
+                    bit_depth: Optional[int] = None, handle: Optional[Handle] = None) -> torch.Tensor:
+    hd = _stage_handle(frame, handle)
+    h, w = frame.shape
+    out = torch.empty((h, w), dtype=_STORE_DTYPE[storage], device=frame.device)
+    img = image_desc(frame, bit_depth)
+    check(load().ofv_stage_normalize(hd.ptr, byref(img), norm_radius, norm_eps, _lib.STORE[storage],
+                                     c_void_p(out.data_ptr()), out.stride(0)), hd.ptr)
+    return out
+
+
+def stage_reduce(plane: torch.Tensor, handle: Optional[Handle] = None) -> torch.Tensor:
+    _plane_check(plane)
+    storage = {v: k for k, v in _STORE_DTYPE.items()}[plane.dtype]
+    hd = _stage_handle(plane, handle)
+    h, w = plane.shape
+    out = torch.empty(((h + 1) // 2, (w + 1) // 2), dtype=plane.dtype, device=plane.device)
+    check(load().ofv_stage_reduce(hd.ptr, _lib.STORE[storage], c_void_p(plane.data_ptr()), w, h, plane.stride(0),
+                                  c_void_p(out.data_ptr()), out.stride(0)), hd.ptr)
+    return out
+
+
+def stage_restrict_flow(flow: torch.Tensor, handle: Optional[Handle] = None) -> torch.Tensor:
+    _, h, w = flow.shape
+    _check_flow(flow, h, w, "flow")
+    hd = _stage_handle(flow, handle)
+    out = torch.empty((2, (h + 1) // 2, (w + 1) // 2), dtype=torch.float32, device=flow.device)
+    check(load().ofv_stage_restrict_flow(hd.ptr, c_void_p(flow.data_ptr()), w, h, w, c_void_p(out.data_ptr()),
+                                         (w + 1) // 2), hd.ptr)
+    return out
+
+
+def stage_upsample(flow: torch.Tensor, h: int, w: int, handle: Optional[Handle] = None) -> torch.Tensor:
+    _, ch, cw = flow.shape
+    _check_flow(flow, ch, cw, "flow")
+    hd = _stage_handle(flow, handle)
+    out = torch.empty((2, h, w), dtype=torch.float32, device=flow.device)
+    check(load().ofv_stage_upsample(hd.ptr, c_void_p(flow.data_ptr()), cw, ch, cw, c_void_p(out.data_ptr()), w, h,
+                                    w), hd.ptr)
+    return out
+
+
+def stage_gn_iteration(p0: torch.Tensor, p1: torch.Tensor, flow_in: Optional[torch.Tensor], mode: str,
+                       kernel_radius: int, reg_rel: float = 1e-3, reg_abs: float = 1e-9,
+                       handle: Optional[Handle] = None) -> torch.Tensor:
+    """One fused Gauss-Newton iteration; mode is 'zero', 'direct' or 'upsample'."""
+    _plane_check(p0)
+    _plane_check(p1, p0.dtype)
+    if p1.stride(0) != p0.stride(0) or p1.shape != p0.shape:
+        raise ValueError("p0 and p1 must share shape and pitch")
+    storage = {v: k for k, v in _STORE_DTYPE.items()}[p0.dtype]
+    h, w = p0.shape
+    m = {"zero": _lib.FLOW_IN_ZERO, "direct": _lib.FLOW_IN_DIRECT, "upsample": _lib.FLOW_IN_UPSAMPLE}[mode]
+    hd = _stage_handle(p0, handle)
+    out = torch.empty((2, h, w), dtype=torch.float32, device=p0.device)
+    if flow_in is None:
+        fin, iw, ih = None, w, h
+    else:
+        _, ih, iw = flow_in.shape
+        _check_flow(flow_in, ih, iw, "flow_in")
+        fin = c_void_p(flow_in.data_ptr())
+    check(load().ofv_stage_gn_iteration(hd.ptr, _lib.STORE[storage], c_void_p(p0.data_ptr()),
+                                        c_void_p(p1.data_ptr()), w, h, p0.stride(0), m, fin, iw, ih, iw,
+                                        c_void_p(out.data_ptr()), w, kernel_radius, reg_rel, reg_abs), hd.ptr)
+    return out

@@ -1,0 +1,747 @@
+// C ABI of the OFV estimator: argument validation, workspace management and
+// the coarse-to-fine schedule of the pipeline (section "Live-Optical Flow
+// Velocimetry", arXiv 2509.25924, six-step list).  Every compute entry point
+// validates all arguments on the host first, then only enqueues kernels on
+// the handle's stream: no allocation, no synchronisation.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ofv.h"
+#include "ofv_stages.h"
+#include "ofv_internal.h"
+
+using namespace ofv;
+
+namespace {
+
+constexpr int64_t kPitchAlign = 64;      // elements; 256 B rows for float32 planes
+constexpr size_t kSlabAlign = 256;        // bytes
+
+int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+thread_local std::string g_create_error;
+
+}  // namespace
+
+struct ofv_ctx {
+  int device = -1;  // -1: validation-only handle (no device resources)
+  hipStream_t stream = nullptr;
+  int max_w = 0, max_h = 0, max_batch = 0;
+  // level geometry of the largest frame; planes of smaller frames reuse it
+  int lw[OFV_MAX_LEVELS] = {}, lh[OFV_MAX_LEVELS] = {};
+  int64_t lpitch[OFV_MAX_LEVELS] = {};
+  int64_t img_off[OFV_MAX_LEVELS] = {};   // element offset of level l inside a frame slab
+  size_t frame_bytes = 0;                  // one frame's pyramid slab (sized for float32)
+  size_t flow_bytes = 0;                   // one flow ping-pong buffer (2 planes of level 0)
+  size_t slot_bytes = 0;                   // one pair: 2 slabs + 2 flow buffers
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  std::string err;
+};
+
+namespace {
+
+ofv_status fail(ofv_ctx* h, ofv_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  if (h) h->err = buf; else g_create_error = buf;
+  return s;
+}
+
+bool fault_injected(const char* what) {
+  const char* e = std::getenv("OFV_FAULT_INJECT");
+  return e && std::strstr(e, what) != nullptr;
+}
+
+// Makes the handle's device current for the duration of a call.
+struct DeviceGuard {
+  int prev = -1;
+  bool changed = false;
+  explicit DeviceGuard(int dev) {
+    if (dev < 0) return;
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) changed = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    if (changed) (void)hipSetDevice(prev);
+  }
+};
+
+size_t pixel_bytes(int type) { return type == OFV_PIX_U8 ? 1 : (type == OFV_PIX_U16 ? 2 : 4); }
+size_t storage_bytes(int st) { return st == OFV_STORE_F32 ? 4 : 2; }
+
+// Byte range [lo, hi) touched by an image.
+void image_range(const ofv_image* f, uintptr_t& lo, uintptr_t& hi) {
+  lo = reinterpret_cast<uintptr_t>(f->data);
+  hi = lo + (static_cast<uint64_t>(f->height - 1) * static_cast<uint64_t>(f->pitch) + f->width) *
+                pixel_bytes(f->type);
+}
+
+bool overlap(uintptr_t a0, uintptr_t a1, uintptr_t b0, uintptr_t b1) { return a0 < b1 && b0 < a1; }
+
+ofv_status check_image(ofv_ctx* h, const ofv_image* f, const char* name) {
+  if (!f) return fail(h, OFV_ERR_INVALID_ARG, "%s is NULL", name);
+  if (!f->data) return fail(h, OFV_ERR_INVALID_ARG, "%s->data is NULL", name);
+  if (f->width < 1 || f->height < 1)
+    return fail(h, OFV_ERR_INVALID_ARG, "%s has size %dx%d (must be >= 1x1)", name, f->width, f->height);
+  if (f->pitch < f->width)
+    return fail(h, OFV_ERR_INVALID_ARG, "%s pitch %lld < width %d", name, (long long)f->pitch, f->width);
+  if (f->type == OFV_PIX_U8) {
+    if (f->bit_depth < 1 || f->bit_depth > 8)
+      return fail(h, OFV_ERR_INVALID_ARG, "%s: bit_depth %d invalid for U8 (1..8)", name, f->bit_depth);
+  } else if (f->type == OFV_PIX_U16) {
+    if (f->bit_depth < 1 || f->bit_depth > 16)
+      return fail(h, OFV_ERR_INVALID_ARG, "%s: bit_depth %d invalid for U16 (1..16)", name, f->bit_depth);
+  } else if (f->type != OFV_PIX_F32) {
+    return fail(h, OFV_ERR_INVALID_ARG, "%s: unknown pixel type %d", name, f->type);
+  }
+  return OFV_OK;
+}
+
+ofv_status check_params(ofv_ctx* h, const ofv_params* p) {
+  if (!p) return fail(h, OFV_ERR_INVALID_ARG, "params is NULL");
+  if (p->num_levels < 1 || p->num_levels > OFV_MAX_LEVELS)
+    return fail(h, OFV_ERR_INVALID_ARG, "num_levels %d outside 1..%d", p->num_levels, OFV_MAX_LEVELS);
+  if (p->kernel_radius < 1) return fail(h, OFV_ERR_INVALID_ARG, "kernel_radius %d < 1", p->kernel_radius);
+  if (p->kernel_radius > OFV_MAX_KERNEL_RADIUS)
+    return fail(h, OFV_ERR_UNSUPPORTED, "kernel_radius %d > %d", p->kernel_radius, OFV_MAX_KERNEL_RADIUS);
+  if (p->iterations < 1) return fail(h, OFV_ERR_INVALID_ARG, "iterations %d < 1", p->iterations);
+  if (p->norm_radius < 0 || p->norm_radius > OFV_MAX_NORM_RADIUS)
+    return fail(h, OFV_ERR_INVALID_ARG, "norm_radius %d outside 0..%d", p->norm_radius, OFV_MAX_NORM_RADIUS);
+  if (!std::isfinite(p->norm_eps) || p->norm_eps < 0.0f)
+    return fail(h, OFV_ERR_INVALID_ARG, "norm_eps must be finite and >= 0");
+  if (!std::isfinite(p->reg_rel) || p->reg_rel < 0.0f || !std::isfinite(p->reg_abs) || p->reg_abs < 0.0f)
+    return fail(h, OFV_ERR_INVALID_ARG, "reg_rel and reg_abs must be finite and >= 0");
+  if (p->storage < OFV_STORE_F32 || p->storage > OFV_STORE_BF16)
+    return fail(h, OFV_ERR_INVALID_ARG, "unknown storage %d", p->storage);
+  if (p->flags != 0) return fail(h, OFV_ERR_INVALID_ARG, "flags must be 0");
+  return OFV_OK;
+}
+
+ofv_status check_handle(ofv_ctx* h) {
+  if (!h) return OFV_ERR_INVALID_ARG;
+  h->err.clear();
+  return OFV_OK;
+}
+
+ofv_status device_error(ofv_ctx* h, hipError_t e, const char* where) {
+  return fail(h, OFV_ERR_DEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+// ------------------------------------------------------------------ per-pair geometry and buffers
+
+struct PairPlan {
+  const ofv_image* f[2];
+  const float* init;
+  float* out;
+  int lw[OFV_MAX_LEVELS], lh[OFV_MAX_LEVELS];
+  char* slot;
+};
+
+void level_dims(int w, int hgt, int levels, int* lw, int* lh) {
+  lw[0] = w;
+  lh[0] = hgt;
+  for (int l = 1; l < levels; ++l) {
+    lw[l] = (lw[l - 1] + 1) / 2;
+    lh[l] = (lh[l - 1] + 1) / 2;
+  }
+}
+
+char* img_plane(const ofv_ctx* h, const PairPlan& pp, int frame, int level, size_t ts) {
+  return pp.slot + frame * h->frame_bytes + static_cast<size_t>(h->img_off[level]) * ts;
+}
+
+float* flow_buf(const ofv_ctx* h, const PairPlan& pp, int which) {
+  return reinterpret_cast<float*>(pp.slot + 2 * h->frame_bytes + which * h->flow_bytes);
+}
+
+int choose_tile_h(int64_t strips_total, int64_t rows_max) {
+  // Enough workgroups to cover 256 CUs several times, without making the
+  // vertical halo (2 KR + 2 rows per tile) dominate.
+  if (const char* e = std::getenv("OFV_TILE_H")) {
+    int v = std::atoi(e);
+    if (v >= 4 && v <= 1024) return v;
+  }
+  int th = 64;
+  while (th > 16 && strips_total * ((rows_max + th - 1) / th) < 2048) th /= 2;
+  return th;
+}
+
+// Launches jobs in chunks of kMaxJobs; `fill` writes job i into args and
+// returns its block count.
+template <typename Args, typename Fill, typename Launch>
+ofv_status run_chunked(ofv_ctx* h, int njobs, Args& args, Fill fill, Launch launch, const char* what) {
+  for (int base = 0; base < njobs; base += kMaxJobs) {
+    const int cnt = std::min(kMaxJobs, njobs - base);
+    args.njobs = cnt;
+    int blocks = 0;
+    for (int i = 0; i < cnt; ++i) {
+      args.job[i].tile_start = blocks;
+      blocks += fill(base + i, args.job[i]);
+    }
+    if (blocks == 0) continue;
+    hipError_t e = launch(args, blocks);
+    if (e != hipSuccess) return device_error(h, e, what);
+  }
+  return OFV_OK;
+}
+
+ofv_status run_pipeline(ofv_ctx* h, int n, PairPlan* pp, const ofv_params* p) {
+  const int L = p->num_levels;
+  const int kr = p->kernel_radius;
+  const int it = p->iterations;
+  const int st = p->storage;
+  const size_t ts = storage_bytes(st);
+  hipStream_t s = h->stream;
+
+  // Step 1: normalisation of both frames of every pair -> level 0.
+  {
+    NormArgs na{};
+    na.nr = p->norm_radius;
+    na.eps = p->norm_eps;
+    na.storage = st;
+    auto fill = [&](int i, NormJob& J) {
+      const PairPlan& q = pp[i / 2];
+      const ofv_image* f = q.f[i % 2];
+      J.in = f->data;
+      J.in_pitch = f->pitch;
+      J.type = f->type;
+      J.bits = f->bit_depth;
+      J.w = f->width;
+      J.h = f->height;
+      J.out = img_plane(h, q, i % 2, 0, ts);
+      J.out_pitch = h->lpitch[0];
+      return ((J.w + 63) / 64) * ((J.h + 15) / 16);
+    };
+    ofv_status r = run_chunked(h, 2 * n, na, fill,
+                               [&](const NormArgs& a, int b) { return launch_normalize(a, b, s); }, "normalize");
+    if (r != OFV_OK) return r;
+  }
+  // Step 2: pyramid levels 1..L-1 of both frames.
+  for (int l = 1; l < L; ++l) {
+    ReduceArgs ra{};
+    ra.storage = st;
+    ra.scale = 1.0f;
+    auto fill = [&](int i, ReduceJob& J) {
+      const PairPlan& q = pp[i / 2];
+      J.in = img_plane(h, q, i % 2, l - 1, ts);
+      J.out = img_plane(h, q, i % 2, l, ts);
+      J.in_pitch = h->lpitch[l - 1];
+      J.out_pitch = h->lpitch[l];
+      J.w = q.lw[l - 1];
+      J.h = q.lh[l - 1];
+      return ((q.lw[l] + 63) / 64) * ((q.lh[l] + 3) / 4);
+    };
+    ofv_status r = run_chunked(h, 2 * n, ra, fill,
+                               [&](const ReduceArgs& a, int b) { return launch_reduce(a, b, s); }, "reduce");
+    if (r != OFV_OK) return r;
+  }
+  // Initial flow: restricted to the coarsest level by REDUCE / 2 (pairs that have one).
+  std::vector<int> cur(n, -1);  // flow buffer holding the current field, -1 = zero field
+  std::vector<int> with_init;
+  for (int j = 0; j < n; ++j)
+    if (pp[j].init) with_init.push_back(j);
+  if (!with_init.empty()) {
+    const int ni = static_cast<int>(with_init.size());
+    if (L == 1) {
+      // copy, so that flow_init may alias flow_out
+      for (int j : with_init) {
+        const int w = pp[j].lw[0], hh = pp[j].lh[0];
+        float* dst = flow_buf(h, pp[j], 1);
+        for (int c = 0; c < 2; ++c) {
+          hipError_t e = hipMemcpy2DAsync(dst + c * h->lpitch[0] * h->lh[0], h->lpitch[0] * sizeof(float),
+                                          pp[j].init + static_cast<int64_t>(c) * w * hh, w * sizeof(float),
+                                          w * sizeof(float), hh, hipMemcpyDeviceToDevice, s);
+          if (e != hipSuccess) return device_error(h, e, "flow_init copy");
+        }
+        cur[j] = 1;
+      }
+    } else {
+      for (int l = 1; l < L; ++l) {
+        ReduceArgs ra{};
+        ra.storage = ST_F32;
+        ra.scale = 0.5f;
+        auto fill = [&](int i, ReduceJob& J) {
+          const PairPlan& q = pp[with_init[i / 2]];
+          const int c = i % 2;
+          if (l == 1) {
+            J.in = q.init + static_cast<int64_t>(c) * q.lw[0] * q.lh[0];
+            J.in_pitch = q.lw[0];
+          } else {
+            J.in = flow_buf(h, q, (l - 1) & 1) + c * h->lpitch[l - 1] * h->lh[l - 1];
+            J.in_pitch = h->lpitch[l - 1];
+          }
+          J.out = flow_buf(h, q, l & 1) + c * h->lpitch[l] * h->lh[l];
+          J.out_pitch = h->lpitch[l];
+          J.w = q.lw[l - 1];
+          J.h = q.lh[l - 1];
+          return ((q.lw[l] + 63) / 64) * ((q.lh[l] + 3) / 4);
+        };
+        ofv_status r = run_chunked(h, 2 * ni, ra, fill,
+                                   [&](const ReduceArgs& a, int b) { return launch_reduce(a, b, s); },
+                                   "restrict flow_init");
+        if (r != OFV_OK) return r;
+      }
+      for (int j : with_init) cur[j] = (L - 1) & 1;
+    }
+  }
+  // Steps 3-6: Gauss-Newton iterations, coarse to fine; the up-sampling of
+  // step 4 is fused into the first iteration of every finer level and the
+  // last level-0 iteration writes the caller's buffer.
+  const int tx = gn_tile_w(kr);
+  for (int l = L - 1; l >= 0; --l) {
+    int64_t strips = 0, rows_max = 0;
+    for (int j = 0; j < n; ++j) {
+      strips += (pp[j].lw[l] + tx - 1) / tx;
+      rows_max = std::max<int64_t>(rows_max, pp[j].lh[l]);
+    }
+    const int tile_h = choose_tile_h(strips, rows_max);
+    for (int k = 0; k < it; ++k) {
+      const bool final_iter = (l == 0 && k == it - 1);
+      GnArgs ga{};
+      ga.tile_h = tile_h;
+      ga.reg_rel = p->reg_rel;
+      ga.reg_abs = p->reg_abs;
+      std::vector<int> next(n);
+      // the input-flow mode is a compile-time property of the kernel: group pairs by it
+      auto mode_of = [&](int j) {
+        if (k == 0 && l < L - 1) return static_cast<int>(FLOW_UPSAMPLE);
+        return static_cast<int>(cur[j] < 0 ? FLOW_ZERO : FLOW_DIRECT);
+      };
+      for (int mode = FLOW_ZERO; mode <= FLOW_UPSAMPLE; ++mode) {
+        std::vector<int> group;
+        for (int j = 0; j < n; ++j)
+          if (mode_of(j) == mode) group.push_back(j);
+        if (group.empty()) continue;
+        auto fill = [&](int gi, GnJob& J) {
+          const int j = group[gi];
+          const PairPlan& q = pp[j];
+          J.p0 = img_plane(h, q, 0, l, ts);
+          J.p1 = img_plane(h, q, 1, l, ts);
+          J.img_pitch = h->lpitch[l];
+          J.w = q.lw[l];
+          J.h = q.lh[l];
+          J.cw = l + 1 < L ? q.lw[l + 1] : 0;
+          J.ch = l + 1 < L ? q.lh[l + 1] : 0;
+          J.mode = mode;
+          if (mode == FLOW_UPSAMPLE) {
+            const float* src = flow_buf(h, q, cur[j]);
+            J.in_u = src;
+            J.in_v = src + h->lpitch[l + 1] * h->lh[l + 1];
+            J.in_pitch = h->lpitch[l + 1];
+          } else if (mode == FLOW_ZERO) {
+            J.in_u = J.in_v = nullptr;
+            J.in_pitch = 0;
+          } else {
+            const float* src = flow_buf(h, q, cur[j]);
+            J.in_u = src;
+            J.in_v = src + h->lpitch[l] * h->lh[l];
+            J.in_pitch = h->lpitch[l];
+          }
+          if (final_iter) {
+            J.out_u = q.out;
+            J.out_v = q.out + static_cast<int64_t>(q.lw[0]) * q.lh[0];
+            J.out_pitch = q.lw[0];
+            next[j] = -2;
+          } else {
+            const int nb = cur[j] == 0 ? 1 : 0;
+            float* dst = flow_buf(h, q, nb);
+            J.out_u = dst;
+            J.out_v = dst + h->lpitch[l] * h->lh[l];
+            J.out_pitch = h->lpitch[l];
+            next[j] = nb;
+          }
+          return static_cast<int>(((q.lw[l] + tx - 1) / tx) * ((q.lh[l] + tile_h - 1) / tile_h));
+        };
+        ofv_status r = run_chunked(h, static_cast<int>(group.size()), ga, fill,
+                                   [&](const GnArgs& a, int b) { return launch_gn(a, kr, st, mode, b, s); },
+                                   "gauss-newton iteration");
+        if (r != OFV_OK) return r;
+      }
+      cur = next;
+    }
+  }
+  return OFV_OK;
+}
+
+ofv_status validate_pair(ofv_ctx* h, const ofv_image* f0, const ofv_image* f1, const float* init,
+                         const float* out, int idx) {
+  char n0[32], n1[32];
+  snprintf(n0, sizeof n0, "frame0[%d]", idx);
+  snprintf(n1, sizeof n1, "frame1[%d]", idx);
+  ofv_status r = check_image(h, f0, n0);
+  if (r != OFV_OK) return r;
+  r = check_image(h, f1, n1);
+  if (r != OFV_OK) return r;
+  if (f0->width != f1->width || f0->height != f1->height)
+    return fail(h, OFV_ERR_INVALID_ARG, "pair %d: frame sizes differ (%dx%d vs %dx%d)", idx, f0->width,
+                f0->height, f1->width, f1->height);
+  if (!out) return fail(h, OFV_ERR_INVALID_ARG, "flow_out[%d] is NULL", idx);
+  if (f0->width > h->max_w || f0->height > h->max_h)
+    return fail(h, OFV_ERR_CAPACITY, "pair %d: %dx%d exceeds the handle's %dx%d", idx, f0->width, f0->height,
+                h->max_w, h->max_h);
+  const uintptr_t o0 = reinterpret_cast<uintptr_t>(out);
+  const uintptr_t o1 = o0 + 2ull * f0->width * f0->height * sizeof(float);
+  uintptr_t a0, a1;
+  image_range(f0, a0, a1);
+  if (overlap(o0, o1, a0, a1)) return fail(h, OFV_ERR_INVALID_ARG, "flow_out[%d] overlaps frame0", idx);
+  image_range(f1, a0, a1);
+  if (overlap(o0, o1, a0, a1)) return fail(h, OFV_ERR_INVALID_ARG, "flow_out[%d] overlaps frame1", idx);
+  if (init && init != out) {
+    const uintptr_t i0 = reinterpret_cast<uintptr_t>(init);
+    if (overlap(o0, o1, i0, i0 + (o1 - o0)))
+      return fail(h, OFV_ERR_INVALID_ARG, "flow_init[%d] partially overlaps flow_out", idx);
+  }
+  return OFV_OK;
+}
+
+ofv_status compute_common(ofv_ctx* h, int n, const ofv_image* f0, const ofv_image* f1, const ofv_params* p,
+                          const float* const* init, float* const* out) {
+  if (check_handle(h) != OFV_OK) return OFV_ERR_INVALID_ARG;
+  if (n < 1) return fail(h, OFV_ERR_INVALID_ARG, "batch size %d < 1", n);
+  if (!f0 || !f1 || !out) return fail(h, OFV_ERR_INVALID_ARG, "frame or flow_out array is NULL");
+  ofv_status r = check_params(h, p);
+  if (r != OFV_OK) return r;
+  if (n > h->max_batch) return fail(h, OFV_ERR_CAPACITY, "batch %d exceeds max_batch %d", n, h->max_batch);
+  for (int j = 0; j < n; ++j) {
+    r = validate_pair(h, &f0[j], &f1[j], init ? init[j] : nullptr, out[j], j);
+    if (r != OFV_OK) return r;
+  }
+  for (int j = 0; j < n; ++j) {
+    const uintptr_t a0 = reinterpret_cast<uintptr_t>(out[j]);
+    const uintptr_t a1 = a0 + 2ull * f0[j].width * f0[j].height * sizeof(float);
+    for (int i = 0; i < n; ++i) {
+      if (i == j) continue;
+      const uintptr_t b0 = reinterpret_cast<uintptr_t>(out[i]);
+      const uintptr_t b1 = b0 + 2ull * f0[i].width * f0[i].height * sizeof(float);
+      if (overlap(a0, a1, b0, b1)) return fail(h, OFV_ERR_INVALID_ARG, "flow_out[%d] overlaps flow_out[%d]", j, i);
+      uintptr_t c0, c1;
+      image_range(&f0[i], c0, c1);
+      if (overlap(a0, a1, c0, c1)) return fail(h, OFV_ERR_INVALID_ARG, "flow_out[%d] overlaps frame0[%d]", j, i);
+      image_range(&f1[i], c0, c1);
+      if (overlap(a0, a1, c0, c1)) return fail(h, OFV_ERR_INVALID_ARG, "flow_out[%d] overlaps frame1[%d]", j, i);
+    }
+  }
+  if (fault_injected("launch")) return fail(h, OFV_ERR_DEVICE, "injected launch failure");
+  if (h->device < 0) return fail(h, OFV_ERR_UNSUPPORTED, "validation-only handle (created with device -1)");
+  DeviceGuard g(h->device);
+  std::vector<PairPlan> pp(n);
+  for (int j = 0; j < n; ++j) {
+    pp[j].f[0] = &f0[j];
+    pp[j].f[1] = &f1[j];
+    pp[j].init = init ? init[j] : nullptr;
+    pp[j].out = out[j];
+    pp[j].slot = h->ws + static_cast<size_t>(j) * h->slot_bytes;
+    level_dims(f0[j].width, f0[j].height, p->num_levels, pp[j].lw, pp[j].lh);
+  }
+  return run_pipeline(h, n, pp.data(), p);
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+
+extern "C" {
+
+void ofv_default_params(ofv_params* p) {
+  if (!p) return;
+  p->num_levels = 3;
+  p->kernel_radius = 4;
+  p->iterations = 3;
+  p->norm_radius = 1;
+  p->norm_eps = 1e-4f;
+  p->reg_rel = 1e-3f;
+  p->reg_abs = 1e-9f;
+  p->storage = OFV_STORE_F32;
+  p->flags = 0;
+}
+
+const char* ofv_status_string(ofv_status s) {
+  switch (s) {
+    case OFV_OK: return "ok";
+    case OFV_ERR_INVALID_ARG: return "invalid argument";
+    case OFV_ERR_UNSUPPORTED: return "unsupported";
+    case OFV_ERR_CAPACITY: return "exceeds workspace capacity";
+    case OFV_ERR_OUT_OF_MEMORY: return "out of device memory";
+    case OFV_ERR_DEVICE: return "device error";
+  }
+  return "unknown status";
+}
+
+const char* ofv_last_error(ofv_handle h) { return h ? h->err.c_str() : g_create_error.c_str(); }
+
+ofv_status ofv_create(ofv_handle* out, int device, int max_width, int max_height, int max_batch, void* stream) {
+  g_create_error.clear();
+  if (!out) return fail(nullptr, OFV_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (max_width < 1 || max_height < 1 || max_batch < 1)
+    return fail(nullptr, OFV_ERR_INVALID_ARG, "max sizes must be >= 1 (got %dx%d, batch %d)", max_width, max_height,
+                max_batch);
+  if (device < -1) return fail(nullptr, OFV_ERR_INVALID_ARG, "device %d < -1", device);
+  ofv_ctx* h = new (std::nothrow) ofv_ctx();
+  if (!h) return fail(nullptr, OFV_ERR_OUT_OF_MEMORY, "host allocation failed");
+  h->device = device;
+  h->stream = static_cast<hipStream_t>(stream);
+  h->max_w = max_width;
+  h->max_h = max_height;
+  h->max_batch = max_batch;
+  level_dims(max_width, max_height, OFV_MAX_LEVELS, h->lw, h->lh);
+  int64_t off = 0;
+  for (int l = 0; l < OFV_MAX_LEVELS; ++l) {
+    h->lpitch[l] = round_up(h->lw[l], kPitchAlign);
+    h->img_off[l] = off;
+    off += h->lpitch[l] * h->lh[l];
+  }
+  h->frame_bytes = round_up(off * 4, kSlabAlign);
+  h->flow_bytes = round_up(2 * h->lpitch[0] * h->lh[0] * 4, kSlabAlign);
+  h->slot_bytes = 2 * h->frame_bytes + 2 * h->flow_bytes;
+  h->ws_bytes = h->slot_bytes * static_cast<size_t>(max_batch);
+  if (device >= 0) {
+    if (fault_injected("alloc")) {
+      delete h;
+      return fail(nullptr, OFV_ERR_OUT_OF_MEMORY, "injected allocation failure");
+    }
+    DeviceGuard g(device);
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess || cur != device) {
+      delete h;
+      return fail(nullptr, OFV_ERR_DEVICE, "cannot select device %d: %s", device,
+                  hipGetErrorString(e != hipSuccess ? e : hipErrorInvalidDevice));
+    }
+    e = hipMalloc(reinterpret_cast<void**>(&h->ws), h->ws_bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      const size_t h_bytes_tmp = h->ws_bytes;
+      delete h;
+      return fail(nullptr, OFV_ERR_OUT_OF_MEMORY, "hipMalloc(%zu bytes): %s", h_bytes_tmp, hipGetErrorString(e));
+    }
+  }
+  *out = h;
+  return OFV_OK;
+}
+
+ofv_status ofv_set_stream(ofv_handle h, void* stream) {
+  if (check_handle(h) != OFV_OK) return OFV_ERR_INVALID_ARG;
+  h->stream = static_cast<hipStream_t>(stream);
+  return OFV_OK;
+}
+
+ofv_status ofv_workspace_bytes(ofv_handle h, size_t* bytes) {
+  if (check_handle(h) != OFV_OK) return OFV_ERR_INVALID_ARG;
+  if (!bytes) return fail(h, OFV_ERR_INVALID_ARG, "bytes is NULL");
+  *bytes = h->ws_bytes;
+  return OFV_OK;
+}
+
+ofv_status ofv_compute_flow(ofv_handle h, const ofv_image* frame0, const ofv_image* frame1,
+                            const ofv_params* params, float* flow_out) {
+  return compute_common(h, 1, frame0, frame1, params, nullptr, &flow_out);
+}
+
+ofv_status ofv_compute_flow_ex(ofv_handle h, const ofv_image* frame0, const ofv_image* frame1,
+                               const ofv_params* params, const float* flow_init, float* flow_out) {
+  return compute_common(h, 1, frame0, frame1, params, &flow_init, &flow_out);
+}
+
+ofv_status ofv_compute_flow_batch(ofv_handle h, int n, const ofv_image* frame0, const ofv_image* frame1,
+                                  const ofv_params* params, const float* const* flow_init,
+                                  float* const* flow_out) {
+  return compute_common(h, n, frame0, frame1, params, flow_init, flow_out);
+}
+
+ofv_status ofv_destroy(ofv_handle h) {
+  if (!h) return OFV_OK;
+  ofv_status r = OFV_OK;
+  if (h->device >= 0) {
+    DeviceGuard g(h->device);
+    if (hipStreamSynchronize(h->stream) != hipSuccess) r = OFV_ERR_DEVICE;
+    if (h->ws && hipFree(h->ws) != hipSuccess) r = OFV_ERR_DEVICE;
+  }
+  delete h;
+  return r;
+}
+
+// ------------------------------------------------------------------ stage entry points
+
+static ofv_status stage_prologue(ofv_ctx* h) {
+  if (check_handle(h) != OFV_OK) return OFV_ERR_INVALID_ARG;
+  return OFV_OK;
+}
+
+static ofv_status stage_device(ofv_ctx* h) {
+  if (fault_injected("launch")) return fail(h, OFV_ERR_DEVICE, "injected launch failure");
+  if (h->device < 0) return fail(h, OFV_ERR_UNSUPPORTED, "validation-only handle (created with device -1)");
+  return OFV_OK;
+}
+
+ofv_status ofv_stage_normalize(ofv_handle h, const ofv_image* frame, int norm_radius, float norm_eps, int storage,
+                               void* out, int64_t out_pitch) {
+  if (stage_prologue(h) != OFV_OK) return OFV_ERR_INVALID_ARG;
+  ofv_status r = check_image(h, frame, "frame");
+  if (r != OFV_OK) return r;
+  if (norm_radius < 0 || norm_radius > OFV_MAX_NORM_RADIUS)
+    return fail(h, OFV_ERR_INVALID_ARG, "norm_radius %d outside 0..%d", norm_radius, OFV_MAX_NORM_RADIUS);
+  if (!std::isfinite(norm_eps) || norm_eps < 0.0f) return fail(h, OFV_ERR_INVALID_ARG, "norm_eps invalid");
+  if (storage < 0 || storage > 2) return fail(h, OFV_ERR_INVALID_ARG, "unknown storage %d", storage);
+  if (!out) return fail(h, OFV_ERR_INVALID_ARG, "out is NULL");
+  if (out_pitch < frame->width) return fail(h, OFV_ERR_INVALID_ARG, "out_pitch < width");
+  if ((r = stage_device(h)) != OFV_OK) return r;
+  DeviceGuard g(h->device);
+  NormArgs na{};
+  na.njobs = 1;
+  na.nr = norm_radius;
+  na.eps = norm_eps;
+  na.storage = storage;
+  NormJob& J = na.job[0];
+  J.in = frame->data;
+  J.in_pitch = frame->pitch;
+  J.type = frame->type;
+  J.bits = frame->bit_depth;
+  J.w = frame->width;
+  J.h = frame->height;
+  J.out = out;
+  J.out_pitch = out_pitch;
+  J.tile_start = 0;
+  hipError_t e = launch_normalize(na, ((J.w + 63) / 64) * ((J.h + 15) / 16), h->stream);
+  return e == hipSuccess ? OFV_OK : device_error(h, e, "normalize");
+}
+
+static ofv_status reduce_common(ofv_ctx* h, int storage, const void* in, int w, int hgt, int64_t in_pitch, void* out,
+                                int64_t out_pitch, float scale, int planes, int64_t in_plane, int64_t out_plane) {
+  if (!in || !out) return fail(h, OFV_ERR_INVALID_ARG, "in or out is NULL");
+  if (w < 1 || hgt < 1) return fail(h, OFV_ERR_INVALID_ARG, "size %dx%d invalid", w, hgt);
+  if (in_pitch < w || out_pitch < (w + 1) / 2) return fail(h, OFV_ERR_INVALID_ARG, "pitch too small");
+  ofv_status r = stage_device(h);
+  if (r != OFV_OK) return r;
+  DeviceGuard g(h->device);
+  const size_t es = storage_bytes(storage);
+  ReduceArgs ra{};
+  ra.njobs = planes;
+  ra.storage = storage;
+  ra.scale = scale;
+  int blocks = 0;
+  for (int c = 0; c < planes; ++c) {
+    ReduceJob& J = ra.job[c];
+    J.in = static_cast<const char*>(in) + c * in_plane * es;
+    J.out = static_cast<char*>(out) + c * out_plane * es;
+    J.in_pitch = in_pitch;
+    J.out_pitch = out_pitch;
+    J.w = w;
+    J.h = hgt;
+    J.tile_start = blocks;
+    blocks += (((w + 1) / 2 + 63) / 64) * (((hgt + 1) / 2 + 3) / 4);
+  }
+  hipError_t e = launch_reduce(ra, blocks, h->stream);
+  return e == hipSuccess ? OFV_OK : device_error(h, e, "reduce");
+}
+
+ofv_status ofv_stage_reduce(ofv_handle h, int storage, const void* in, int width, int height, int64_t in_pitch,
+                            void* out, int64_t out_pitch) {
+  if (stage_prologue(h) != OFV_OK) return OFV_ERR_INVALID_ARG;
+  if (storage < 0 || storage > 2) return fail(h, OFV_ERR_INVALID_ARG, "unknown storage %d", storage);
+  return reduce_common(h, storage, in, width, height, in_pitch, out, out_pitch, 1.0f, 1, 0, 0);
+}
+
+ofv_status ofv_stage_restrict_flow(ofv_handle h, const float* in, int width, int height, int64_t in_pitch,
+                                   float* out, int64_t out_pitch) {
+  if (stage_prologue(h) != OFV_OK) return OFV_ERR_INVALID_ARG;
+  return reduce_common(h, ST_F32, in, width, height, in_pitch, out, out_pitch, 0.5f, 2,
+                       static_cast<int64_t>(height) * in_pitch, static_cast<int64_t>((height + 1) / 2) * out_pitch);
+}
+
+ofv_status ofv_stage_upsample(ofv_handle h, const float* in, int in_width, int in_height, int64_t in_pitch,
+                              float* out, int width, int height, int64_t out_pitch) {
+  if (stage_prologue(h) != OFV_OK) return OFV_ERR_INVALID_ARG;
+  if (!in || !out) return fail(h, OFV_ERR_INVALID_ARG, "in or out is NULL");
+  if (in_width < 1 || in_height < 1 || width < 1 || height < 1)
+    return fail(h, OFV_ERR_INVALID_ARG, "sizes must be >= 1");
+  if (in_pitch < in_width || out_pitch < width) return fail(h, OFV_ERR_INVALID_ARG, "pitch too small");
+  ofv_status r = stage_device(h);
+  if (r != OFV_OK) return r;
+  DeviceGuard g(h->device);
+  UpsampleArgs a{};
+  a.in_u = in;
+  a.in_v = in + static_cast<int64_t>(in_height) * in_pitch;
+  a.out_u = out;
+  a.out_v = out + static_cast<int64_t>(height) * out_pitch;
+  a.in_pitch = in_pitch;
+  a.out_pitch = out_pitch;
+  a.cw = in_width;
+  a.ch = in_height;
+  a.w = width;
+  a.h = height;
+  hipError_t e = launch_upsample(a, h->stream);
+  return e == hipSuccess ? OFV_OK : device_error(h, e, "upsample");
+}
+
+ofv_status ofv_stage_gn_iteration(ofv_handle h, int storage, const void* p0, const void* p1, int width, int height,
+                                  int64_t img_pitch, int mode, const float* flow_in, int in_width, int in_height,
+                                  int64_t in_pitch, float* flow_out, int64_t out_pitch, int kernel_radius,
+                                  float reg_rel, float reg_abs) {
+  if (stage_prologue(h) != OFV_OK) return OFV_ERR_INVALID_ARG;
+  if (storage < 0 || storage > 2) return fail(h, OFV_ERR_INVALID_ARG, "unknown storage %d", storage);
+  if (!p0 || !p1 || !flow_out) return fail(h, OFV_ERR_INVALID_ARG, "p0, p1 or flow_out is NULL");
+  if (width < 1 || height < 1) return fail(h, OFV_ERR_INVALID_ARG, "size %dx%d invalid", width, height);
+  if (img_pitch < width || out_pitch < width) return fail(h, OFV_ERR_INVALID_ARG, "pitch too small");
+  if (kernel_radius < 1) return fail(h, OFV_ERR_INVALID_ARG, "kernel_radius < 1");
+  if (kernel_radius > OFV_MAX_KERNEL_RADIUS) return fail(h, OFV_ERR_UNSUPPORTED, "kernel_radius too large");
+  if (!std::isfinite(reg_rel) || reg_rel < 0 || !std::isfinite(reg_abs) || reg_abs < 0)
+    return fail(h, OFV_ERR_INVALID_ARG, "reg_rel/reg_abs invalid");
+  if (mode < OFV_FLOW_IN_ZERO || mode > OFV_FLOW_IN_UPSAMPLE) return fail(h, OFV_ERR_INVALID_ARG, "unknown mode");
+  int iw = width, ih = height;
+  if (mode != OFV_FLOW_IN_ZERO) {
+    if (!flow_in) return fail(h, OFV_ERR_INVALID_ARG, "flow_in is NULL");
+    if (mode == OFV_FLOW_IN_UPSAMPLE) {
+      if (in_width < 1 || in_height < 1) return fail(h, OFV_ERR_INVALID_ARG, "coarse size invalid");
+      iw = in_width;
+      ih = in_height;
+    }
+    if (in_pitch < iw) return fail(h, OFV_ERR_INVALID_ARG, "in_pitch too small");
+    const uintptr_t a0 = reinterpret_cast<uintptr_t>(flow_in);
+    const uintptr_t a1 = a0 + (2ull * ih * in_pitch) * sizeof(float);
+    const uintptr_t b0 = reinterpret_cast<uintptr_t>(flow_out);
+    const uintptr_t b1 = b0 + (2ull * height * out_pitch) * sizeof(float);
+    if (overlap(a0, a1, b0, b1)) return fail(h, OFV_ERR_INVALID_ARG, "flow_out overlaps flow_in");
+  }
+  ofv_status r = stage_device(h);
+  if (r != OFV_OK) return r;
+  DeviceGuard g(h->device);
+  GnArgs ga{};
+  ga.njobs = 1;
+  ga.reg_rel = reg_rel;
+  ga.reg_abs = reg_abs;
+  const int tx = gn_tile_w(kernel_radius);
+  ga.tile_h = choose_tile_h((width + tx - 1) / tx, height);
+  GnJob& J = ga.job[0];
+  J.p0 = p0;
+  J.p1 = p1;
+  J.img_pitch = img_pitch;
+  J.w = width;
+  J.h = height;
+  J.cw = iw;
+  J.ch = ih;
+  J.mode = mode;
+  J.in_u = flow_in;
+  J.in_v = flow_in ? flow_in + static_cast<int64_t>(ih) * in_pitch : nullptr;
+  J.in_pitch = in_pitch;
+  J.out_u = flow_out;
+  J.out_v = flow_out + static_cast<int64_t>(height) * out_pitch;
+  J.out_pitch = out_pitch;
+  J.tile_start = 0;
+  const int blocks = ((width + tx - 1) / tx) * ((height + ga.tile_h - 1) / ga.tile_h);
+  hipError_t e = launch_gn(ga, kernel_radius, storage, mode, blocks, h->stream);
+  return e == hipSuccess ? OFV_OK : device_error(h, e, "gauss-newton iteration");
+}
+
+}  // extern "C"

@@ -1,0 +1,10 @@
+// Fused Gauss-Newton iteration kernels: bf16_t image storage, input flow mode FLOW_UPSAMPLE.
+#include "ofv_gn_impl.h"
+
+namespace ofv {
+
+hipError_t launch_gn_bf16_upsample(const GnArgs& a, int kr, int nblocks, hipStream_t s) {
+  return launch_gn_typed<FLOW_UPSAMPLE, bf16_t>(a, kr, nblocks, s);
+}
+
+}  // namespace ofv

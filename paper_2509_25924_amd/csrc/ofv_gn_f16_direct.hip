@@ -1,0 +1,10 @@
+// Fused Gauss-Newton iteration kernels: _Float16 image storage, input flow mode FLOW_DIRECT.
+#include "ofv_gn_impl.h"
+
+namespace ofv {
+
+hipError_t launch_gn_f16_direct(const GnArgs& a, int kr, int nblocks, hipStream_t s) {
+  return launch_gn_typed<FLOW_DIRECT, _Float16>(a, kr, nblocks, s);
+}
+
+}  // namespace ofv

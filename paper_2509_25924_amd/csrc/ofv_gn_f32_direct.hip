@@ -1,0 +1,10 @@
+// Fused Gauss-Newton iteration kernels: float image storage, input flow mode FLOW_DIRECT.
+#include "ofv_gn_impl.h"
+
+namespace ofv {
+
+hipError_t launch_gn_f32_direct(const GnArgs& a, int kr, int nblocks, hipStream_t s) {
+  return launch_gn_typed<FLOW_DIRECT, float>(a, kr, nblocks, s);
+}
+
+}  // namespace ofv

@@ -1,0 +1,90 @@
+// Internal interface between the C ABI layer and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ofv {
+
+enum Storage { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2 };
+enum FlowIn { FLOW_ZERO = 0, FLOW_DIRECT = 1, FLOW_UPSAMPLE = 2 };
+
+// Pairs (or planes) handled by one launch; larger batches are split.
+constexpr int kMaxJobs = 16;
+constexpr int kGnThreads = 256;
+constexpr int kMaxKR = 12;
+constexpr int kMaxNR = 16;
+
+// ---------------------------------------------------------------- normalisation
+struct NormJob {
+  const void* in;      // frame pixel (0,0)
+  void* out;           // output plane (storage type)
+  int64_t in_pitch;    // elements
+  int64_t out_pitch;   // elements
+  int w, h;
+  int type;            // 0 u8, 1 u16, 2 f32
+  int bits;            // significant bits of integer frames
+  int tile_start;      // first block of this job
+  int pad_;
+};
+struct NormArgs {
+  int njobs;
+  int nr;
+  float eps;
+  int storage;
+  NormJob job[kMaxJobs];
+};
+
+// ---------------------------------------------------------------- REDUCE
+struct ReduceJob {
+  const void* in;
+  void* out;
+  int64_t in_pitch, out_pitch;
+  int w, h;            // input size
+  int tile_start;
+  int pad_;
+};
+struct ReduceArgs {
+  int njobs;
+  int storage;         // element type of in/out (flows use ST_F32)
+  float scale;         // 1 for images, 0.5 for the initial-flow restriction
+  int pad_;
+  ReduceJob job[kMaxJobs];
+};
+
+// ---------------------------------------------------------------- up-sampling (stage entry point)
+struct UpsampleArgs {
+  const float* in_u; const float* in_v;
+  float* out_u; float* out_v;
+  int64_t in_pitch, out_pitch;
+  int cw, ch, w, h;
+};
+
+// ---------------------------------------------------------------- Gauss-Newton iteration
+struct GnJob {
+  const void* p0; const void* p1;     // image planes of this level
+  const float* in_u; const float* in_v;
+  float* out_u; float* out_v;
+  int64_t img_pitch, in_pitch, out_pitch;
+  int w, h;            // level size
+  int cw, ch;          // coarse size (FLOW_UPSAMPLE)
+  int mode;            // FlowIn (equal for all jobs of a launch)
+  int tile_start;
+};
+struct GnArgs {
+  int njobs;
+  int tile_h;          // output rows per workgroup
+  float reg_rel, reg_abs;
+  GnJob job[kMaxJobs];
+};
+
+// Columns of output produced by one 256-lane strip for window radius kr.
+inline int gn_tile_w(int kr) { return kGnThreads - 2 * kr - 2; }
+
+hipError_t launch_normalize(const NormArgs& a, int nblocks, hipStream_t s);
+hipError_t launch_reduce(const ReduceArgs& a, int nblocks, hipStream_t s);
+hipError_t launch_upsample(const UpsampleArgs& a, hipStream_t s);
+// All jobs of one launch share the input-flow mode (a compile-time parameter of the kernel).
+hipError_t launch_gn(const GnArgs& a, int kr, int storage, int mode, int nblocks, hipStream_t s);
+
+}  // namespace ofv

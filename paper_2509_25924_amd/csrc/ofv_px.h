@@ -1,0 +1,80 @@
+// Storage element types of the image planes and their float32 conversions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ofv {
+
+struct bf16_t {
+  uint16_t bits;
+};
+
+template <typename T>
+struct Px;
+
+template <>
+struct Px<float> {
+  static __device__ __forceinline__ float ld(const float* p) { return *p; }
+  static __device__ __forceinline__ void st(float* p, float v) { *p = v; }
+};
+
+template <>
+struct Px<_Float16> {
+  static __device__ __forceinline__ float ld(const _Float16* p) { return static_cast<float>(*p); }
+  static __device__ __forceinline__ void st(_Float16* p, float v) { *p = static_cast<_Float16>(v); }
+};
+
+// bfloat16 = the upper half of an IEEE binary32; conversion from float rounds
+// to nearest, ties to even, and keeps NaNs quiet.
+template <>
+struct Px<bf16_t> {
+  static __device__ __forceinline__ float ld(const bf16_t* p) {
+    return __uint_as_float(static_cast<uint32_t>(p->bits) << 16);
+  }
+  static __device__ __forceinline__ void st(bf16_t* p, float v) {
+    uint32_t u = __float_as_uint(v);
+    if ((u & 0x7f800000u) == 0x7f800000u) {
+      p->bits = static_cast<uint16_t>((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+      return;
+    }
+    u += 0x7fffu + ((u >> 16) & 1u);
+    p->bits = static_cast<uint16_t>(u >> 16);
+  }
+};
+
+// Bilinear sample of a plane at (x, y); coordinates are clamped to
+// [0, w-1] x [0, h-1] first, so every address stays inside the plane (NaN
+// coordinates clamp to 0).
+template <typename T>
+__device__ __forceinline__ float bilinear(const T* __restrict__ p, int64_t pitch, int w, int h, float x,
+                                          float y) {
+  x = fminf(fmaxf(x, 0.0f), static_cast<float>(w - 1));
+  y = fminf(fmaxf(y, 0.0f), static_cast<float>(h - 1));
+  const float xf = floorf(x);
+  const float yf = floorf(y);
+  const float ax = x - xf;
+  const float ay = y - yf;
+  const int ix = static_cast<int>(xf);
+  const int iy = static_cast<int>(yf);
+  const int dx = ix < w - 1 ? 1 : 0;
+  const int64_t dy = iy < h - 1 ? pitch : 0;
+  const T* r0 = p + static_cast<int64_t>(iy) * pitch + ix;
+  const float p00 = Px<T>::ld(r0);
+  const float p01 = Px<T>::ld(r0 + dx);
+  const float p10 = Px<T>::ld(r0 + dy);
+  const float p11 = Px<T>::ld(r0 + dy + dx);
+  const float top = p00 + ax * (p01 - p00);
+  const float bot = p10 + ax * (p11 - p10);
+  return top + ay * (bot - top);
+}
+
+// Workgroup -> job lookup: jobs are laid out consecutively in the 1-D grid.
+template <typename Args>
+__device__ __forceinline__ int find_job(const Args& a, int block) {
+  int j = 0;
+  while (j + 1 < a.njobs && block >= a.job[j + 1].tile_start) ++j;
+  return j;
+}
+
+}  // namespace ofv

@@ -1,0 +1,230 @@
+"""C-ABI checks that need no GPU: exports, struct layout, argument validation.
+
+A handle created with device -1 owns no device resources; its compute calls
+run every host-side check and then return OFV_ERR_UNSUPPORTED, so each
+validation branch can be exercised here.
+"""
+import ctypes
+import os
+import re
+import subprocess
+from ctypes import byref, c_size_t, c_void_p
+
+import pytest
+
+from paper_2509_25924_amd import _build, _lib
+from paper_2509_25924_amd._lib import OfvImage, OfvParams
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("ofv.h", "ofv_stages.h")]
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not _build.built():
+        _build.build()
+    return _lib.load()
+
+
+def _declared_functions():
+    names = []
+    for h in HEADERS:
+        txt = open(h).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        names += re.findall(r"\b(ofv_[a-z_]+)\s*\(", txt)
+    return sorted(set(names))
+
+
+def test_every_declared_function_is_exported(lib):
+    declared = _declared_functions()
+    assert len(declared) >= 15
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (ofv_\w+)", out))
+    missing = [n for n in declared if n not in exported]
+    assert not missing, missing
+    # and the binding declares each of them
+    assert set(declared) <= set(_lib.EXPORTS)
+
+
+def test_struct_layout_matches_header(tmp_path):
+    src = tmp_path / "probe.c"
+    src.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "ofv.h"\n'
+        'int main(void){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(ofv_image), offsetof(ofv_image, pitch),'
+        ' offsetof(ofv_image, bit_depth), sizeof(ofv_params), offsetof(ofv_params, norm_eps),'
+        ' offsetof(ofv_params, flags)); return 0;}\n')
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    vals = list(map(int, subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()))
+    assert vals == [ctypes.sizeof(OfvImage), OfvImage.pitch.offset, OfvImage.bit_depth.offset,
+                    ctypes.sizeof(OfvParams), OfvParams.norm_eps.offset, OfvParams.flags.offset]
+
+
+def test_default_params(lib):
+    p = OfvParams()
+    lib.ofv_default_params(byref(p))
+    assert (p.num_levels, p.kernel_radius, p.iterations, p.norm_radius) == (3, 4, 3, 1)
+    assert abs(p.norm_eps - 1e-4) < 1e-10 and abs(p.reg_rel - 1e-3) < 1e-9 and p.storage == 0 and p.flags == 0
+    lib.ofv_default_params(None)
+
+
+def test_status_strings(lib):
+    for s in range(-5, 1):
+        assert lib.ofv_status_string(s)
+    assert lib.ofv_status_string(-99) == b"unknown status"
+
+
+@pytest.fixture
+def vhandle(lib):
+    h = c_void_p()
+    assert lib.ofv_create(byref(h), -1, 256, 128, 2, None) == _lib.OFV_OK
+    yield h
+    assert lib.ofv_destroy(h) == _lib.OFV_OK
+
+
+def _img(ptr=0x100000, w=64, h=32, pitch=None, typ=_lib.PIX_U8, bits=8):
+    return OfvImage(ptr, w, h, pitch if pitch is not None else w, typ, bits)
+
+
+def _params(**kw):
+    p = OfvParams()
+    _lib.load().ofv_default_params(byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+OUT = 0x90000000
+
+
+def _call(lib, h, i0, i1, p, out=OUT):
+    return lib.ofv_compute_flow(h, byref(i0), byref(i1), byref(p), c_void_p(out))
+
+
+def test_create_rejects_bad_arguments(lib):
+    h = c_void_p()
+    assert lib.ofv_create(None, -1, 8, 8, 1, None) == _lib.OFV_ERR_INVALID_ARG
+    assert lib.ofv_create(byref(h), -1, 0, 8, 1, None) == _lib.OFV_ERR_INVALID_ARG
+    assert h.value is None
+    assert b"max sizes" in lib.ofv_last_error(None)
+    assert lib.ofv_create(byref(h), -1, 8, 8, 0, None) == _lib.OFV_ERR_INVALID_ARG
+    assert lib.ofv_create(byref(h), -2, 8, 8, 1, None) == _lib.OFV_ERR_INVALID_ARG
+    assert lib.ofv_destroy(None) == _lib.OFV_OK
+
+
+def test_workspace_size_reported(lib, vhandle):
+    n = c_size_t()
+    assert lib.ofv_workspace_bytes(vhandle, byref(n)) == _lib.OFV_OK
+    # 2 pairs x (2 pyramid slabs of ~4/3 x 256x128 floats + 2 flow buffers of 2 x 256x128 floats)
+    assert 2 * (2 * 4 * 256 * 128 * 4 // 3 + 2 * 2 * 256 * 128 * 4) <= n.value < 2 * 1_000_000
+    assert lib.ofv_workspace_bytes(vhandle, None) == _lib.OFV_ERR_INVALID_ARG
+
+
+def test_valid_call_reaches_the_device_step(lib, vhandle):
+    assert _call(lib, vhandle, _img(), _img(0x200000), _params()) == _lib.OFV_ERR_UNSUPPORTED
+    assert b"validation-only" in lib.ofv_last_error(vhandle)
+
+
+@pytest.mark.parametrize("mut,status,msg", [
+    (lambda i0, i1, p: setattr(i0, "data", None), _lib.OFV_ERR_INVALID_ARG, b"data is NULL"),
+    (lambda i0, i1, p: setattr(i0, "width", 0), _lib.OFV_ERR_INVALID_ARG, b"size"),
+    (lambda i0, i1, p: setattr(i1, "height", -3), _lib.OFV_ERR_INVALID_ARG, b"size"),
+    (lambda i0, i1, p: setattr(i0, "pitch", 10), _lib.OFV_ERR_INVALID_ARG, b"pitch"),
+    (lambda i0, i1, p: setattr(i0, "bit_depth", 9), _lib.OFV_ERR_INVALID_ARG, b"bit_depth"),
+    (lambda i0, i1, p: (setattr(i0, "type", _lib.PIX_U16), setattr(i0, "bit_depth", 17)), _lib.OFV_ERR_INVALID_ARG,
+     b"bit_depth"),
+    (lambda i0, i1, p: setattr(i0, "type", 7), _lib.OFV_ERR_INVALID_ARG, b"pixel type"),
+    (lambda i0, i1, p: setattr(i1, "width", 63), _lib.OFV_ERR_INVALID_ARG, b"sizes differ"),
+    (lambda i0, i1, p: setattr(p, "num_levels", 0), _lib.OFV_ERR_INVALID_ARG, b"num_levels"),
+    (lambda i0, i1, p: setattr(p, "num_levels", 17), _lib.OFV_ERR_INVALID_ARG, b"num_levels"),
+    (lambda i0, i1, p: setattr(p, "kernel_radius", 0), _lib.OFV_ERR_INVALID_ARG, b"kernel_radius"),
+    (lambda i0, i1, p: setattr(p, "kernel_radius", 13), _lib.OFV_ERR_UNSUPPORTED, b"kernel_radius"),
+    (lambda i0, i1, p: setattr(p, "iterations", 0), _lib.OFV_ERR_INVALID_ARG, b"iterations"),
+    (lambda i0, i1, p: setattr(p, "norm_radius", -1), _lib.OFV_ERR_INVALID_ARG, b"norm_radius"),
+    (lambda i0, i1, p: setattr(p, "norm_radius", 17), _lib.OFV_ERR_INVALID_ARG, b"norm_radius"),
+    (lambda i0, i1, p: setattr(p, "norm_eps", float("nan")), _lib.OFV_ERR_INVALID_ARG, b"norm_eps"),
+    (lambda i0, i1, p: setattr(p, "reg_rel", -1.0), _lib.OFV_ERR_INVALID_ARG, b"reg_rel"),
+    (lambda i0, i1, p: setattr(p, "reg_abs", float("inf")), _lib.OFV_ERR_INVALID_ARG, b"reg_abs"),
+    (lambda i0, i1, p: setattr(p, "storage", 3), _lib.OFV_ERR_INVALID_ARG, b"storage"),
+    (lambda i0, i1, p: setattr(p, "flags", 1), _lib.OFV_ERR_INVALID_ARG, b"flags"),
+    (lambda i0, i1, p: (setattr(i0, "width", 257), setattr(i1, "width", 257), setattr(i0, "pitch", 257),
+                        setattr(i1, "pitch", 257)), _lib.OFV_ERR_CAPACITY, b"exceeds"),
+    (lambda i0, i1, p: (setattr(i0, "height", 129), setattr(i1, "height", 129)), _lib.OFV_ERR_CAPACITY, b"exceeds"),
+])
+def test_compute_rejects_bad_arguments(lib, vhandle, mut, status, msg):
+    i0, i1, p = _img(), _img(0x200000), _params()
+    mut(i0, i1, p)
+    assert _call(lib, vhandle, i0, i1, p) == status
+    assert msg in lib.ofv_last_error(vhandle)
+
+
+def test_null_arguments(lib, vhandle):
+    i0, i1, p = _img(), _img(0x200000), _params()
+    assert lib.ofv_compute_flow(None, byref(i0), byref(i1), byref(p), c_void_p(OUT)) == _lib.OFV_ERR_INVALID_ARG
+    assert lib.ofv_compute_flow(vhandle, None, byref(i1), byref(p), c_void_p(OUT)) == _lib.OFV_ERR_INVALID_ARG
+    assert lib.ofv_compute_flow(vhandle, byref(i0), byref(i1), None, c_void_p(OUT)) == _lib.OFV_ERR_INVALID_ARG
+    assert lib.ofv_compute_flow(vhandle, byref(i0), byref(i1), byref(p), None) == _lib.OFV_ERR_INVALID_ARG
+
+
+def test_output_aliasing_is_rejected(lib, vhandle):
+    i0, i1, p = _img(), _img(0x200000), _params()
+    # flow_out overlapping either frame
+    assert _call(lib, vhandle, i0, i1, p, out=0x100000 + 100) == _lib.OFV_ERR_INVALID_ARG
+    assert b"overlaps frame0" in lib.ofv_last_error(vhandle)
+    assert _call(lib, vhandle, i0, i1, p, out=0x200000 - 8) == _lib.OFV_ERR_INVALID_ARG
+    # flow_init may equal flow_out but not partially overlap it
+    assert lib.ofv_compute_flow_ex(vhandle, byref(i0), byref(i1), byref(p), c_void_p(OUT),
+                                   c_void_p(OUT)) == _lib.OFV_ERR_UNSUPPORTED
+    assert lib.ofv_compute_flow_ex(vhandle, byref(i0), byref(i1), byref(p), c_void_p(OUT + 4),
+                                   c_void_p(OUT)) == _lib.OFV_ERR_INVALID_ARG
+
+
+def test_batch_validation(lib, vhandle):
+    n = 3
+    a0 = (OfvImage * n)(*[_img(0x100000 * (k + 1)) for k in range(n)])
+    a1 = (OfvImage * n)(*[_img(0x1000000 + 0x100000 * k) for k in range(n)])
+    outs = (c_void_p * n)(*[OUT + 0x100000 * k for k in range(n)])
+    p = _params()
+    assert lib.ofv_compute_flow_batch(vhandle, n, a0, a1, byref(p), None, outs) == _lib.OFV_ERR_CAPACITY
+    assert lib.ofv_compute_flow_batch(vhandle, 0, a0, a1, byref(p), None, outs) == _lib.OFV_ERR_INVALID_ARG
+    assert lib.ofv_compute_flow_batch(vhandle, 2, a0, a1, byref(p), None, outs) == _lib.OFV_ERR_UNSUPPORTED
+    outs2 = (c_void_p * 2)(OUT, OUT + 64)
+    assert lib.ofv_compute_flow_batch(vhandle, 2, a0, a1, byref(p), None, outs2) == _lib.OFV_ERR_INVALID_ARG
+    assert b"overlaps flow_out" in lib.ofv_last_error(vhandle)
+
+
+def test_stage_validation(lib, vhandle):
+    img = _img()
+    assert lib.ofv_stage_normalize(vhandle, byref(img), 2, 1e-4, 0, c_void_p(OUT), 64) == _lib.OFV_ERR_UNSUPPORTED
+    assert lib.ofv_stage_normalize(vhandle, byref(img), 2, 1e-4, 0, c_void_p(OUT), 32) == _lib.OFV_ERR_INVALID_ARG
+    assert lib.ofv_stage_normalize(vhandle, byref(img), 99, 1e-4, 0, c_void_p(OUT), 64) == _lib.OFV_ERR_INVALID_ARG
+    assert lib.ofv_stage_reduce(vhandle, 0, c_void_p(0x1000), 10, 10, 9, c_void_p(OUT), 5) == _lib.OFV_ERR_INVALID_ARG
+    assert lib.ofv_stage_reduce(vhandle, 0, c_void_p(0x1000), 10, 10, 10, c_void_p(OUT), 5) == _lib.OFV_ERR_UNSUPPORTED
+    assert lib.ofv_stage_upsample(vhandle, c_void_p(0x1000), 5, 5, 5, c_void_p(OUT), 10, 10, 10) == \
+        _lib.OFV_ERR_UNSUPPORTED
+    args = [vhandle, 0, c_void_p(0x1000), c_void_p(0x2000), 16, 16, 16, _lib.FLOW_IN_DIRECT, c_void_p(OUT), 16, 16,
+            16, c_void_p(OUT + 16), 16, 4, 1e-3, 1e-9]
+    assert lib.ofv_stage_gn_iteration(*args) == _lib.OFV_ERR_INVALID_ARG      # output overlaps input
+    args[12] = c_void_p(OUT + 1 << 20)
+    assert lib.ofv_stage_gn_iteration(*args) == _lib.OFV_ERR_UNSUPPORTED
+    args[14] = 13
+    assert lib.ofv_stage_gn_iteration(*args) == _lib.OFV_ERR_UNSUPPORTED
+    args[14] = 4
+    args[7] = 5
+    assert lib.ofv_stage_gn_iteration(*args) == _lib.OFV_ERR_INVALID_ARG
+
+
+def test_fault_injection_reports_device_error(lib, vhandle, monkeypatch):
+    monkeypatch.setenv("OFV_FAULT_INJECT", "launch")
+    assert _call(lib, vhandle, _img(), _img(0x200000), _params()) == _lib.OFV_ERR_DEVICE
+    assert b"injected" in lib.ofv_last_error(vhandle)
+    monkeypatch.setenv("OFV_FAULT_INJECT", "alloc")
+    h = c_void_p()
+    assert lib.ofv_create(byref(h), 0, 64, 64, 1, None) == _lib.OFV_ERR_OUT_OF_MEMORY
+    assert h.value is None
+
+
+def test_missing_library_fails_loudly(tmp_path, monkeypatch):
+    monkeypatch.setattr(_lib, "_lib", None)
+    with pytest.raises(RuntimeError, match="missing"):
+        _lib.load(str(tmp_path / "nope.so"))
