@@ -32,6 +32,8 @@ def parse():
     ap.add_argument("--workload", default="shear_1mp", choices=["shear_1mp", "rankine_256", "paper_1mp"])
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--no-graph", action="store_true", help="launch eagerly instead of replaying a hipGraph")
+    ap.add_argument("--variant", default="tuned", choices=["tuned", "auto", "march", "tile64x32", "tile64x16"],
+                    help="Gauss-Newton work decomposition: autotuned per level (default) or forced")
     ap.add_argument("--kernel-launches", type=int, default=200, help="launches timed for the dominant kernel")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -83,6 +85,10 @@ def main():
     f1 = torch.from_numpy(pair.frame1).to(dev)
     out = torch.empty((2, h, w), dtype=torch.float32, device=dev)
     handle = ofv.Handle(w, h, 1)
+    if args.variant == "tuned":
+        handle.autotune(f0, f1, prm, bit_depth=bits, repeats=3)
+    else:
+        handle.set_gn_variant(args.variant)
 
     def step():
         ofv.compute_flow(f0, f1, prm, bit_depth=bits, out=out, handle=handle)
@@ -174,7 +180,9 @@ def main():
         "config": {"workload": f"{args.workload}: {desc}", "height": h, "width": w,
                    "num_levels": L, "kernel_radius": kr, "iterations": it,
                    "norm_radius": prm["norm_radius"], "storage": args.storage,
-                   "pairs_per_step": 1, "launch": "hipGraph replay" if graph is not None else "eager"},
+                   "pairs_per_step": 1, "launch": "hipGraph replay" if graph is not None else "eager",
+                   "gn_decomposition": args.variant,
+                   "tuning_table": handle.tuning_table().strip().splitlines() if args.variant == "tuned" else []},
         "fields_per_s": round(1.0 / sec, 1),
         "step_algorithmic_GBps": round(step_bytes / sec / 1e9, 1),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -127,6 +127,40 @@ ofv_status ofv_compute_flow_batch(ofv_handle h, int n, const ofv_image* frame0, 
                                   const ofv_params* params, const float* const* flow_init,
                                   float* const* flow_out);
 
+/* Work decompositions of the fused Gauss-Newton kernel, chosen per pyramid
+ * level and input-flow mode.  All give the same results up to float32
+ * rounding order (parity with the FP64 reference holds for each). */
+#define OFV_GN_AUTO (-1)      /* tuned table if it has an entry, else OFV_GN_TILE_64x16 */
+#define OFV_GN_MARCH 0        /* 256-column strips marching down tile_h rows */
+#define OFV_GN_TILE_64x32 1   /* 64 x 32 output tiles, three LDS phases */
+#define OFV_GN_TILE_64x16 2   /* 64 x 16 output tiles, three LDS phases */
+
+/* Force a decomposition for later calls on h (OFV_GN_AUTO restores the
+ * default); tile_h (rows per strip for OFV_GN_MARCH) is 0 for automatic or
+ * 4..1024. */
+ofv_status ofv_set_gn_variant(ofv_handle h, int variant, int tile_h);
+
+/* Autotuner: runs the estimator on this pair once per candidate
+ * decomposition (64x16 tiles, 64x32 tiles, strips of 16/32/64 rows), `repeats`
+ * timed runs each, times every Gauss-Newton launch with HIP events, and
+ * records the fastest candidate per (window radius, storage, flow mode, level
+ * size, batch size) in the handle; later calls with matching geometry use it.
+ * flow_out receives the flow (as ofv_compute_flow).  Unlike the compute
+ * calls this synchronises the stream and may create HIP events; call it at
+ * set-up, not inside graph capture.  1 <= repeats <= 1000. */
+ofv_status ofv_autotune(ofv_handle h, const ofv_image* frame0, const ofv_image* frame1, const ofv_params* params,
+                        float* flow_out, int repeats);
+
+/* The tuned table as text, one entry per line:
+ * "kr storage mode width height batch variant tile_h".  Writes at most cap
+ * bytes (NUL-terminated) to buf when buf is not NULL; *needed (if not NULL)
+ * receives the size including the NUL.  OFV_ERR_CAPACITY if cap is short. */
+ofv_status ofv_tuning_export(ofv_handle h, char* buf, size_t cap, size_t* needed);
+
+/* Merge entries in the export format into h's table; nothing is merged if
+ * any entry is malformed (OFV_ERR_INVALID_ARG). */
+ofv_status ofv_tuning_import(ofv_handle h, const char* text);
+
 /* Release the handle and its workspace.  NULL is accepted.  Synchronises the
  * handle's stream first. */
 ofv_status ofv_destroy(ofv_handle h);

@@ -21,6 +21,7 @@ FLOW_IN_ZERO, FLOW_IN_DIRECT, FLOW_IN_UPSAMPLE = 0, 1, 2
 MAX_LEVELS = 16
 MAX_KERNEL_RADIUS = 12
 MAX_NORM_RADIUS = 16
+GN_VARIANTS = {"auto": -1, "march": 0, "tile64x32": 1, "tile64x16": 2}
 
 
 class OfvImage(ctypes.Structure):
@@ -46,6 +47,10 @@ EXPORTS = {
     "ofv_compute_flow_batch": (c_int, [c_void_p, c_int, POINTER(OfvImage), POINTER(OfvImage), POINTER(OfvParams),
                                        POINTER(c_void_p), POINTER(c_void_p)]),
     "ofv_destroy": (c_int, [c_void_p]),
+    "ofv_set_gn_variant": (c_int, [c_void_p, c_int, c_int]),
+    "ofv_autotune": (c_int, [c_void_p, POINTER(OfvImage), POINTER(OfvImage), POINTER(OfvParams), c_void_p, c_int]),
+    "ofv_tuning_export": (c_int, [c_void_p, c_char_p, c_size_t, POINTER(c_size_t)]),
+    "ofv_tuning_import": (c_int, [c_void_p, c_char_p]),
     "ofv_status_string": (c_char_p, [c_int]),
     "ofv_last_error": (c_char_p, [c_void_p]),
     "ofv_stage_normalize": (c_int, [c_void_p, POINTER(OfvImage), c_int, c_float, c_int, c_void_p, c_int64]),

@@ -52,6 +52,32 @@ class Handle:
         check(load().ofv_workspace_bytes(self.ptr, byref(n)), self.ptr)
         return n.value
 
+    def set_gn_variant(self, variant: str = "auto", tile_h: int = 0) -> None:
+        """Force a work decomposition of the Gauss-Newton kernel ('auto', 'march', 'tile64x32', 'tile64x16')."""
+        check(load().ofv_set_gn_variant(self.ptr, _lib.GN_VARIANTS[variant], int(tile_h)), self.ptr)
+
+    def autotune(self, frame0: torch.Tensor, frame1: torch.Tensor, params: Dict, bit_depth: Optional[int] = None,
+                 repeats: int = 3) -> torch.Tensor:
+        """Time every decomposition on this pair and keep the fastest per level (synchronises)."""
+        self.bind_stream()
+        h, w = frame0.shape
+        out = torch.empty((2, h, w), dtype=torch.float32, device=frame0.device)
+        i0, i1 = image_desc(frame0, bit_depth), image_desc(frame1, bit_depth)
+        p = params_struct(params)
+        check(load().ofv_autotune(self.ptr, byref(i0), byref(i1), byref(p), c_void_p(out.data_ptr()), int(repeats)),
+              self.ptr)
+        return out
+
+    def tuning_table(self) -> str:
+        need = c_size_t()
+        check(load().ofv_tuning_export(self.ptr, None, 0, byref(need)), self.ptr)
+        buf = ctypes.create_string_buffer(need.value)
+        check(load().ofv_tuning_export(self.ptr, buf, need.value, byref(need)), self.ptr)
+        return buf.value.decode()
+
+    def load_tuning_table(self, text: str) -> None:
+        check(load().ofv_tuning_import(self.ptr, text.encode()), self.ptr)
+
     def fits(self, w: int, h: int, n: int = 1) -> bool:
         return w <= self.max_width and h <= self.max_height and n <= self.max_batch
 

@@ -11,7 +11,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <sstream>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "ofv.h"
@@ -45,6 +48,28 @@ struct ofv_ctx {
   char* ws = nullptr;
   size_t ws_bytes = 0;
   std::string err;
+  // work decomposition of the Gauss-Newton kernel: tuned table, forced choice
+  struct TuneKey {
+    int kr, storage, mode, w, hgt, n;
+    bool operator<(const TuneKey& o) const {
+      return std::tie(kr, storage, mode, w, hgt, n) < std::tie(o.kr, o.storage, o.mode, o.w, o.hgt, o.n);
+    }
+  };
+  struct Choice {
+    int variant, tile_h;
+  };
+  std::map<TuneKey, Choice> tuned;
+  int forced_variant = -1;  // -1: tuned table, else the heuristic
+  int forced_tile_h = 0;
+  // event capture around Gauss-Newton launches (ofv_autotune only)
+  bool capture = false;
+  std::vector<hipEvent_t> events;
+  size_t events_used = 0;
+  struct Rec {
+    TuneKey key;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
 };
 
 namespace {
@@ -177,6 +202,40 @@ int choose_tile_h(int64_t strips_total, int64_t rows_max) {
   return th;
 }
 
+// Work decomposition of the Gauss-Newton kernel for one launch group:
+// OFV_GN_VARIANT in the environment, then a choice forced on the handle, then
+// the handle's tuned table, then the default (64 x 16 tiles).
+void pick_gn(const ofv_ctx* h, const ofv_ctx::TuneKey& key, int64_t strips, int64_t rows_max, int& variant,
+             int& tile_h) {
+  tile_h = choose_tile_h(strips, rows_max);
+  if (const char* e = std::getenv("OFV_GN_VARIANT")) {
+    if (!std::strcmp(e, "march")) { variant = GN_MARCH; return; }
+    if (!std::strcmp(e, "tile32")) { variant = GN_TILE_64x32; return; }
+    if (!std::strcmp(e, "tile16")) { variant = GN_TILE_64x16; return; }
+  }
+  if (h->forced_variant >= 0) {
+    variant = h->forced_variant;
+    if (h->forced_tile_h > 0) tile_h = h->forced_tile_h;
+    return;
+  }
+  auto it = h->tuned.find(key);
+  if (it != h->tuned.end()) {
+    variant = it->second.variant;
+    tile_h = it->second.tile_h;
+    return;
+  }
+  variant = GN_TILE_64x16;
+}
+
+hipEvent_t next_event(ofv_ctx* h) {
+  if (h->events_used == h->events.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    h->events.push_back(e);
+  }
+  return h->events[h->events_used++];
+}
+
 // Launches jobs in chunks of kMaxJobs; `fill` writes job i into args and
 // returns its block count.
 template <typename Args, typename Fill, typename Launch>
@@ -305,11 +364,9 @@ ofv_status run_pipeline(ofv_ctx* h, int n, PairPlan* pp, const ofv_params* p) {
       strips += (pp[j].lw[l] + tx - 1) / tx;
       rows_max = std::max<int64_t>(rows_max, pp[j].lh[l]);
     }
-    const int tile_h = choose_tile_h(strips, rows_max);
     for (int k = 0; k < it; ++k) {
       const bool final_iter = (l == 0 && k == it - 1);
       GnArgs ga{};
-      ga.tile_h = tile_h;
       ga.reg_rel = p->reg_rel;
       ga.reg_abs = p->reg_abs;
       std::vector<int> next(n);
@@ -323,6 +380,15 @@ ofv_status run_pipeline(ofv_ctx* h, int n, PairPlan* pp, const ofv_params* p) {
         for (int j = 0; j < n; ++j)
           if (mode_of(j) == mode) group.push_back(j);
         if (group.empty()) continue;
+        ofv_ctx::TuneKey key{kr, st, mode, 0, 0, static_cast<int>(group.size())};
+        for (int j : group) {
+          key.w = std::max(key.w, pp[j].lw[l]);
+          key.hgt = std::max(key.hgt, pp[j].lh[l]);
+        }
+        int variant = 0, tile_h = 0, tw = 0, th = 0;
+        pick_gn(h, key, strips, rows_max, variant, tile_h);
+        gn_tile_dims(variant, kr, tile_h, tw, th);
+        ga.tile_h = tile_h;
         auto fill = [&](int gi, GnJob& J) {
           const int j = group[gi];
           const PairPlan& q = pp[j];
@@ -361,12 +427,23 @@ ofv_status run_pipeline(ofv_ctx* h, int n, PairPlan* pp, const ofv_params* p) {
             J.out_pitch = h->lpitch[l];
             next[j] = nb;
           }
-          return static_cast<int>(((q.lw[l] + tx - 1) / tx) * ((q.lh[l] + tile_h - 1) / tile_h));
+          return static_cast<int>(((q.lw[l] + tw - 1) / tw) * ((q.lh[l] + th - 1) / th));
         };
+        hipEvent_t ev0 = nullptr, ev1 = nullptr;
+        if (h->capture) {
+          ev0 = next_event(h);
+          ev1 = next_event(h);
+          if (!ev0 || !ev1) return fail(h, OFV_ERR_DEVICE, "hipEventCreate failed while tuning");
+          (void)hipEventRecord(ev0, s);
+        }
         ofv_status r = run_chunked(h, static_cast<int>(group.size()), ga, fill,
-                                   [&](const GnArgs& a, int b) { return launch_gn(a, kr, st, mode, b, s); },
+                                   [&](const GnArgs& a, int b) { return launch_gn(a, kr, st, mode, variant, b, s); },
                                    "gauss-newton iteration");
         if (r != OFV_OK) return r;
+        if (h->capture) {
+          (void)hipEventRecord(ev1, s);
+          h->recs.push_back({key, ev0, ev1});
+        }
       }
       cur = next;
     }
@@ -566,10 +643,105 @@ ofv_status ofv_destroy(ofv_handle h) {
   if (h->device >= 0) {
     DeviceGuard g(h->device);
     if (hipStreamSynchronize(h->stream) != hipSuccess) r = OFV_ERR_DEVICE;
+    for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
     if (h->ws && hipFree(h->ws) != hipSuccess) r = OFV_ERR_DEVICE;
   }
   delete h;
   return r;
+}
+
+// ------------------------------------------------------------------ work-decomposition tuning
+
+ofv_status ofv_set_gn_variant(ofv_handle h, int variant, int tile_h) {
+  if (check_handle(h) != OFV_OK) return OFV_ERR_INVALID_ARG;
+  if (variant < -1 || variant > GN_TILE_64x16) return fail(h, OFV_ERR_INVALID_ARG, "unknown variant %d", variant);
+  if (tile_h != 0 && (tile_h < 4 || tile_h > 1024)) return fail(h, OFV_ERR_INVALID_ARG, "tile_h %d outside 4..1024", tile_h);
+  h->forced_variant = variant;
+  h->forced_tile_h = tile_h;
+  return OFV_OK;
+}
+
+ofv_status ofv_autotune(ofv_handle h, const ofv_image* frame0, const ofv_image* frame1, const ofv_params* params,
+                        float* flow_out, int repeats) {
+  if (check_handle(h) != OFV_OK) return OFV_ERR_INVALID_ARG;
+  if (repeats < 1 || repeats > 1000) return fail(h, OFV_ERR_INVALID_ARG, "repeats %d outside 1..1000", repeats);
+  // validate exactly like a compute call (the validation-only handle stops there)
+  ofv_status r = compute_common(h, 1, frame0, frame1, params, nullptr, &flow_out);
+  if (r != OFV_OK) return r;
+  DeviceGuard g(h->device);
+  struct Cand {
+    int variant, tile_h;
+  };
+  // tile variants ignore tile_h (their tile height is fixed); it is recorded as their height
+  const Cand cands[] = {{GN_TILE_64x16, 16}, {GN_TILE_64x32, 32}, {GN_MARCH, 16}, {GN_MARCH, 32}, {GN_MARCH, 64}};
+  std::map<ofv_ctx::TuneKey, std::pair<float, ofv_ctx::Choice>> best;
+  const int saved_v = h->forced_variant, saved_t = h->forced_tile_h;
+  for (const Cand& c : cands) {
+    h->forced_variant = c.variant;
+    h->forced_tile_h = c.tile_h;
+    r = compute_common(h, 1, frame0, frame1, params, nullptr, &flow_out);  // warm-up
+    if (r != OFV_OK) break;
+    h->capture = true;
+    h->events_used = 0;
+    h->recs.clear();
+    for (int k = 0; k < repeats && r == OFV_OK; ++k) r = compute_common(h, 1, frame0, frame1, params, nullptr, &flow_out);
+    h->capture = false;
+    if (r != OFV_OK) break;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) {
+      r = fail(h, OFV_ERR_DEVICE, "synchronisation failed while tuning");
+      break;
+    }
+    std::map<ofv_ctx::TuneKey, float> tot;
+    for (const auto& rec : h->recs) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, rec.a, rec.b) != hipSuccess) ms = 1e30f;
+      tot[rec.key] += ms;
+    }
+    for (const auto& kv : tot) {
+      auto it = best.find(kv.first);
+      if (it == best.end() || kv.second < it->second.first)
+        best[kv.first] = {kv.second, ofv_ctx::Choice{c.variant, c.tile_h}};
+    }
+  }
+  h->forced_variant = saved_v;
+  h->forced_tile_h = saved_t;
+  h->recs.clear();
+  if (r != OFV_OK) return r;
+  for (const auto& kv : best) h->tuned[kv.first] = kv.second.second;
+  return OFV_OK;
+}
+
+ofv_status ofv_tuning_export(ofv_handle h, char* buf, size_t cap, size_t* needed) {
+  if (check_handle(h) != OFV_OK) return OFV_ERR_INVALID_ARG;
+  std::ostringstream os;
+  for (const auto& kv : h->tuned)
+    os << kv.first.kr << ' ' << kv.first.storage << ' ' << kv.first.mode << ' ' << kv.first.w << ' '
+       << kv.first.hgt << ' ' << kv.first.n << ' ' << kv.second.variant << ' ' << kv.second.tile_h << '\n';
+  const std::string txt = os.str();
+  if (needed) *needed = txt.size() + 1;
+  if (!buf) return OFV_OK;
+  if (cap < txt.size() + 1) return fail(h, OFV_ERR_CAPACITY, "buffer of %zu bytes, %zu needed", cap, txt.size() + 1);
+  std::memcpy(buf, txt.c_str(), txt.size() + 1);
+  return OFV_OK;
+}
+
+ofv_status ofv_tuning_import(ofv_handle h, const char* text) {
+  if (check_handle(h) != OFV_OK) return OFV_ERR_INVALID_ARG;
+  if (!text) return fail(h, OFV_ERR_INVALID_ARG, "text is NULL");
+  std::istringstream is(text);
+  std::map<ofv_ctx::TuneKey, ofv_ctx::Choice> add;
+  ofv_ctx::TuneKey k{};
+  ofv_ctx::Choice c{};
+  int line = 0;
+  while (is >> k.kr >> k.storage >> k.mode >> k.w >> k.hgt >> k.n >> c.variant >> c.tile_h) {
+    ++line;
+    if (c.variant < GN_MARCH || c.variant > GN_TILE_64x16 || c.tile_h < 4 || c.tile_h > 1024)
+      return fail(h, OFV_ERR_INVALID_ARG, "tuning entry %d is invalid", line);
+    add[k] = c;
+  }
+  if (!is.eof()) return fail(h, OFV_ERR_INVALID_ARG, "tuning text is malformed after %d entries", line);
+  for (const auto& kv : add) h->tuned[kv.first] = kv.second;
+  return OFV_OK;
 }
 
 // ------------------------------------------------------------------ stage entry points
@@ -722,7 +894,10 @@ ofv_status ofv_stage_gn_iteration(ofv_handle h, int storage, const void* p0, con
   ga.reg_rel = reg_rel;
   ga.reg_abs = reg_abs;
   const int tx = gn_tile_w(kernel_radius);
-  ga.tile_h = choose_tile_h((width + tx - 1) / tx, height);
+  int variant = 0, tw = 0, th = 0;
+  pick_gn(h, ofv_ctx::TuneKey{kernel_radius, storage, mode, width, height, 1}, (width + tx - 1) / tx, height,
+          variant, ga.tile_h);
+  gn_tile_dims(variant, kernel_radius, ga.tile_h, tw, th);
   GnJob& J = ga.job[0];
   J.p0 = p0;
   J.p1 = p1;
@@ -739,8 +914,8 @@ ofv_status ofv_stage_gn_iteration(ofv_handle h, int storage, const void* p0, con
   J.out_v = flow_out + static_cast<int64_t>(height) * out_pitch;
   J.out_pitch = out_pitch;
   J.tile_start = 0;
-  const int blocks = ((width + tx - 1) / tx) * ((height + ga.tile_h - 1) / ga.tile_h);
-  hipError_t e = launch_gn(ga, kernel_radius, storage, mode, blocks, h->stream);
+  const int blocks = ((width + tw - 1) / tw) * ((height + th - 1) / th);
+  hipError_t e = launch_gn(ga, kernel_radius, storage, mode, variant, blocks, h->stream);
   return e == hipSuccess ? OFV_OK : device_error(h, e, "gauss-newton iteration");
 }
 

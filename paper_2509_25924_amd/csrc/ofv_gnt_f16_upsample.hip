@@ -1,0 +1,10 @@
+// Fused Gauss-Newton iteration, 2-D tile variants: _Float16 image storage, input flow mode FLOW_UPSAMPLE.
+#include "ofv_gn_tile.h"
+
+namespace ofv {
+
+hipError_t launch_gnt_f16_upsample(const GnArgs& a, int kr, int variant, int nblocks, hipStream_t s) {
+  return launch_gn_tile_typed<FLOW_UPSAMPLE, _Float16>(a, kr, variant, nblocks, s);
+}
+
+}  // namespace ofv

@@ -1,0 +1,10 @@
+// Fused Gauss-Newton iteration, 2-D tile variants: float image storage, input flow mode FLOW_DIRECT.
+#include "ofv_gn_tile.h"
+
+namespace ofv {
+
+hipError_t launch_gnt_f32_direct(const GnArgs& a, int kr, int variant, int nblocks, hipStream_t s) {
+  return launch_gn_tile_typed<FLOW_DIRECT, float>(a, kr, variant, nblocks, s);
+}
+
+}  // namespace ofv

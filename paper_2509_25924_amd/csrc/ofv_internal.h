@@ -78,13 +78,23 @@ struct GnArgs {
   GnJob job[kMaxJobs];
 };
 
+// Work decompositions of the fused Gauss-Newton kernel.
+enum GnVariant { GN_MARCH = 0, GN_TILE_64x32 = 1, GN_TILE_64x16 = 2 };
+
 // Columns of output produced by one 256-lane strip for window radius kr.
 inline int gn_tile_w(int kr) { return kGnThreads - 2 * kr - 2; }
+
+// Output tile of a variant: width and height (march: strip width, tile_h rows).
+inline void gn_tile_dims(int variant, int kr, int tile_h, int& tw, int& th) {
+  if (variant == GN_TILE_64x32) { tw = 64; th = 32; }
+  else if (variant == GN_TILE_64x16) { tw = 64; th = 16; }
+  else { tw = gn_tile_w(kr); th = tile_h; }
+}
 
 hipError_t launch_normalize(const NormArgs& a, int nblocks, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, int nblocks, hipStream_t s);
 hipError_t launch_upsample(const UpsampleArgs& a, hipStream_t s);
 // All jobs of one launch share the input-flow mode (a compile-time parameter of the kernel).
-hipError_t launch_gn(const GnArgs& a, int kr, int storage, int mode, int nblocks, hipStream_t s);
+hipError_t launch_gn(const GnArgs& a, int kr, int storage, int mode, int variant, int nblocks, hipStream_t s);
 
 }  // namespace ofv

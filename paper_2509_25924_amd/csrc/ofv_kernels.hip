@@ -41,12 +41,23 @@ __global__ __launch_bounds__(256) void normalize_kernel(const NormArgs a) {
   const int nr = a.nr;
   const int tw = kNormTW + 2 * nr;
   const int th = kNormTH + 2 * nr;
-  for (int i = threadIdx.x; i < tw * th; i += blockDim.x) {
-    const int gx = x0 - nr + i % tw;
-    const int gy = y0 - nr + i / tw;
-    float v = 0.0f;
-    if (gx >= 0 && gx < J.w && gy >= 0 && gy < J.h) v = load_frame_px(J, gx, gy);
-    tile[i] = v;
+  // all loads of the tile are issued before any is stored (up to 8 per lane
+  // in flight); rows and columns outside the frame read as 0 and are never used
+  const int n = tw * th;
+  for (int i0 = threadIdx.x; i0 < n; i0 += 8 * 256) {
+    float v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int i = min(i0 + 256 * k, n - 1);
+      const int gx = x0 - nr + i % tw;
+      const int gy = y0 - nr + i / tw;
+      const bool in = gx >= 0 && gx < J.w && gy >= 0 && gy < J.h;
+      v[k] = load_frame_px(J, min(max(gx, 0), J.w - 1), min(max(gy, 0), J.h - 1));
+      v[k] = in ? v[k] : 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (i0 + 256 * k < n) tile[i0 + 256 * k] = v[k];
   }
   __syncthreads();
   const int lx = threadIdx.x & 63;
@@ -179,8 +190,30 @@ OFV_DECL(bf16, zero)
 OFV_DECL(bf16, direct)
 OFV_DECL(bf16, upsample)
 #undef OFV_DECL
+#define OFV_DECLT(ST, MD) \
+  hipError_t launch_gnt_##ST##_##MD(const GnArgs& a, int kr, int variant, int nblocks, hipStream_t s);
+OFV_DECLT(f32, zero)
+OFV_DECLT(f32, direct)
+OFV_DECLT(f32, upsample)
+OFV_DECLT(f16, zero)
+OFV_DECLT(f16, direct)
+OFV_DECLT(f16, upsample)
+OFV_DECLT(bf16, zero)
+OFV_DECLT(bf16, direct)
+OFV_DECLT(bf16, upsample)
+#undef OFV_DECLT
 
-hipError_t launch_gn(const GnArgs& a, int kr, int storage, int mode, int nblocks, hipStream_t s) {
+hipError_t launch_gn(const GnArgs& a, int kr, int storage, int mode, int variant, int nblocks, hipStream_t s) {
+  if (variant != GN_MARCH) {
+#define OFV_PICKT(ST)                                                                     \
+  if (mode == FLOW_ZERO) return launch_gnt_##ST##_zero(a, kr, variant, nblocks, s);     \
+  if (mode == FLOW_DIRECT) return launch_gnt_##ST##_direct(a, kr, variant, nblocks, s); \
+  return launch_gnt_##ST##_upsample(a, kr, variant, nblocks, s);
+    if (storage == ST_F32) { OFV_PICKT(f32) }
+    if (storage == ST_F16) { OFV_PICKT(f16) }
+    OFV_PICKT(bf16)
+#undef OFV_PICKT
+  }
 #define OFV_PICK(ST)                                                    \
   if (mode == FLOW_ZERO) return launch_gn_##ST##_zero(a, kr, nblocks, s);     \
   if (mode == FLOW_DIRECT) return launch_gn_##ST##_direct(a, kr, nblocks, s); \

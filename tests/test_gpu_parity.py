@@ -373,3 +373,46 @@ def test_graph_replay_matches_eager(ofv):
         torch.cuda.synchronize()
         assert torch.equal(other, -eager)
     h.close()
+
+
+@pytest.mark.parametrize("variant,tile_h", [("march", 0), ("march", 8), ("tile64x32", 0), ("tile64x16", 0)])
+def test_every_decomposition_matches_oracle(ofv, variant, tile_h):
+    say("decomposition", variant, tile_h)
+    pair, prm = synth.config_shear_1mp(size=300)
+    prm = dict(prm, kernel_radius=7)
+    f0, f1 = dev_tensor(pair.frame0), dev_tensor(pair.frame1)
+    h = ofv.Handle(300, 300, 1)
+    h.set_gn_variant(variant, tile_h)
+    got = ofv.compute_flow(f0, f1, prm, bit_depth=12, handle=h)
+    ref = oracle.compute_flow(pair.frame0, pair.frame1, prm, bit_depth0=12)
+    err = torch.max(torch.abs(o64(got) - ref)).item()
+    say("  max |dV| =", err)
+    assert err <= FLOW_TOL
+    h.close()
+
+
+def test_autotune_table_roundtrip(ofv):
+    say("autotune")
+    pair, prm = synth.config_rankine_256()
+    f0, f1 = dev_tensor(pair.frame0), dev_tensor(pair.frame1)
+    h = ofv.Handle(256, 256, 1)
+    out = h.autotune(f0, f1, prm, bit_depth=8, repeats=2)
+    table = h.tuning_table()
+    lines = [l for l in table.splitlines() if l.strip()]
+    # one entry per (level, input-flow mode): 3 levels, the coarsest without up-sampling
+    assert len(lines) >= prm["num_levels"]
+    for l in lines:
+        kr, st, mode, w, hh, n, var, th = map(int, l.split())
+        assert kr == prm["kernel_radius"] and n == 1 and var in (0, 1, 2)
+    tuned = ofv.compute_flow(f0, f1, prm, bit_depth=8, handle=h)
+    ref = oracle.compute_flow(pair.frame0, pair.frame1, prm, bit_depth0=8)
+    assert torch.max(torch.abs(o64(tuned) - ref)).item() <= FLOW_TOL
+    assert torch.max(torch.abs(o64(out) - ref)).item() <= FLOW_TOL
+    h2 = ofv.Handle(256, 256, 1)
+    h2.load_tuning_table(table)
+    assert h2.tuning_table() == table
+    assert torch.equal(ofv.compute_flow(f0, f1, prm, bit_depth=8, handle=h2), tuned)
+    with pytest.raises(ofv.OfvError):
+        h2.load_tuning_table("5 0 1 64 64 1 9 16\n")
+    h.close()
+    h2.close()
