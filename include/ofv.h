@@ -127,6 +127,32 @@ ofv_status ofv_compute_flow_batch(ofv_handle h, int n, const ofv_image* frame0, 
                                   const ofv_params* params, const float* const* flow_init,
                                   float* const* flow_out);
 
+/* Reserve device memory for ofv_compute_flow_backward on pairs up to the
+ * handle's max size with up to max_levels levels and max_iterations
+ * iterations per level: the output field of every iteration (8 bytes per
+ * pixel of each level per iteration), 41 scratch planes and two gradient
+ * pyramids.  A set-up call: it allocates (and may synchronise to release a
+ * smaller reservation). */
+ofv_status ofv_reserve_backward(ofv_handle h, int max_levels, int max_iterations);
+
+/* Reverse-mode derivative of the whole estimator (normalisation, pyramid,
+ * every Gauss-Newton iteration, up-sampling, initial-field restriction):
+ * given grad_flow = dL/dflow_out (device float32 [2][H][W]) it writes
+ *   grad_frame0, grad_frame1: dL/dframe, device float32 [H][W] (row pitch W),
+ *     in the frames' own units (integer frames: per digital number);
+ *   grad_flow_init: dL/dflow_init, device float32 [2][H][W] (needs flow_init).
+ * Each output may be NULL.  The forward is re-run first, keeping only each
+ * iteration's output field; warps, gradients, products and window sums are
+ * recomputed per iteration rather than stored.  The image gradients are
+ * accumulated with float atomics, so results are reproducible only up to
+ * summation order.  Needs F32 storage (OFV_ERR_UNSUPPORTED otherwise) and a
+ * prior ofv_reserve_backward covering the levels and iterations
+ * (OFV_ERR_CAPACITY otherwise).  Enqueues only: no allocation, no sync.
+ * Outputs must not overlap the inputs or each other. */
+ofv_status ofv_compute_flow_backward(ofv_handle h, const ofv_image* frame0, const ofv_image* frame1,
+                                     const ofv_params* params, const float* flow_init, const float* grad_flow,
+                                     float* grad_frame0, float* grad_frame1, float* grad_flow_init);
+
 /* Work decompositions of the fused Gauss-Newton kernel, chosen per pyramid
  * level and input-flow mode.  All give the same results up to float32
  * rounding order (parity with the FP64 reference holds for each). */

@@ -47,6 +47,9 @@ EXPORTS = {
     "ofv_compute_flow_batch": (c_int, [c_void_p, c_int, POINTER(OfvImage), POINTER(OfvImage), POINTER(OfvParams),
                                        POINTER(c_void_p), POINTER(c_void_p)]),
     "ofv_destroy": (c_int, [c_void_p]),
+    "ofv_reserve_backward": (c_int, [c_void_p, c_int, c_int]),
+    "ofv_compute_flow_backward": (c_int, [c_void_p, POINTER(OfvImage), POINTER(OfvImage), POINTER(OfvParams),
+                                          c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "ofv_set_gn_variant": (c_int, [c_void_p, c_int, c_int]),
     "ofv_autotune": (c_int, [c_void_p, POINTER(OfvImage), POINTER(OfvImage), POINTER(OfvParams), c_void_p, c_int]),
     "ofv_tuning_export": (c_int, [c_void_p, c_char_p, c_size_t, POINTER(c_size_t)]),

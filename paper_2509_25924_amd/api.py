@@ -52,6 +52,10 @@ class Handle:
         check(load().ofv_workspace_bytes(self.ptr, byref(n)), self.ptr)
         return n.value
 
+    def reserve_backward(self, levels: int, iterations: int) -> None:
+        """Allocate the adjoint's workspace for up to `levels` x `iterations` (set-up call)."""
+        check(load().ofv_reserve_backward(self.ptr, int(levels), int(iterations)), self.ptr)
+
     def set_gn_variant(self, variant: str = "auto", tile_h: int = 0) -> None:
         """Force a work decomposition of the Gauss-Newton kernel ('auto', 'march', 'tile64x32', 'tile64x16')."""
         check(load().ofv_set_gn_variant(self.ptr, _lib.GN_VARIANTS[variant], int(tile_h)), self.ptr)
@@ -182,6 +186,64 @@ def compute_flow_batch(frames0: Sequence[torch.Tensor], frames1: Sequence[torch.
     p = params_struct(params)
     check(load().ofv_compute_flow_batch(hd.ptr, n, arr0, arr1, byref(p), init_ptrs, out_ptrs), hd.ptr)
     return list(outs)
+
+
+def compute_flow_backward(frame0: torch.Tensor, frame1: torch.Tensor, params: Dict, grad_flow: torch.Tensor,
+                          flow_init: Optional[torch.Tensor] = None, bit_depth: Optional[int] = None,
+                          need_frames: bool = True, need_init: bool = True, handle: Optional[Handle] = None):
+    """Hand-written adjoint: (dL/dframe0, dL/dframe1, dL/dflow_init) for dL/dflow = grad_flow.
+
+    Frame gradients are float32 [H, W] in the frames' own units; entries not
+    requested (or dL/dflow_init without flow_init) are None.
+    """
+    h, w = frame0.shape
+    hd = handle or default_handle(w, h, 1, frame0.device.index)
+    hd.bind_stream()
+    hd.reserve_backward(params.get("num_levels", 3), params.get("iterations", 3))
+    _check_flow(grad_flow, h, w, "grad_flow")
+    g0 = torch.empty((h, w), dtype=torch.float32, device=frame0.device) if need_frames else None
+    g1 = torch.empty((h, w), dtype=torch.float32, device=frame0.device) if need_frames else None
+    gi = None
+    if flow_init is not None:
+        _check_flow(flow_init, h, w, "flow_init")
+        if need_init:
+            gi = torch.empty((2, h, w), dtype=torch.float32, device=frame0.device)
+    i0, i1 = image_desc(frame0, bit_depth), image_desc(frame1, bit_depth)
+    p = params_struct(params)
+    ptr = lambda t: None if t is None else c_void_p(t.data_ptr())  # noqa: E731
+    check(load().ofv_compute_flow_backward(hd.ptr, byref(i0), byref(i1), byref(p), ptr(flow_init), ptr(grad_flow),
+                                           ptr(g0), ptr(g1), ptr(gi)), hd.ptr)
+    return g0, g1, gi
+
+
+class OFVFunction(torch.autograd.Function):
+    """Dense flow with gradients w.r.t. both frames and the initial field.
+
+    ``OFVFunction.apply(frame0, frame1, flow_init, params, handle)``; frames
+    are float32 [H, W] device tensors (integer frames give no frame
+    gradient), flow_init is None or float32 [2, H, W].  The backward calls the
+    library's hand-written adjoint (recompute mode).
+    """
+
+    @staticmethod
+    def forward(ctx, frame0, frame1, flow_init, params, handle=None):
+        out = compute_flow(frame0, frame1, params, flow_init=flow_init, handle=handle)
+        ctx.params = dict(params)
+        ctx.handle = handle
+        ctx.has_init = flow_init is not None
+        ctx.save_for_backward(frame0, frame1, flow_init if flow_init is not None else frame0.new_empty(0))
+        return out
+
+    @staticmethod
+    def backward(ctx, grad):
+        f0, f1, fi = ctx.saved_tensors
+        need_f = ctx.needs_input_grad[0] or ctx.needs_input_grad[1]
+        need_i = ctx.has_init and ctx.needs_input_grad[2]
+        g0, g1, gi = compute_flow_backward(f0, f1, ctx.params, grad.contiguous(),
+                                           flow_init=fi if ctx.has_init else None, need_frames=need_f,
+                                           need_init=need_i, handle=ctx.handle)
+        return (g0 if ctx.needs_input_grad[0] else None, g1 if ctx.needs_input_grad[1] else None,
+                gi if need_i else None, None, None)
 
 
 def _check_flow(t: torch.Tensor, h: int, w: int, name: str) -> None:

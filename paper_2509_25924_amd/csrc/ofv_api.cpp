@@ -70,6 +70,10 @@ struct ofv_ctx {
     hipEvent_t a, b;
   };
   std::vector<Rec> recs;
+  // backward workspace (ofv_reserve_backward): saved iterates, scratch planes, image-gradient pyramids
+  float* bw = nullptr;
+  size_t bw_bytes = 0;
+  int bw_levels = 0, bw_iters = 0;
 };
 
 namespace {
@@ -255,7 +259,9 @@ ofv_status run_chunked(ofv_ctx* h, int njobs, Args& args, Fill fill, Launch laun
   return OFV_OK;
 }
 
-ofv_status run_pipeline(ofv_ctx* h, int n, PairPlan* pp, const ofv_params* p) {
+// save (optional, n == 1): per (level l, iteration k) at index l * IT + k, the u plane
+// that receives that iteration's output (v plane lpitch[l] * lh[l] further).
+ofv_status run_pipeline(ofv_ctx* h, int n, PairPlan* pp, const ofv_params* p, float* const* save = nullptr) {
   const int L = p->num_levels;
   const int kr = p->kernel_radius;
   const int it = p->iterations;
@@ -414,7 +420,21 @@ ofv_status run_pipeline(ofv_ctx* h, int n, PairPlan* pp, const ofv_params* p) {
             J.in_v = src + h->lpitch[l] * h->lh[l];
             J.in_pitch = h->lpitch[l];
           }
-          if (final_iter) {
+          if (save) {
+            // every iteration reads its predecessor's saved output and writes its own slot
+            if (mode == FLOW_UPSAMPLE) {
+              J.in_u = save[(l + 1) * it + it - 1];
+              J.in_v = J.in_u + h->lpitch[l + 1] * h->lh[l + 1];
+            } else if (mode == FLOW_DIRECT && k >= 1) {
+              J.in_u = save[l * it + k - 1];
+              J.in_v = J.in_u + h->lpitch[l] * h->lh[l];
+              J.in_pitch = h->lpitch[l];
+            }
+            J.out_u = save[l * it + k];
+            J.out_v = J.out_u + h->lpitch[l] * h->lh[l];
+            J.out_pitch = h->lpitch[l];
+            next[j] = 0;
+          } else if (final_iter) {
             J.out_u = q.out;
             J.out_v = q.out + static_cast<int64_t>(q.lw[0]) * q.lh[0];
             J.out_pitch = q.lw[0];
@@ -637,6 +657,288 @@ ofv_status ofv_compute_flow_batch(ofv_handle h, int n, const ofv_image* frame0, 
   return compute_common(h, n, frame0, frame1, params, flow_init, flow_out);
 }
 
+// ------------------------------------------------------------------ adjoint
+
+namespace {
+
+constexpr int kBwPlanes = 41;  // scratch planes of level-0 size used by the backward pass
+
+size_t bw_saved_floats(const ofv_ctx* h, int levels, int iters) {
+  size_t n = 0;
+  for (int l = 0; l < levels; ++l) n += static_cast<size_t>(iters) * 2 * h->lpitch[l] * h->lh[l];
+  return n;
+}
+
+}  // namespace
+
+ofv_status ofv_reserve_backward(ofv_handle h, int max_levels, int max_iterations) {
+  if (check_handle(h) != OFV_OK) return OFV_ERR_INVALID_ARG;
+  if (max_levels < 1 || max_levels > OFV_MAX_LEVELS)
+    return fail(h, OFV_ERR_INVALID_ARG, "max_levels %d outside 1..%d", max_levels, OFV_MAX_LEVELS);
+  if (max_iterations < 1 || max_iterations > 64)
+    return fail(h, OFV_ERR_INVALID_ARG, "max_iterations %d outside 1..64", max_iterations);
+  if (h->device < 0) return fail(h, OFV_ERR_UNSUPPORTED, "validation-only handle (created with device -1)");
+  if (max_levels <= h->bw_levels && max_iterations <= h->bw_iters && h->bw) return OFV_OK;
+  DeviceGuard g(h->device);
+  const size_t plane0 = static_cast<size_t>(h->lpitch[0]) * h->lh[0];
+  const size_t floats = bw_saved_floats(h, max_levels, max_iterations) + kBwPlanes * plane0 + h->frame_bytes / 2;
+  if (h->bw) {
+    if (hipStreamSynchronize(h->stream) != hipSuccess || hipFree(h->bw) != hipSuccess)
+      return fail(h, OFV_ERR_DEVICE, "releasing the previous backward workspace failed");
+    h->bw = nullptr;
+    h->bw_bytes = 0;
+    h->bw_levels = h->bw_iters = 0;
+  }
+  if (fault_injected("alloc")) return fail(h, OFV_ERR_OUT_OF_MEMORY, "injected allocation failure");
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&h->bw), floats * sizeof(float));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    h->bw = nullptr;
+    return fail(h, OFV_ERR_OUT_OF_MEMORY, "hipMalloc(%zu bytes): %s", floats * sizeof(float), hipGetErrorString(e));
+  }
+  h->bw_bytes = floats * sizeof(float);
+  h->bw_levels = max_levels;
+  h->bw_iters = max_iterations;
+  return OFV_OK;
+}
+
+ofv_status ofv_compute_flow_backward(ofv_handle h, const ofv_image* frame0, const ofv_image* frame1,
+                                     const ofv_params* params, const float* flow_init, const float* grad_flow,
+                                     float* grad_frame0, float* grad_frame1, float* grad_flow_init) {
+  if (check_handle(h) != OFV_OK) return OFV_ERR_INVALID_ARG;
+  ofv_status r = check_params(h, params);
+  if (r != OFV_OK) return r;
+  r = check_image(h, frame0, "frame0");
+  if (r != OFV_OK) return r;
+  r = check_image(h, frame1, "frame1");
+  if (r != OFV_OK) return r;
+  if (frame0->width != frame1->width || frame0->height != frame1->height)
+    return fail(h, OFV_ERR_INVALID_ARG, "frame sizes differ");
+  if (frame0->width > h->max_w || frame0->height > h->max_h)
+    return fail(h, OFV_ERR_CAPACITY, "%dx%d exceeds the handle's %dx%d", frame0->width, frame0->height, h->max_w,
+                h->max_h);
+  if (!grad_flow) return fail(h, OFV_ERR_INVALID_ARG, "grad_flow is NULL");
+  if (grad_flow_init && !flow_init) return fail(h, OFV_ERR_INVALID_ARG, "grad_flow_init needs flow_init");
+  if (params->storage != OFV_STORE_F32) return fail(h, OFV_ERR_UNSUPPORTED, "the adjoint needs F32 storage");
+  const int W = frame0->width, H = frame0->height;
+  const uintptr_t n1 = static_cast<uintptr_t>(W) * H * sizeof(float);
+  {
+    // outputs must not overlap the inputs or each other
+    uintptr_t rng[7][2];
+    int cnt = 0;
+    uintptr_t a0, a1;
+    image_range(frame0, a0, a1);
+    rng[cnt][0] = a0, rng[cnt++][1] = a1;
+    image_range(frame1, a0, a1);
+    rng[cnt][0] = a0, rng[cnt++][1] = a1;
+    const uintptr_t gf = reinterpret_cast<uintptr_t>(grad_flow);
+    rng[cnt][0] = gf, rng[cnt++][1] = gf + 2 * n1;
+    if (flow_init) {
+      const uintptr_t fi = reinterpret_cast<uintptr_t>(flow_init);
+      rng[cnt][0] = fi, rng[cnt++][1] = fi + 2 * n1;
+    }
+    const int nin = cnt;
+    const float* outs[3] = {grad_frame0, grad_frame1, grad_flow_init};
+    const uintptr_t len[3] = {n1, n1, 2 * n1};
+    for (int i = 0; i < 3; ++i) {
+      if (!outs[i]) continue;
+      const uintptr_t o0 = reinterpret_cast<uintptr_t>(outs[i]);
+      for (int k = 0; k < cnt; ++k)
+        if (overlap(o0, o0 + len[i], rng[k][0], rng[k][1]))
+          return fail(h, OFV_ERR_INVALID_ARG, "gradient output %d overlaps %s", i,
+                      k < nin ? "an input" : "another gradient output");
+      rng[cnt][0] = o0, rng[cnt++][1] = o0 + len[i];
+    }
+  }
+  const int L = params->num_levels, IT = params->iterations;
+  if (!h->bw || L > h->bw_levels || IT > h->bw_iters)
+    return fail(h, OFV_ERR_CAPACITY, "backward workspace holds %d levels x %d iterations; call ofv_reserve_backward",
+                h->bw_levels, h->bw_iters);
+  if (fault_injected("launch")) return fail(h, OFV_ERR_DEVICE, "injected launch failure");
+  if (h->device < 0) return fail(h, OFV_ERR_UNSUPPORTED, "validation-only handle (created with device -1)");
+  DeviceGuard g(h->device);
+  hipStream_t s = h->stream;
+
+  // ---- workspace carving
+  std::vector<float*> save(static_cast<size_t>(L) * IT);
+  float* cursor = h->bw;
+  for (int l = 0; l < L; ++l)
+    for (int k = 0; k < IT; ++k) {
+      save[l * IT + k] = cursor;
+      cursor += 2 * h->lpitch[l] * h->lh[l];
+    }
+  cursor = h->bw + bw_saved_floats(h, h->bw_levels, h->bw_iters);
+  const int64_t plane0 = h->lpitch[0] * h->lh[0];
+  float* pl[kBwPlanes];
+  for (int i = 0; i < kBwPlanes; ++i) pl[i] = cursor + i * plane0;
+  float* gpyr = cursor + kBwPlanes * plane0;  // two frames, same level offsets as the pyramid slabs
+  const int sp = static_cast<int>(h->lpitch[0]);
+
+  // ---- forward, keeping every iteration's output
+  PairPlan pp{};
+  pp.f[0] = frame0;
+  pp.f[1] = frame1;
+  pp.init = flow_init;
+  pp.out = nullptr;
+  pp.slot = h->ws;
+  level_dims(W, H, L, pp.lw, pp.lh);
+  r = run_pipeline(h, 1, &pp, params, save.data());
+  if (r != OFV_OK) return r;
+
+  // image-gradient pyramids: frame f, level l at gpyr + f * slab + img_off[l]
+  const int64_t slab = static_cast<int64_t>(h->frame_bytes / 4);
+  auto gP = [&](int f, int l) { return gpyr + f * slab + h->img_off[l]; };
+  hipError_t e = launch_fill(gpyr, 2 * slab, 0.0f, s);
+  if (e != hipSuccess) return device_error(h, e, "fill");
+
+  // gradient plane pairs (u plane, v plane one plane0 apart): three in rotation
+  float* gbuf[3] = {pl[30], pl[32], pl[34]};
+  float* vup = pl[36];  // up-sampled input field of a level's first iteration (pair)
+  const float* gu = grad_flow;
+  const float* gv = grad_flow + static_cast<int64_t>(W) * H;
+  int gpitch = W;
+  int gcur = -1;  // index into gbuf, -1 = the caller's grad_flow
+
+  for (int l = 0; l < L; ++l) {
+    const int lw = pp.lw[l], lh = pp.lh[l];
+    for (int k = IT - 1; k >= 0; --k) {
+      const float* vu;
+      const float* vv;
+      int vp;
+      if (k >= 1) {
+        vu = save[l * IT + k - 1];
+        vv = vu + h->lpitch[l] * h->lh[l];
+        vp = static_cast<int>(h->lpitch[l]);
+      } else if (l < L - 1) {
+        UpsampleArgs ua{};
+        ua.in_u = save[(l + 1) * IT + IT - 1];
+        ua.in_v = ua.in_u + h->lpitch[l + 1] * h->lh[l + 1];
+        ua.in_pitch = h->lpitch[l + 1];
+        ua.cw = pp.lw[l + 1];
+        ua.ch = pp.lh[l + 1];
+        ua.out_u = vup;
+        ua.out_v = vup + plane0;
+        ua.out_pitch = sp;
+        ua.w = lw;
+        ua.h = lh;
+        e = launch_upsample(ua, s);
+        if (e != hipSuccess) return device_error(h, e, "upsample");
+        vu = vup;
+        vv = vup + plane0;
+        vp = sp;
+      } else if (flow_init) {
+        const float* b = flow_buf(h, pp, L == 1 ? 1 : (L - 1) & 1);
+        vu = b;
+        vv = b + h->lpitch[l] * h->lh[l];
+        vp = static_cast<int>(h->lpitch[l]);
+      } else {
+        e = launch_fill(vup, 2 * plane0, 0.0f, s);
+        if (e != hipSuccess) return device_error(h, e, "fill");
+        vu = vup;
+        vv = vup + plane0;
+        vp = sp;
+      }
+      const int gnext = (gcur + 1 + 3) % 3;
+      AdjLevel a{};
+      a.w = lw;
+      a.h = lh;
+      a.kr = params->kernel_radius;
+      a.reg_rel = params->reg_rel;
+      a.reg_abs = params->reg_abs;
+      a.p0 = reinterpret_cast<const float*>(img_plane(h, pp, 0, l, 4));
+      a.p1 = reinterpret_cast<const float*>(img_plane(h, pp, 1, l, 4));
+      a.ip = static_cast<int>(h->lpitch[l]);
+      a.vu = vu;
+      a.vv = vv;
+      a.vp = vp;
+      a.gu = gu;
+      a.gv = gv;
+      a.gp = gpitch;
+      a.ou = gbuf[gnext];
+      a.ov = gbuf[gnext] + plane0;
+      a.op = sp;
+      a.gP0 = gP(0, l);
+      a.gP1 = gP(1, l);
+      a.sp = sp;
+      a.S = pl[0];
+      a.T = pl[1];
+      a.GX = pl[2];
+      a.GY = pl[3];
+      a.B = pl[4];
+      for (int q = 0; q < 5; ++q) {
+        a.A[q] = pl[5 + q];
+        a.gA[q] = pl[10 + q];
+        a.tmp[q] = pl[15 + q];
+      }
+      a.gGx = pl[20];
+      a.gGy = pl[21];
+      a.gT = pl[22];
+      a.gVu = pl[23];
+      a.gVv = pl[24];
+      e = launch_adj_iteration(a, s);
+      if (e != hipSuccess) return device_error(h, e, "adjoint iteration");
+      gcur = gnext;
+      gu = gbuf[gcur];
+      gv = gbuf[gcur] + plane0;
+      gpitch = sp;
+    }
+    if (l < L - 1) {
+      // gradient w.r.t. the coarser level's last output: transpose of the up-sampling
+      const int gacc = (gcur + 1) % 3;
+      e = launch_fill(gbuf[gacc], 2 * plane0, 0.0f, s);
+      if (e != hipSuccess) return device_error(h, e, "fill");
+      e = launch_upsample_adj(gu, gv, lw, lh, sp, gbuf[gacc], gbuf[gacc] + plane0, pp.lw[l + 1], pp.lh[l + 1], sp, s);
+      if (e != hipSuccess) return device_error(h, e, "upsample adjoint");
+      gcur = gacc;
+      gu = gbuf[gcur];
+      gv = gbuf[gcur] + plane0;
+    }
+  }
+  // gu, gv: gradient w.r.t. the coarsest level's input field = the restricted initial field
+  if (grad_flow_init) {
+    float* cu = const_cast<float*>(gu);
+    for (int l = L - 1; l >= 1; --l) {
+      const bool last = (l == 1);
+      const int tgt = (gcur + 1) % 3;
+      for (int c = 0; c < 2; ++c) {
+        float* dst = last ? grad_flow_init + static_cast<int64_t>(c) * W * H : gbuf[tgt] + c * plane0;
+        e = launch_reduce_adj(cu + c * plane0, pp.lw[l], pp.lh[l], sp, dst, pp.lw[l - 1], pp.lh[l - 1],
+                              last ? W : sp, 0.5f, 0, s);
+        if (e != hipSuccess) return device_error(h, e, "restriction adjoint");
+      }
+      gcur = tgt;
+      cu = gbuf[gcur];
+    }
+    if (L == 1) {
+      for (int c = 0; c < 2; ++c) {
+        e = hipMemcpy2DAsync(grad_flow_init + static_cast<int64_t>(c) * W * H, W * sizeof(float), cu + c * plane0,
+                             sp * sizeof(float), W * sizeof(float), H, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return device_error(h, e, "copy");
+      }
+    }
+  }
+  // image-gradient pyramids: REDUCE transposed, coarse to fine
+  for (int f = 0; f < 2; ++f)
+    for (int l = L - 1; l >= 1; --l) {
+      e = launch_reduce_adj(gP(f, l), pp.lw[l], pp.lh[l], static_cast<int>(h->lpitch[l]), gP(f, l - 1), pp.lw[l - 1],
+                            pp.lh[l - 1], static_cast<int>(h->lpitch[l - 1]), 1.0f, 1, s);
+      if (e != hipSuccess) return device_error(h, e, "pyramid adjoint");
+    }
+  // normalisation (and intensity scaling) transposed
+  float* outs[2] = {grad_frame0, grad_frame1};
+  const ofv_image* fr[2] = {frame0, frame1};
+  for (int f = 0; f < 2; ++f) {
+    if (!outs[f]) continue;
+    ImageIn in{fr[f]->data, fr[f]->pitch, W, H, fr[f]->type, fr[f]->bit_depth};
+    float* scratch[8];
+    for (int i = 0; i < 8; ++i) scratch[i] = pl[5 + i];
+    e = launch_norm_adj(in, params->norm_radius, params->norm_eps, gP(f, 0), static_cast<int>(h->lpitch[0]), scratch,
+                        sp, outs[f], W, s);
+    if (e != hipSuccess) return device_error(h, e, "normalisation adjoint");
+  }
+  return OFV_OK;
+}
+
 ofv_status ofv_destroy(ofv_handle h) {
   if (!h) return OFV_OK;
   ofv_status r = OFV_OK;
@@ -644,6 +946,7 @@ ofv_status ofv_destroy(ofv_handle h) {
     DeviceGuard g(h->device);
     if (hipStreamSynchronize(h->stream) != hipSuccess) r = OFV_ERR_DEVICE;
     for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
+    if (h->bw && hipFree(h->bw) != hipSuccess) r = OFV_ERR_DEVICE;
     if (h->ws && hipFree(h->ws) != hipSuccess) r = OFV_ERR_DEVICE;
   }
   delete h;

@@ -97,4 +97,36 @@ hipError_t launch_upsample(const UpsampleArgs& a, hipStream_t s);
 // All jobs of one launch share the input-flow mode (a compile-time parameter of the kernel).
 hipError_t launch_gn(const GnArgs& a, int kr, int storage, int mode, int variant, int nblocks, hipStream_t s);
 
+// ---------------------------------------------------------------- adjoint (float32 storage)
+struct ImageIn {
+  const void* data;
+  int64_t pitch;
+  int w, h, type, bits;
+};
+
+// Planes of one backward Gauss-Newton iteration at one level.
+struct AdjLevel {
+  int w, h, kr;
+  float reg_rel, reg_abs;
+  const float* p0; const float* p1; int ip;   // level images
+  const float* vu; const float* vv; int vp;   // input field of the iteration
+  const float* gu; const float* gv; int gp;   // gradient w.r.t. the iteration's output
+  float* ou; float* ov; int op;               // gradient w.r.t. its input field (written)
+  float* gP0; float* gP1;                     // image gradients (accumulated), pitch ip
+  int sp;                                     // pitch of the scratch planes below
+  float* S; float* T; float* GX; float* GY; float* B;
+  float* A[5]; float* gA[5]; float* tmp[5];
+  float* gGx; float* gGy; float* gT; float* gVu; float* gVv;
+};
+
+hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s);
+hipError_t launch_adj_iteration(const AdjLevel& a, hipStream_t s);
+hipError_t launch_upsample_adj(const float* gfu, const float* gfv, int w, int h, int fp, float* gcu, float* gcv, int cw,
+                               int ch, int cp, hipStream_t s);
+hipError_t launch_reduce_adj(const float* gc, int cw, int ch, int cp, float* gf, int w, int h, int fp, float scale,
+                             int accumulate, hipStream_t s);
+// scratch: 8 planes of pitch sp
+hipError_t launch_norm_adj(const ImageIn& f, int nr, float eps, const float* gN, int gp, float* const* scratch, int sp,
+                           float* gF, int fp, hipStream_t s);
+
 }  // namespace ofv
