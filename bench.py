@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--kernel-launches", type=int, default=200, help="launches timed for the dominant kernel")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--suite", default=None, choices=["batch4mp", "live21mp", "adjoint512", "paper", "all"],
+                    help="run an additional measurement instead of the default workload (one JSON line each)")
     return ap.parse_args()
 
 
@@ -57,6 +59,245 @@ def workload(name):
     return pair, prm, desc, bits
 
 
+# ---------------------------------------------------------------------------
+# Additional measurements (one JSON line each): batched reduced-precision
+# 4 Mp pairs, the 21 Mp live loop with uneven batches, the adjoint's cost, and
+# the paper's own throughput setting.
+# ---------------------------------------------------------------------------
+
+def _timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def _sweep_bytes(levels, w, h, iters, s_bytes, in_bytes, npairs=1):
+    lw, lh = [w], [h]
+    for _ in range(levels - 1):
+        lw.append((lw[-1] + 1) // 2)
+        lh.append((lh[-1] + 1) // 2)
+    npx = [a * b for a, b in zip(lw, lh)]
+    b = 2 * in_bytes * npx[0] + 2 * s_bytes * npx[0]
+    b += sum(2 * s_bytes * (npx[l - 1] + npx[l]) for l in range(1, levels))
+    for l in range(levels):
+        first = (2 * s_bytes + 10) if l < levels - 1 else (2 * s_bytes + 8)
+        b += npx[l] * (first + (iters - 1) * (2 * s_bytes + 16))
+    return b * npairs
+
+
+def suite_batch4mp(args, dev):
+    """64 time-resolved 2048x2048 12-bit turbulence pairs in one call, FP16 storage."""
+    import torch
+    import paper_2509_25924_amd as ofv
+    import synth
+    from synth.gpu_render import make_pair_device
+    n_distinct, n = 8, 64
+    f0s, f1s = [], []
+    gt0 = None
+    for t in range(n_distinct):
+        flow = synth.Turbulence(seed=3, rms=2.0, dmax_cap=8.0, ref_h=256, ref_w=256, t=float(t))
+        a, b, gt = make_pair_device(2048, 2048, flow, fwhm=2.5, ppp=0.1, seed=3000 + t, bit_depth=12,
+                                    noise=0.01 * 4095, device=dev, max_disp=8.0, with_gt=(t == 0))
+        gt0 = gt if t == 0 else gt0
+        f0s.append(a)
+        f1s.append(b)
+    f0s = [f0s[i % n_distinct] for i in range(n)]
+    f1s = [f1s[i % n_distinct] for i in range(n)]
+    prm = {"num_levels": 5, "kernel_radius": 4, "iterations": 3, "norm_radius": 2}
+    outs = [torch.empty((2, 2048, 2048), dtype=torch.float32, device=dev) for _ in range(n)]
+    hb = ofv.Handle(2048, 2048, n)
+    res = {}
+    for storage in ("f16", "f32"):
+        for variant in ("tile64x16", "tile64x32", "march"):
+            hb.set_gn_variant(variant)
+            p = dict(prm, storage=storage)
+            sec = _timed(lambda: ofv.compute_flow_batch(f0s, f1s, p, bit_depth=12, outs=outs, handle=hb), 3, 1)
+            res[f"{storage}/{variant}"] = sec
+    best = min((v, k) for k, v in res.items() if k.startswith("f16"))
+    # accuracy on pair 0 of the FP16 and FP32 results against the FP64 oracle and the ground truth
+    import numpy as np
+    import oracle
+    hb.set_gn_variant("auto")
+    fr0 = f0s[0].cpu().numpy().astype(np.uint16)
+    fr1 = f1s[0].cpu().numpy().astype(np.uint16)
+    vor = oracle.compute_flow(fr0, fr1, prm, bit_depth0=12).numpy()
+    bnd = 4 * 2 ** 4
+    inner = (slice(None), slice(bnd, -bnd), slice(bnd, -bnd))
+    rms_orc = float(np.sqrt(np.mean((vor - gt0)[inner] ** 2)))
+    acc = {"pair": 0, "rms_vs_gt_oracle_px": round(rms_orc, 5)}
+    for st in ("f16", "f32"):
+        v = ofv.compute_flow_batch(f0s[:1], f1s[:1], dict(prm, storage=st), bit_depth=12, handle=hb)[0]
+        v = v.cpu().double().numpy()
+        d = np.abs(v - vor).max(axis=0)
+        rms = float(np.sqrt(np.mean((v - gt0)[inner] ** 2)))
+        acc[st] = {"max_abs_vs_oracle_px": round(float(d.max()), 5),
+                   "p99_9_abs_vs_oracle_px": round(float(np.quantile(d, 0.999)), 6),
+                   "frac_over_1e-3": float(np.mean(d > 1e-3)), "frac_over_2e-2": float(np.mean(d > 2e-2)),
+                   "rms_vs_gt_px": round(rms, 5), "rms_ratio_vs_oracle": round(rms / rms_orc, 4)}
+    # the plain FP32 single-pair path on the same pairs
+    h1 = ofv.Handle(2048, 2048, 1)
+    h1.autotune(f0s[0], f1s[0], dict(prm, storage="f32"), bit_depth=12, repeats=2)
+    out1 = outs[0]
+    sec1 = _timed(lambda: [ofv.compute_flow(f0s[i], f1s[i], dict(prm, storage="f32"), bit_depth=12, out=out1,
+                                            handle=h1) for i in range(n)], 2, 1)
+    byts = _sweep_bytes(5, 2048, 2048, 3, 2, 2, n)
+    return {"metric": "batched fields/s (64 x 2048x2048, FP16 storage)", "value": round(n / best[0], 1),
+            "unit": "fields/s", "mvectors_per_s": round(n * 2048 * 2048 / best[0] / 1e6, 1),
+            "decomposition": best[1], "seconds_per_batch": {k: round(v, 5) for k, v in res.items()},
+            "fp32_single_pair_fields_per_s": round(n / sec1, 1),
+            "speedup_vs_fp32_single_pair": round(sec1 / best[0], 2),
+            "step_algorithmic_GBps": round(byts / best[0] / 1e9, 1), "accuracy": acc,
+            "data": "synthetic: 8 distinct time steps of a 256-mode k^-5/3 field tiled to 64 pairs"}
+
+
+def suite_live21mp(args, dev):
+    """21 Mp cylinder-wake frames, uneven batch {5120x4096, 2048^2 crop, 1024^2 crop} per step, hipGraph loop."""
+    import torch
+    import paper_2509_25924_amd as ofv
+    import synth
+    from synth.gpu_render import make_pair_device
+    W, H = 5120, 4096
+    phases = 16
+    pairs = []
+    for ph in range(phases):
+        flow = synth.CylinderWake(H, W, t=200.0 * ph / phases, dmax=10.0)
+        pairs.append(make_pair_device(H, W, flow, fwhm=2.5, ppp=0.1, seed=4000 + ph, bit_depth=12,
+                                      noise=0.01 * 4095, device=dev, max_disp=10.0)[:2])
+    prm = {"num_levels": 4, "kernel_radius": 10, "iterations": 3, "norm_radius": 2}
+    hb = ofv.Handle(W, H, 3)
+    outs = [torch.empty((2, H, W), dtype=torch.float32, device=dev),
+            torch.empty((2, 2048, 2048), dtype=torch.float32, device=dev),
+            torch.empty((2, 1024, 1024), dtype=torch.float32, device=dev)]
+
+    def batch(ph, p):
+        a, b = pairs[ph]
+        f0 = [a, a[1024:3072, 1536:3584], a[1536:2560, 2048:3072]]
+        f1 = [b, b[1024:3072, 1536:3584], b[1536:2560, 2048:3072]]
+        ofv.compute_flow_batch(f0, f1, p, bit_depth=12, outs=outs, handle=hb)
+
+    res = {}
+    steps = 500
+    for storage in ("bf16", "f32"):
+        p = dict(prm, storage=storage)
+        for variant in ("tile64x32", "march"):
+            hb.set_gn_variant(variant)
+            graphs = []
+            s = torch.cuda.Stream()
+            s.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(s):
+                batch(0, p)
+            torch.cuda.current_stream().wait_stream(s)
+            for ph in range(phases):
+                g = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(g):
+                    batch(ph, p)
+                graphs.append(g)
+            hb.bind_stream()
+            k = [0]
+
+            def step():
+                graphs[k[0] % phases].replay()
+                k[0] += 1
+            res[f"{storage}/{variant}"] = _timed(step, steps, 16)
+            del graphs
+    best = min(res.values())
+    per = {k: round(1.0 / v, 1) for k, v in res.items()}
+    vec = W * H + 2048 * 2048 + 1024 * 1024
+    return {"metric": "live steps/s (5120x4096 + 2048^2 + 1024^2 uneven batch per step, hipGraph)",
+            "value": round(1.0 / best, 1), "unit": "steps/s", "steps": steps,
+            "gvectors_per_s": round(vec / best / 1e9, 3), "steps_per_s_by_config": per,
+            "fields_per_s_each_size": round(1.0 / best, 1),
+            "data": "synthetic: 16 phases of a cylinder wake (potential flow + Lamb-Oseen street, max 10 px)"}
+
+
+def suite_adjoint512(args, dev):
+    """Backward/forward cost: 16 float 512x512 pairs, loss sum |V - V_gt|^2."""
+    import torch
+    import paper_2509_25924_amd as ofv
+    import synth
+    n = 16
+    pairs = [synth.config_adjoint_512(i) for i in range(n)]
+    prm = pairs[0][1]
+    f0 = [torch.from_numpy(p.frame0).to(dev) for p, _ in pairs]
+    f1 = [torch.from_numpy(p.frame1).to(dev) for p, _ in pairs]
+    gt = [torch.from_numpy(p.gt.astype("float32")).to(dev) for p, _ in pairs]
+    h = ofv.Handle(512, 512, n)
+    h.reserve_backward(prm["num_levels"], prm["iterations"])
+    outs = [torch.empty((2, 512, 512), dtype=torch.float32, device=dev) for _ in range(n)]
+    fwd = _timed(lambda: ofv.compute_flow_batch(f0, f1, prm, outs=outs, handle=h), 20, 3)
+    fwd1 = _timed(lambda: [ofv.compute_flow(f0[i], f1[i], prm, out=outs[i], handle=h) for i in range(n)], 10, 2)
+    grads = [(2 * (outs[i] - gt[i])).contiguous() for i in range(n)]
+    bwd = _timed(lambda: [ofv.compute_flow_backward(f0[i], f1[i], prm, grads[i], handle=h) for i in range(n)], 5, 1)
+    L, it = prm["num_levels"], prm["iterations"]
+    npx = sum((512 >> l) ** 2 for l in range(L))
+    saved = it * 8 * npx            # one output field per iteration
+    store_all = it * 48 * npx       # S, T, Gx, Gy, b, five products, u, v per iteration
+    return {"metric": "bwd/fwd time ratio (16 x 512x512 float pairs)", "value": round(bwd / fwd1, 2), "unit": "ratio",
+            "forward_ms_batch": round(fwd * 1e3, 3), "forward_ms_16_single": round(fwd1 * 1e3, 3),
+            "backward_ms_16": round(bwd * 1e3, 3), "bwd_over_batched_fwd": round(bwd / fwd, 2),
+            "saved_bytes_per_pair_recompute": saved, "bytes_per_pair_store_all_estimate": store_all,
+            "data": "synthetic Rankine / turbulence float frames"}
+
+
+def suite_paper(args, dev):
+    """The paper's throughput setting: 8-bit pairs, NR 2, KR 10, IT 3, PSL 0..2, sizes 1, 4 and 21 Mp."""
+    import torch
+    import paper_2509_25924_amd as ofv
+    import synth
+    from synth.gpu_render import make_pair_device
+    rows = []
+    for (w, h) in ((1024, 1024), (2048, 2048), (5120, 4096)):
+        pairs = []
+        for i in range(10 if w * h <= 4 << 20 else 4):
+            flow = synth.Translation(1.3, -0.7, shear=0.002, y_ref=h / 2)
+            pairs.append(make_pair_device(h, w, flow, fwhm=2.5, ppp=0.1, seed=5000 + i, bit_depth=8, noise=2.0,
+                                          device=dev, max_disp=3.0)[:2])
+        hd = ofv.Handle(w, h, 1)
+        out = torch.empty((2, h, w), dtype=torch.float32, device=dev)
+        for levels in (1, 2, 3):
+            for storage in ("f32", "bf16"):
+                prm = {"num_levels": levels, "kernel_radius": 10, "iterations": 3, "norm_radius": 2,
+                       "storage": storage}
+                hd.autotune(pairs[0][0], pairs[0][1], prm, bit_depth=8, repeats=2)
+                k = [0]
+
+                def one():
+                    a, b = pairs[k[0] % len(pairs)]
+                    ofv.compute_flow(a, b, prm, bit_depth=8, out=out, handle=hd)
+                    k[0] += 1
+                sec = _timed(one, 40 if w * h > 4 << 20 else 200, 5)
+                rows.append({"size": f"{w}x{h}", "psl": levels - 1, "storage": storage,
+                             "fields_per_s": round(1.0 / sec, 1), "mvectors_per_s": round(w * h / sec / 1e6, 1)})
+        hd.close()
+    return {"metric": "fields/s at the paper's throughput setting (NR 2, KR 10, IT 3)", "rows": rows,
+            "paper_rtx5090_offline_fields_per_s": {"1Mp": [1100, 1800], "4Mp": [400, 500], "21Mp": [80, 99]},
+            "data": "synthetic 8-bit particle pairs (translation + shear), pre-loaded in device memory"}
+
+
+def run_suite(args):
+    import torch
+    import paper_2509_25924_amd as ofv
+    from paper_2509_25924_amd import _build
+    if not _build.built():
+        _build.build()
+    ofv.load()
+    dev = torch.device("cuda:0")
+    names = ["batch4mp", "live21mp", "adjoint512", "paper"] if args.suite == "all" else [args.suite]
+    fns = {"batch4mp": suite_batch4mp, "live21mp": suite_live21mp, "adjoint512": suite_adjoint512,
+           "paper": suite_paper}
+    for nm in names:
+        print(f"# suite {nm} ...", file=sys.stderr, flush=True)
+        r = fns[nm](args, dev)
+        r["suite"] = nm
+        print(json.dumps(r), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -64,6 +305,9 @@ def main():
         print("bench.py measures one GPU only: this estimator build has no multi-GPU path "
               "(independent pairs shard across GPUs with no communication); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.suite:
+        run_suite(args)
+        return
 
     import numpy as np
     import torch

@@ -156,7 +156,8 @@ ofv_status ofv_compute_flow_backward(ofv_handle h, const ofv_image* frame0, cons
 /* Work decompositions of the fused Gauss-Newton kernel, chosen per pyramid
  * level and input-flow mode.  All give the same results up to float32
  * rounding order (parity with the FP64 reference holds for each). */
-#define OFV_GN_AUTO (-1)      /* tuned table if it has an entry, else OFV_GN_TILE_64x16 */
+#define OFV_GN_AUTO (-1)      /* tuned table entry if any, else the march for launches of >= 3 Mi pixels,
+                                 OFV_GN_TILE_64x16 below */
 #define OFV_GN_MARCH 0        /* 256-column strips marching down tile_h rows */
 #define OFV_GN_TILE_64x32 1   /* 64 x 32 output tiles, three LDS phases */
 #define OFV_GN_TILE_64x16 2   /* 64 x 16 output tiles, three LDS phases */

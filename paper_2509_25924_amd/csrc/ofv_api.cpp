@@ -208,9 +208,11 @@ int choose_tile_h(int64_t strips_total, int64_t rows_max) {
 
 // Work decomposition of the Gauss-Newton kernel for one launch group:
 // OFV_GN_VARIANT in the environment, then a choice forced on the handle, then
-// the handle's tuned table, then the default (64 x 16 tiles).
-void pick_gn(const ofv_ctx* h, const ofv_ctx::TuneKey& key, int64_t strips, int64_t rows_max, int& variant,
-             int& tile_h) {
+// the handle's tuned table, then the default: the strip march once the launch
+// covers enough pixels to give every CU several strips (measured on MI355X:
+// march ahead from about 4 Mp per launch), 64 x 16 tiles below that.
+void pick_gn(const ofv_ctx* h, const ofv_ctx::TuneKey& key, int64_t strips, int64_t rows_max, int64_t pixels,
+             int& variant, int& tile_h) {
   tile_h = choose_tile_h(strips, rows_max);
   if (const char* e = std::getenv("OFV_GN_VARIANT")) {
     if (!std::strcmp(e, "march")) { variant = GN_MARCH; return; }
@@ -228,7 +230,7 @@ void pick_gn(const ofv_ctx* h, const ofv_ctx::TuneKey& key, int64_t strips, int6
     tile_h = it->second.tile_h;
     return;
   }
-  variant = GN_TILE_64x16;
+  variant = pixels >= (int64_t{3} << 20) ? GN_MARCH : GN_TILE_64x16;
 }
 
 hipEvent_t next_event(ofv_ctx* h) {
@@ -392,7 +394,9 @@ ofv_status run_pipeline(ofv_ctx* h, int n, PairPlan* pp, const ofv_params* p, fl
           key.hgt = std::max(key.hgt, pp[j].lh[l]);
         }
         int variant = 0, tile_h = 0, tw = 0, th = 0;
-        pick_gn(h, key, strips, rows_max, variant, tile_h);
+        int64_t pixels = 0;
+        for (int j : group) pixels += static_cast<int64_t>(pp[j].lw[l]) * pp[j].lh[l];
+        pick_gn(h, key, strips, rows_max, pixels, variant, tile_h);
         gn_tile_dims(variant, kr, tile_h, tw, th);
         ga.tile_h = tile_h;
         auto fill = [&](int gi, GnJob& J) {
@@ -1199,7 +1203,7 @@ ofv_status ofv_stage_gn_iteration(ofv_handle h, int storage, const void* p0, con
   const int tx = gn_tile_w(kernel_radius);
   int variant = 0, tw = 0, th = 0;
   pick_gn(h, ofv_ctx::TuneKey{kernel_radius, storage, mode, width, height, 1}, (width + tx - 1) / tx, height,
-          variant, ga.tile_h);
+          static_cast<int64_t>(width) * height, variant, ga.tile_h);
   gn_tile_dims(variant, kernel_radius, ga.tile_h, tw, th);
   GnJob& J = ga.job[0];
   J.p0 = p0;

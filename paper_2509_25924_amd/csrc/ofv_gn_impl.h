@@ -313,16 +313,11 @@ __global__ __launch_bounds__(kGnThreads) void gn_kernel(const GnArgs a) {
             // V(m) of the output row entered the ring KR steps ago
             const float um = ru[(k + KR + 1) % NWIN];
             const float vm = rv[(k + KR + 1) % NWIN];
-            const float sxx = acc[0], sxy = acc[1], syy = acc[2], sxb = acc[3], syb = acc[4];
-            const float lam = a.reg_rel * (sxx + syy) + a.reg_abs;
-            const float aa = sxx + lam;
-            const float dd = syy + lam;
-            const float det = aa * dd - sxy * sxy;
-            const float r1 = sxb + lam * um;
-            const float r2 = syb + lam * vm;
+            float un, vn;
+            solve2x2(acc[0], acc[1], acc[2], acc[3], acc[4], um, vm, a.reg_rel, a.reg_abs, un, vn);
             const int64_t o = static_cast<int64_t>(orow) * J.out_pitch + col;
-            J.out_u[o] = (dd * r1 - sxy * r2) / det;
-            J.out_v[o] = (aa * r2 - sxy * r1) / det;
+            J.out_u[o] = un;
+            J.out_v[o] = vn;
           }
           // the row leaving the window next step sits in slot (i - 2KR) mod NWIN
 #pragma unroll

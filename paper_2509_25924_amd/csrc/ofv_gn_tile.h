@@ -240,16 +240,11 @@ __global__ __launch_bounds__(256) void gn_tile_kernel(const GnArgs a) {
             const int o = (oy + KR + 1) * LP + (j + KR + 1);
             const float um = sU[o];
             const float vm = sV[o];
-            const float sxx = acc[0], sxy = acc[1], syy = acc[2], sxb = acc[3], syb = acc[4];
-            const float lam = a.reg_rel * (sxx + syy) + a.reg_abs;
-            const float aa = sxx + lam;
-            const float dd = syy + lam;
-            const float inv = 1.0f / (aa * dd - sxy * sxy);
-            const float r1 = sxb + lam * um;
-            const float r2 = syb + lam * vm;
+            float un, vn;
+            solve2x2(acc[0], acc[1], acc[2], acc[3], acc[4], um, vm, a.reg_rel, a.reg_abs, un, vn);
             const int64_t oo = static_cast<int64_t>(gy) * J.out_pitch + gx;
-            J.out_u[oo] = (dd * r1 - sxy * r2) * inv;
-            J.out_v[oo] = (aa * r2 - sxy * r1) * inv;
+            J.out_u[oo] = un;
+            J.out_v[oo] = vn;
           }
         }
       }

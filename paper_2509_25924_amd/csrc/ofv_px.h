@@ -69,6 +69,34 @@ __device__ __forceinline__ float bilinear(const T* __restrict__ p, int64_t pitch
   return top + ay * (bot - top);
 }
 
+// Damped 2x2 solve of one Gauss-Newton step (Eq. of_symmetric linearised):
+//   (A + lam I) V' = c + lam V(m),  lam = reg_rel (Sxx + Syy) + reg_abs,
+// by Cramer's rule in float32.  Where the system is ill-conditioned
+// (q = 4 det / trace^2 < 1e-2) the float32 determinant has lost leading
+// digits to cancellation; there the determinant and the solution are
+// recomputed in float64 from the same float32 sums (products of two floats
+// are exact in double, so det is then exact up to one rounding).
+__device__ __forceinline__ void solve2x2(float sxx, float sxy, float syy, float sxb, float syb, float um, float vm,
+                                         float reg_rel, float reg_abs, float& u, float& v) {
+  const float lam = reg_rel * (sxx + syy) + reg_abs;
+  const float aa = sxx + lam;
+  const float dd = syy + lam;
+  const float r1 = sxb + lam * um;
+  const float r2 = syb + lam * vm;
+  const float det = aa * dd - sxy * sxy;
+  const float tr = aa + dd;
+  if (det >= 2.5e-3f * tr * tr) {
+    const float inv = 1.0f / det;
+    u = (dd * r1 - sxy * r2) * inv;
+    v = (aa * r2 - sxy * r1) * inv;
+  } else {
+    const double a = aa, d = dd, b = sxy, x1 = r1, x2 = r2;
+    const double dt = a * d - b * b;
+    u = static_cast<float>((d * x1 - b * x2) / dt);
+    v = static_cast<float>((a * x2 - b * x1) / dt);
+  }
+}
+
 // Workgroup -> job lookup: jobs are laid out consecutively in the 1-D grid.
 template <typename Args>
 __device__ __forceinline__ int find_job(const Args& a, int block) {
