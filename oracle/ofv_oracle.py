@@ -37,6 +37,12 @@ restated where it is used):
  R8  Up-sampling is V_fine(X, Y) = 2 * bilinear(V_coarse, X / 2, Y / 2).
  R9  The same IT at every level; V = 0 at the coarsest level, or the
      optional initial field restricted by REDUCE / 2 per level.
+
+Besides the method itself, compute_flow can round every image plane (the
+normalised frames and each REDUCE output) to a storage type, leaving all
+arithmetic in float64.  That is not part of the paper: it gives the error
+that storing the planes in float32 / float16 / bfloat16 causes by itself,
+the floor against which a reduced-precision implementation is judged.
 """
 from __future__ import annotations
 
@@ -140,10 +146,21 @@ def reduce(p: torch.Tensor) -> torch.Tensor:
     return out
 
 
-def pyramid(p0: torch.Tensor, levels: int) -> List[torch.Tensor]:
-    out = [p0]
+_PLANE_TYPES = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}
+
+
+def round_plane(p: torch.Tensor, plane_round: Optional[str]) -> torch.Tensor:
+    """p rounded to nearest in the storage type (ties to even), back in float64."""
+    if plane_round is None:
+        return p
+    return p.to(_PLANE_TYPES[plane_round]).to(DT)
+
+
+def pyramid(p0: torch.Tensor, levels: int, plane_round: Optional[str] = None) -> List[torch.Tensor]:
+    """Levels 0..levels-1; with plane_round each REDUCE reads the rounded finer level."""
+    out = [round_plane(p0, plane_round)]
     for _ in range(levels - 1):
-        out.append(reduce(out[-1]))
+        out.append(round_plane(reduce(out[-1]), plane_round))
     return out
 
 
@@ -271,13 +288,15 @@ class Trace:
 
 
 def compute_flow(frame0, frame1, params: Dict, bit_depth0: int = 8, bit_depth1: Optional[int] = None,
-                 flow_init=None, trace: Optional[Trace] = None):
+                 flow_init=None, trace: Optional[Trace] = None, plane_round: Optional[str] = None):
     """Dense displacement field (u, v) in px/frame at full resolution.
 
     params: num_levels (PSL + 1), kernel_radius (KR), iterations (IT),
     norm_radius (NR), and optionally norm_eps, reg_rel, reg_abs.
     Returns a float64 tensor [2, H, W]; u along +x (columns), v along +y
     (rows), mapping frame0 to frame1, defined at the midpoint.
+    plane_round ("f32", "f16", "bf16" or None) rounds every image plane to
+    that storage type (not part of the method; see the module docstring).
     """
     if bit_depth1 is None:
         bit_depth1 = bit_depth0
@@ -291,8 +310,8 @@ def compute_flow(frame0, frame1, params: Dict, bit_depth0: int = 8, bit_depth1: 
     n0 = normalize(intensity(frame0, bit_depth0), nr, p["norm_eps"])
     n1 = normalize(intensity(frame1, bit_depth1), nr, p["norm_eps"])
     # step 2: pyramids
-    pyr0 = pyramid(n0, levels)
-    pyr1 = pyramid(n1, levels)
+    pyr0 = pyramid(n0, levels, plane_round)
+    pyr1 = pyramid(n1, levels, plane_round)
     if trace is not None:
         trace.levels0, trace.levels1 = pyr0, pyr1
     # initial flow at the coarsest level

@@ -346,6 +346,37 @@ def test_reduced_precision_storage_gate(ofv, storage):
     assert rms_gpu <= 1.05 * rms_orc
 
 
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_reduced_precision_turbulence_vs_storage_floor(ofv, storage):
+    """1024x1024 12-bit turbulence pair (the batched workload's field and
+    parameters).  Rounding the planes to the storage type already moves a few
+    ill-conditioned pixels of the FP64 oracle by more than 2e-2 px; the GPU
+    path may not do worse than twice that floor, and its RMS error against
+    the ground truth stays within 5 % of the oracle's."""
+    say("turbulence storage floor", storage)
+    from synth.gpu_render import make_pair_device
+    flow = synth.Turbulence(seed=3, rms=2.0, dmax_cap=8.0, ref_h=256, ref_w=256, t=0.0)
+    a, b, gt = make_pair_device(1024, 1024, flow, fwhm=2.5, ppp=0.1, seed=3000, bit_depth=12,
+                                noise=0.01 * 4095, device=torch.device("cuda"), max_disp=8.0, with_gt=True)
+    prm = {"num_levels": 5, "kernel_radius": 4, "iterations": 3, "norm_radius": 2}
+    f0 = a.cpu().numpy().astype(np.uint16)
+    f1 = b.cpu().numpy().astype(np.uint16)
+    ref = oracle.compute_flow(f0, f1, prm, bit_depth0=12).numpy()
+    floor = oracle.compute_flow(f0, f1, prm, bit_depth0=12, plane_round=storage).numpy()
+    got = ofv.compute_flow(a, b, dict(prm, storage=storage), bit_depth=12).cpu().double().numpy()
+    d_floor = np.abs(floor - ref).max(axis=0)
+    d_gpu = np.abs(got - ref).max(axis=0)
+    f_floor = float(np.mean(d_floor > 2e-2))
+    f_gpu = float(np.mean(d_gpu > 2e-2))
+    bnd = 64
+    rms = lambda v: float(np.sqrt(np.mean((v - gt)[:, bnd:-bnd, bnd:-bnd] ** 2)))
+    say(f"  frac > 2e-2: gpu {f_gpu:.2e} floor {f_floor:.2e}; p99.9 gpu {np.quantile(d_gpu, 0.999):.3e} "
+        f"floor {np.quantile(d_floor, 0.999):.3e}; rms gpu {rms(got):.4f} oracle {rms(ref):.4f}")
+    assert f_gpu <= 2 * f_floor + 1e-4
+    assert np.quantile(d_gpu, 0.999) <= 2 * np.quantile(d_floor, 0.999) + 1e-3
+    assert rms(got) <= 1.05 * rms(ref)
+
+
 def test_graph_replay_matches_eager(ofv):
     """The compute path captures into a hipGraph (no allocation, no sync);
     each replay, with eager work between replays, reproduces the eager result."""

@@ -377,3 +377,33 @@ def test_endpoint_error_definition():
     g[0, 0, 0], g[1, 0, 0] = 3.0, 4.0
     e = oracle.endpoint_error(f, g).numpy()
     assert e[0, 0] == 5.0 and e[1, 1] == 0.0
+
+
+# ---------------------------------------------------------------- storage rounding (precision floor, not the method)
+
+@pytest.mark.parametrize("kind,ulp", [("f16", 2.0 ** -10), ("bf16", 2.0 ** -7)])
+def test_round_plane_is_round_to_nearest_even(kind, ulp):
+    # values around 1 where the ulp is known: halfway cases go to the even neighbour
+    x = T([1.0, 1.0 + ulp / 2, 1.0 + 1.5 * ulp, 1.0 + 0.75 * ulp, -(1.0 + ulp / 2), 1.0 + 0.25 * ulp])
+    want = [1.0, 1.0, 1.0 + 2 * ulp, 1.0 + ulp, -1.0, 1.0]
+    assert oracle.ofv_oracle.round_plane(x, kind).tolist() == want
+    assert oracle.ofv_oracle.round_plane(x, None) is x
+
+
+def test_plane_rounding_applies_to_every_level():
+    pair, prm = synth.config_rankine_256()
+    tr = oracle.Trace()
+    oracle.compute_flow(pair.frame0, pair.frame1, dict(prm, iterations=1), bit_depth0=8, trace=tr, plane_round="f16")
+    for lev, p in enumerate(tr.levels0):
+        assert torch.equal(p.half().double(), p), lev          # representable in binary16
+        if lev:                                                # REDUCE read the rounded finer level
+            assert torch.equal(oracle.reduce(tr.levels0[lev - 1]).half().double(), p), lev
+
+
+def test_float32_planes_stay_within_fp32_tolerance():
+    # storing the planes in binary32 moves the result by far less than the
+    # 1e-3 px that the float32 implementation is held to
+    pair, prm = synth.config_rankine_256()
+    ref = oracle.compute_flow(pair.frame0, pair.frame1, prm, bit_depth0=8)
+    got = oracle.compute_flow(pair.frame0, pair.frame1, prm, bit_depth0=8, plane_round="f32")
+    assert 0 < torch.max(torch.abs(got - ref)).item() < 1e-4
