@@ -95,7 +95,10 @@ void ofv_default_params(ofv_params* p);
  * `max_batch` pairs of up to max_width x max_height pixels.  `stream` is a
  * hipStream_t (NULL = the default stream) on which all work is enqueued.
  * Allocates the workspace (pyramids and flow ping-pong buffers, about
- * 8/3 * 4 + 16 bytes per pixel per pair).  On error *out is set to NULL. */
+ * 8/3 * 4 + 16 bytes per pixel per pair).  A float plane of the maximum
+ * size must stay below 2 GiB and its row pitch (max_width rounded up to 64)
+ * below 2^24 elements, else OFV_ERR_UNSUPPORTED.  On error *out is set to
+ * NULL. */
 ofv_status ofv_create(ofv_handle* out, int device, int max_width, int max_height, int max_batch,
                       void* stream);
 
@@ -122,7 +125,10 @@ ofv_status ofv_compute_flow_ex(ofv_handle h, const ofv_image* frame0, const ofv_
  * runs as one launch over all pairs (per pyramid level and iteration).
  * frame0, frame1 and flow_out are arrays of n entries; flow_init is NULL or
  * an array of n pointers (entries may be NULL).  1 <= n <= max_batch.
- * Results equal n separate ofv_compute_flow_ex calls. */
+ * Results equal n separate ofv_compute_flow_ex calls bit for bit when every
+ * level runs the same work decomposition in both (see ofv_set_gn_variant;
+ * the default choice depends on the pixels of the whole launch); other
+ * decompositions differ from them by float32 rounding only. */
 ofv_status ofv_compute_flow_batch(ofv_handle h, int n, const ofv_image* frame0, const ofv_image* frame1,
                                   const ofv_params* params, const float* const* flow_init,
                                   float* const* flow_out);

@@ -26,6 +26,10 @@ using namespace ofv;
 namespace {
 
 constexpr int64_t kPitchAlign = 64;      // elements; 256 B rows for float32 planes
+// Kernels address a plane with 32-bit byte offsets and 24-bit row products:
+// every plane stays below 2 GiB and every pitch below 2^24 elements.
+constexpr int64_t kMaxPlaneBytes = int64_t{1} << 31;
+constexpr int64_t kMaxPitch = int64_t{1} << 24;
 constexpr size_t kSlabAlign = 256;        // bytes
 
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
@@ -210,10 +214,15 @@ int choose_tile_h(int64_t strips_total, int64_t rows_max) {
 // OFV_GN_VARIANT in the environment, then a choice forced on the handle, then
 // the handle's tuned table, then the default: the strip march once the launch
 // covers enough pixels to give every CU several strips (measured on MI355X:
-// march ahead from about 4 Mp per launch), 64 x 16 tiles below that.
+// march ahead from about 4 Mp per launch), 64 x 16 tiles below that.  Levels
+// one pixel wide or high always take the march.
 void pick_gn(const ofv_ctx* h, const ofv_ctx::TuneKey& key, int64_t strips, int64_t rows_max, int64_t pixels,
-             int& variant, int& tile_h) {
+             bool degenerate, int& variant, int& tile_h) {
   tile_h = choose_tile_h(strips, rows_max);
+  if (degenerate) {  // a level of one row or one column: the tile kernels need 2 x 2 pixels
+    variant = GN_MARCH;
+    return;
+  }
   if (const char* e = std::getenv("OFV_GN_VARIANT")) {
     if (!std::strcmp(e, "march")) { variant = GN_MARCH; return; }
     if (!std::strcmp(e, "tile32")) { variant = GN_TILE_64x32; return; }
@@ -383,10 +392,14 @@ ofv_status run_pipeline(ofv_ctx* h, int n, PairPlan* pp, const ofv_params* p, fl
         if (k == 0 && l < L - 1) return static_cast<int>(FLOW_UPSAMPLE);
         return static_cast<int>(cur[j] < 0 ? FLOW_ZERO : FLOW_DIRECT);
       };
-      for (int mode = FLOW_ZERO; mode <= FLOW_UPSAMPLE; ++mode) {
+      // levels thinner than 2 pixels go to the march in a launch of their own,
+      // so the decomposition of every other pair does not depend on them
+      for (int gk = 0; gk < 2 * (FLOW_UPSAMPLE + 1); ++gk) {
+        const int mode = gk >> 1;
+        const bool thin = gk & 1;
         std::vector<int> group;
         for (int j = 0; j < n; ++j)
-          if (mode_of(j) == mode) group.push_back(j);
+          if (mode_of(j) == mode && (pp[j].lw[l] < 2 || pp[j].lh[l] < 2) == thin) group.push_back(j);
         if (group.empty()) continue;
         ofv_ctx::TuneKey key{kr, st, mode, 0, 0, static_cast<int>(group.size())};
         for (int j : group) {
@@ -396,7 +409,7 @@ ofv_status run_pipeline(ofv_ctx* h, int n, PairPlan* pp, const ofv_params* p, fl
         int variant = 0, tile_h = 0, tw = 0, th = 0;
         int64_t pixels = 0;
         for (int j : group) pixels += static_cast<int64_t>(pp[j].lw[l]) * pp[j].lh[l];
-        pick_gn(h, key, strips, rows_max, pixels, variant, tile_h);
+        pick_gn(h, key, strips, rows_max, pixels, thin, variant, tile_h);
         gn_tile_dims(variant, kr, tile_h, tw, th);
         ga.tile_h = tile_h;
         auto fill = [&](int gi, GnJob& J) {
@@ -589,6 +602,9 @@ ofv_status ofv_create(ofv_handle* out, int device, int max_width, int max_height
     return fail(nullptr, OFV_ERR_INVALID_ARG, "max sizes must be >= 1 (got %dx%d, batch %d)", max_width, max_height,
                 max_batch);
   if (device < -1) return fail(nullptr, OFV_ERR_INVALID_ARG, "device %d < -1", device);
+  if (round_up(max_width, kPitchAlign) >= kMaxPitch ||
+      static_cast<int64_t>(round_up(max_width, kPitchAlign)) * max_height * 4 >= kMaxPlaneBytes)
+    return fail(nullptr, OFV_ERR_UNSUPPORTED, "a %dx%d float plane would reach 2 GiB", max_width, max_height);
   ofv_ctx* h = new (std::nothrow) ofv_ctx();
   if (!h) return fail(nullptr, OFV_ERR_OUT_OF_MEMORY, "host allocation failed");
   h->device = device;
@@ -1173,6 +1189,9 @@ ofv_status ofv_stage_gn_iteration(ofv_handle h, int storage, const void* p0, con
   if (!p0 || !p1 || !flow_out) return fail(h, OFV_ERR_INVALID_ARG, "p0, p1 or flow_out is NULL");
   if (width < 1 || height < 1) return fail(h, OFV_ERR_INVALID_ARG, "size %dx%d invalid", width, height);
   if (img_pitch < width || out_pitch < width) return fail(h, OFV_ERR_INVALID_ARG, "pitch too small");
+  if (img_pitch >= kMaxPitch || out_pitch >= kMaxPitch || img_pitch * height * 4 >= kMaxPlaneBytes ||
+      out_pitch * height * 4 >= kMaxPlaneBytes)
+    return fail(h, OFV_ERR_UNSUPPORTED, "image or flow plane of 2 GiB or more");
   if (kernel_radius < 1) return fail(h, OFV_ERR_INVALID_ARG, "kernel_radius < 1");
   if (kernel_radius > OFV_MAX_KERNEL_RADIUS) return fail(h, OFV_ERR_UNSUPPORTED, "kernel_radius too large");
   if (!std::isfinite(reg_rel) || reg_rel < 0 || !std::isfinite(reg_abs) || reg_abs < 0)
@@ -1187,6 +1206,8 @@ ofv_status ofv_stage_gn_iteration(ofv_handle h, int storage, const void* p0, con
       ih = in_height;
     }
     if (in_pitch < iw) return fail(h, OFV_ERR_INVALID_ARG, "in_pitch too small");
+    if (in_pitch >= kMaxPitch || in_pitch * ih * 4 >= kMaxPlaneBytes)
+      return fail(h, OFV_ERR_UNSUPPORTED, "flow_in plane of 2 GiB or more, or pitch of 2^24 or more");
     const uintptr_t a0 = reinterpret_cast<uintptr_t>(flow_in);
     const uintptr_t a1 = a0 + (2ull * ih * in_pitch) * sizeof(float);
     const uintptr_t b0 = reinterpret_cast<uintptr_t>(flow_out);
@@ -1203,7 +1224,7 @@ ofv_status ofv_stage_gn_iteration(ofv_handle h, int storage, const void* p0, con
   const int tx = gn_tile_w(kernel_radius);
   int variant = 0, tw = 0, th = 0;
   pick_gn(h, ofv_ctx::TuneKey{kernel_radius, storage, mode, width, height, 1}, (width + tx - 1) / tx, height,
-          static_cast<int64_t>(width) * height, variant, ga.tile_h);
+          static_cast<int64_t>(width) * height, width < 2 || height < 2, variant, ga.tile_h);
   gn_tile_dims(variant, kernel_radius, ga.tile_h, tw, th);
   GnJob& J = ga.job[0];
   J.p0 = p0;

@@ -4,7 +4,7 @@
 // ofv_gn_impl.h; a different work decomposition with far more independent
 // work per lane, for levels too small to give the march enough workgroups.
 //
-// A 256-lane workgroup computes a TX x TY tile of the new flow in three
+// A workgroup of NT lanes (256 or 512) computes a TX x TY tile of the new flow in three
 // phases separated by barriers:
 //  A. every pixel of the tile plus a (KR+1)-pixel halo, evaluated at its
 //     coordinates clamped into the level: input flow (loaded or up-sampled),
@@ -35,34 +35,54 @@ struct TileGeom {
   static constexpr int LDS_FLOATS = 4 * LP * EY + 5 * PY * HP;
 };
 
-// Bilinear sample at (x, y) clamped into a w x h plane; taps (ix, ix + sx)
-// with ix <= w - 2 (sx = 0 for single-column planes), likewise rows.
-template <typename TS>
-__device__ __forceinline__ float bil_clamped(const TS* __restrict__ p, int pitch, float wm1, float hm1, float wm2,
-                                             float hm2, int sx, int sy, float x, float y) {
+// Bilinear sample at (x, y) clamped into a w x h plane, split into the
+// address set-up and the combination of the four taps: taps (ix, ix + sx)
+// x (iy, iy + sy) with ix <= w - 2 (sx = 0 for single-column planes),
+// likewise rows; (ax, ay) are the weights of the second tap of each pair.
+struct BilTap {
+  uint32_t i;  // element index of tap (ix, iy)
+  float ax, ay;
+};
+
+__device__ __forceinline__ BilTap bil_setup(float x, float y, float wm1, float hm1, float wm2, float hm2,
+                                            uint32_t pitch) {
   // median-of-three clamps (a NaN coordinate ends as tap 0 via the integer conversion)
   x = __builtin_amdgcn_fmed3f(x, 0.0f, wm1);
   y = __builtin_amdgcn_fmed3f(y, 0.0f, hm1);
   const float xf = __builtin_amdgcn_fmed3f(floorf(x), 0.0f, wm2);
   const float yf = __builtin_amdgcn_fmed3f(floorf(y), 0.0f, hm2);
-  const float ax = x - xf;
-  const float ay = y - yf;
-  const TS* r0 = p + (static_cast<int>(yf) * pitch + static_cast<int>(xf));
-  const float p00 = Px<TS>::ld(r0);
-  const float p01 = Px<TS>::ld(r0 + sx);
-  const float p10 = Px<TS>::ld(r0 + sy);
-  const float p11 = Px<TS>::ld(r0 + sy + sx);
+  BilTap t;
+  t.ax = x - xf;
+  t.ay = y - yf;
+  // plane widths and heights are below 2^24 (checked on the host)
+  t.i = __umul24(static_cast<uint32_t>(yf), pitch) + static_cast<uint32_t>(xf);
+  return t;
+}
+
+__device__ __forceinline__ float bil_combine(float p00, float p01, float p10, float p11, float ax, float ay) {
   const float top = fmaf(ax, p01 - p00, p00);
   const float bot = fmaf(ax, p11 - p10, p10);
   return fmaf(ay, bot - top, top);
 }
 
-template <int KR, int MODE, typename TS, int TX, int TY, int SL, int SLV>
-__global__ __launch_bounds__(256) void gn_tile_kernel(const GnArgs a) {
+// Waves per SIMD that the LDS of one NT-lane workgroup leaves room for
+// (160 KiB per compute unit, NT / 256 waves of each workgroup per SIMD):
+// the register budget of the kernel is sized for that occupancy.
+template <int KR, int TX, int TY, int NT>
+struct TileOcc {
+  static constexpr int lds = 4 * TileGeom<KR, TX, TY>::LDS_FLOATS;
+  static constexpr int fit = (163840 / lds) * (NT / 256);
+  static constexpr int value = fit < 1 ? 1 : (fit > 8 ? 8 : fit);
+};
+
+template <int KR, int MODE, typename TS, int TX, int TY, int SL, int SLV, int NT>
+__global__ __launch_bounds__(NT)
+__attribute__((amdgpu_waves_per_eu(TileOcc<KR, TX, TY, NT>::value, TileOcc<KR, TX, TY, NT>::value)))
+void gn_tile_kernel(const GnArgs a) {
   using G = TileGeom<KR, TX, TY>;
   constexpr int NWIN = G::NWIN, EX = G::EX, LP = G::LP, PY = G::PY, HP = G::HP, NE = G::NE;
   static_assert(TX % SL == 0 && TY % SLV == 0, "segments must tile the output");
-  static_assert(TX * (TY / SLV) <= 256, "phase C items");
+  static_assert(TX * (TY / SLV) <= NT, "phase C items");
   extern __shared__ float lds[];
   float* sS = lds;
   float* sT = sS + LP * G::EY;
@@ -79,8 +99,6 @@ __global__ __launch_bounds__(256) void gn_tile_kernel(const GnArgs a) {
   const int H = J.h;
   const float wm1 = static_cast<float>(W - 1), hm1 = static_cast<float>(H - 1);
   const float wm2 = static_cast<float>(W - 2), hm2 = static_cast<float>(H - 2);
-  const int sx = W > 1 ? 1 : 0;
-  const int sy = H > 1 ? ip : 0;
   const int t = blockIdx.x - J.tile_start;
   const int ntx = (W + TX - 1) / TX;
   const int x0 = (t % ntx) * TX;
@@ -89,52 +107,47 @@ __global__ __launch_bounds__(256) void gn_tile_kernel(const GnArgs a) {
   const int gy0 = y0 - KR - 1;
   const int tid = threadIdx.x;
 
-  // ---- phase A: flow, warps, S, T over the ext region (clamped coordinates)
+  // ---- phase A: flow, warps, S, T over the ext region (clamped coordinates).
+  // A lane evaluates up to CH ext pixels at once: the input flow of all of
+  // them is loaded first, then the 8 bilinear taps of each of them are
+  // issued, and only then are any combined, so that a lane has up to 8 CH
+  // gathers in flight.
   {
-    constexpr int NA = (NE + 255) / 256;
-    constexpr int CH = MODE == FLOW_UPSAMPLE ? 4 : 8;
-    constexpr int DY = 256 / EX, DX = 256 % EX;
+    constexpr int NA = (NE + NT - 1) / NT;
+    constexpr int CH = NA <= 16 ? NA : 8;
+    constexpr int DY = NT / EX, DX = NT % EX;
     int ey = tid / EX;
     int ex = tid - ey * EX;
-    const int fpitch = static_cast<int>(J.in_pitch);
+    const uint32_t fpitch = static_cast<uint32_t>(J.in_pitch);
+    const uint32_t uip = static_cast<uint32_t>(ip);
+    const uint32_t rowb = uip * Px<TS>::bytes;  // byte offset of the second tap row
+    const PlaneView v0 = plane_view(p0, uip * static_cast<uint32_t>(H) * sizeof(TS));
+    const PlaneView v1 = plane_view(p1, uip * static_cast<uint32_t>(H) * sizeof(TS));
+    const uint32_t frows = static_cast<uint32_t>(MODE == FLOW_UPSAMPLE ? J.ch : H);
+    const PlaneView vu = plane_view(J.in_u, MODE == FLOW_ZERO ? 0u : fpitch * frows * 4u);
+    const PlaneView vv = plane_view(J.in_v, MODE == FLOW_ZERO ? 0u : fpitch * frows * 4u);
     const float cwm1 = static_cast<float>(J.cw - 1), chm1 = static_cast<float>(J.ch - 1);
     const float cwm2 = static_cast<float>(J.cw - 2), chm2 = static_cast<float>(J.ch - 2);
-    const int csx = J.cw > 1 ? 1 : 0;
-    const int csy = J.ch > 1 ? fpitch : 0;
+    const uint32_t csx = J.cw > 1 ? 1u : 0u;
+    const uint32_t csy = J.ch > 1 ? fpitch : 0u;
 #pragma unroll
     for (int k0 = 0; k0 < NA; k0 += CH) {
-      float uu[CH], vv[CH];
-      int gx[CH], gy[CH], oo[CH];
-      FlowReq fr[CH];
+      float uu[CH], vv2[CH], fx[CH], fy[CH];
+      int oo[CH];
 #pragma unroll
       for (int k = 0; k < CH; ++k) {
-        gx[k] = min(max(gx0 + ex, 0), W - 1);
-        gy[k] = min(max(gy0 + ey, 0), H - 1);
+        const int gx = min(max(gx0 + ex, 0), W - 1);
+        const int gy = min(max(gy0 + ey, 0), H - 1);
+        fx[k] = static_cast<float>(gx);
+        fy[k] = static_cast<float>(gy);
         oo[k] = ey * LP + ex;
         if (MODE == FLOW_DIRECT) {
-          const int o = gy[k] * fpitch + gx[k];
-          uu[k] = J.in_u[o];
-          vv[k] = J.in_v[o];
-        } else if (MODE == FLOW_UPSAMPLE) {
-          // issue the coarse taps of all CH pixels before combining any of them
-          const float fx = __builtin_amdgcn_fmed3f(0.5f * static_cast<float>(gx[k]), 0.0f, cwm1);
-          const float fy = __builtin_amdgcn_fmed3f(0.5f * static_cast<float>(gy[k]), 0.0f, chm1);
-          const float xf = __builtin_amdgcn_fmed3f(floorf(fx), 0.0f, cwm2);
-          const float yf = __builtin_amdgcn_fmed3f(floorf(fy), 0.0f, chm2);
-          fr[k].wx = fx - xf;
-          fr[k].wy = fy - yf;
-          const int o = static_cast<int>(yf) * fpitch + static_cast<int>(xf);
-          fr[k].u00 = J.in_u[o];
-          fr[k].u01 = J.in_u[o + csx];
-          fr[k].u10 = J.in_u[o + csy];
-          fr[k].u11 = J.in_u[o + csy + csx];
-          fr[k].v00 = J.in_v[o];
-          fr[k].v01 = J.in_v[o + csx];
-          fr[k].v10 = J.in_v[o + csy];
-          fr[k].v11 = J.in_v[o + csy + csx];
+          const uint32_t o = __umul24(static_cast<uint32_t>(gy), fpitch) + static_cast<uint32_t>(gx);
+          uu[k] = ld_f32(vu, o);
+          vv2[k] = ld_f32(vv, o);
         } else {
           uu[k] = 0.0f;
-          vv[k] = 0.0f;
+          vv2[k] = 0.0f;
         }
         ex += DX;
         ey += DY;
@@ -144,30 +157,59 @@ __global__ __launch_bounds__(256) void gn_tile_kernel(const GnArgs a) {
         }
       }
       if (MODE == FLOW_UPSAMPLE) {
+        // V = 2 bilinear(V_coarse, x / 2, y / 2): taps of all CH pixels first
+        float cu[CH][4], cv[CH][4], wx[CH], wy[CH];
 #pragma unroll
         for (int k = 0; k < CH; ++k) {
-          const FlowReq& r = fr[k];
-          const float ut = fmaf(r.wx, r.u01 - r.u00, r.u00);
-          const float ub = fmaf(r.wx, r.u11 - r.u10, r.u10);
-          const float vt = fmaf(r.wx, r.v01 - r.v00, r.v00);
-          const float vb = fmaf(r.wx, r.v11 - r.v10, r.v10);
-          uu[k] = 2.0f * fmaf(r.wy, ub - ut, ut);
-          vv[k] = 2.0f * fmaf(r.wy, vb - vt, vt);
+          const BilTap t = bil_setup(0.5f * fx[k], 0.5f * fy[k], cwm1, chm1, cwm2, chm2, fpitch);
+          wx[k] = t.ax;
+          wy[k] = t.ay;
+          cu[k][0] = ld_f32(vu, t.i);
+          cu[k][1] = ld_f32(vu, t.i + csx);
+          cu[k][2] = ld_f32(vu, t.i + csy);
+          cu[k][3] = ld_f32(vu, t.i + csy + csx);
+          cv[k][0] = ld_f32(vv, t.i);
+          cv[k][1] = ld_f32(vv, t.i + csx);
+          cv[k][2] = ld_f32(vv, t.i + csy);
+          cv[k][3] = ld_f32(vv, t.i + csy + csx);
         }
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          uu[k] = 2.0f * bil_combine(cu[k][0], cu[k][1], cu[k][2], cu[k][3], wx[k], wy[k]);
+          vv2[k] = 2.0f * bil_combine(cv[k][0], cv[k][1], cv[k][2], cv[k][3], wx[k], wy[k]);
+        }
+      }
+      float g0[CH][4], g1[CH][4], a0x[CH], a0y[CH], a1x[CH], a1y[CH];
+#pragma unroll
+      for (int k = 0; k < CH; ++k) {
+        const float hu = 0.5f * uu[k];
+        const float hv = 0.5f * vv2[k];
+        const BilTap t0 = bil_setup(fx[k] - hu, fy[k] - hv, wm1, hm1, wm2, hm2, uip);
+        const BilTap t1 = bil_setup(fx[k] + hu, fy[k] + hv, wm1, hm1, wm2, hm2, uip);
+        a0x[k] = t0.ax;
+        a0y[k] = t0.ay;
+        a1x[k] = t1.ax;
+        a1y[k] = t1.ay;
+        // levels are at least 2 x 2 here (the host sends thinner ones to
+        // the march): the taps are (i, i + 1) on rows iy and iy + 1
+        g0[k][0] = Px<TS>::ldv(v0, t0.i);
+        g0[k][1] = Px<TS>::ldv(v0, t0.i + 1);
+        g0[k][2] = Px<TS>::ldvs(v0, t0.i, rowb);
+        g0[k][3] = Px<TS>::ldvs(v0, t0.i + 1, rowb);
+        g1[k][0] = Px<TS>::ldv(v1, t1.i);
+        g1[k][1] = Px<TS>::ldv(v1, t1.i + 1);
+        g1[k][2] = Px<TS>::ldvs(v1, t1.i, rowb);
+        g1[k][3] = Px<TS>::ldvs(v1, t1.i + 1, rowb);
       }
 #pragma unroll
       for (int k = 0; k < CH; ++k) {
-        if (k0 + k < NA && tid + 256 * (k0 + k) < NE) {
-          const float fx = static_cast<float>(gx[k]);
-          const float fy = static_cast<float>(gy[k]);
-          const float hu = 0.5f * uu[k];
-          const float hv = 0.5f * vv[k];
-          const float w0 = bil_clamped(p0, ip, wm1, hm1, wm2, hm2, sx, sy, fx - hu, fy - hv);
-          const float w1 = bil_clamped(p1, ip, wm1, hm1, wm2, hm2, sx, sy, fx + hu, fy + hv);
+        if (k0 + k < NA && tid + NT * (k0 + k) < NE) {
+          const float w0 = bil_combine(g0[k][0], g0[k][1], g0[k][2], g0[k][3], a0x[k], a0y[k]);
+          const float w1 = bil_combine(g1[k][0], g1[k][1], g1[k][2], g1[k][3], a1x[k], a1y[k]);
           sS[oo[k]] = 0.5f * (w0 + w1);
           sT[oo[k]] = w1 - w0;
           sU[oo[k]] = uu[k];
-          sV[oo[k]] = vv[k];
+          sV[oo[k]] = vv2[k];
         }
       }
     }
@@ -178,7 +220,7 @@ __global__ __launch_bounds__(256) void gn_tile_kernel(const GnArgs a) {
   {
     constexpr int NSEG = TX / SL;
     constexpr int NITEM = NSEG * PY;
-    for (int item = tid; item < NITEM; item += 256) {
+    for (int item = tid; item < NITEM; item += NT) {
       const int r = item % PY;  // product row r = ext row r + 1
       const int sg = item / PY;
       const int xs = sg * SL;   // first product column of the first output's window
@@ -252,27 +294,27 @@ __global__ __launch_bounds__(256) void gn_tile_kernel(const GnArgs a) {
   }
 }
 
-template <int KR, int MODE, typename TS, int TX, int TY, int SL, int SLV>
+template <int KR, int MODE, typename TS, int TX, int TY, int SL, int SLV, int NT>
 hipError_t launch_gn_tile_cfg(const GnArgs& a, int nblocks, hipStream_t s) {
   constexpr size_t lds = sizeof(float) * TileGeom<KR, TX, TY>::LDS_FLOATS;
-  auto kern = gn_tile_kernel<KR, MODE, TS, TX, TY, SL, SLV>;
+  auto kern = gn_tile_kernel<KR, MODE, TS, TX, TY, SL, SLV, NT>;
   // dynamic LDS above 64 KiB must be enabled once per kernel (thread-safe static init)
   static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                                      hipFuncAttributeMaxDynamicSharedMemorySize,
                                                      static_cast<int>(lds));
   if (attr != hipSuccess) return attr;
-  hipLaunchKernelGGL(kern, dim3(nblocks), dim3(256), lds, s, a);
+  hipLaunchKernelGGL(kern, dim3(nblocks), dim3(NT), lds, s, a);
   return hipGetLastError();
 }
 
-// variant GN_TILE_64x32: 64 x 32 outputs (segments 16 columns / 8 rows);
-// variant GN_TILE_64x16: 64 x 16 outputs (segments 16 columns / 4 rows).
+// variant GN_TILE_64x32: 64 x 32 outputs, 512 lanes (segments 8 columns / 4 rows);
+// variant GN_TILE_64x16: 64 x 16 outputs, 256 lanes (segments 16 columns / 4 rows).
 template <int MODE, typename TS>
 hipError_t launch_gn_tile_typed(const GnArgs& a, int kr, int variant, int nblocks, hipStream_t s) {
 #define OFV_GNT_CASE(R)                                                                             \
   case R:                                                                                           \
-    return variant == GN_TILE_64x32 ? launch_gn_tile_cfg<R, MODE, TS, 64, 32, 16, 8>(a, nblocks, s) \
-                                    : launch_gn_tile_cfg<R, MODE, TS, 64, 16, 16, 4>(a, nblocks, s);
+    return variant == GN_TILE_64x32 ? launch_gn_tile_cfg<R, MODE, TS, 64, 32, 8, 4, 512>(a, nblocks, s) \
+                                    : launch_gn_tile_cfg<R, MODE, TS, 64, 16, 16, 4, 256>(a, nblocks, s);
   switch (kr) {
     OFV_GNT_CASE(1)
     OFV_GNT_CASE(2)

@@ -10,26 +10,57 @@ namespace ofv {
 
 // ---------------------------------------------------------------------------
 // Step 1: decode + local z-score.  Tile of 64 x 16 outputs per 256 lanes;
-// the (64 + 2 NR) x (16 + 2 NR) input tile is staged in LDS once and each
-// lane evaluates the window mean and the second-pass variance of 4 pixels.
+// integer frames are scaled by the float32 reciprocal of 2^B - 1 and the
+// z-score uses the hardware reciprocal square root (both within a few
+// float32 rounding errors of the exact quotients);
+// the (64 + 2 NR) x (16 + 2 NR) input tile is staged in LDS once (frame
+// pixels outside the frame stored as 0) and each lane evaluates 4
+// vertically adjacent outputs of one column:
+//   mu = S / n,  var = sum over the truncated window of (I - mu)^2 / n,
+//   N = (I - mu) / sqrt(var + eps)      (second-pass variance)
+// For NR <= 3 the lane's (4 + 2 NR) x (2 NR + 1) patch is read into
+// registers once; row sums are shared between the 4 outputs and window
+// taps outside the frame are masked by 0/1 row and column weights.
+// Larger radii take the generic path that walks the window in LDS.
 // ---------------------------------------------------------------------------
 constexpr int kNormTW = 64;
 constexpr int kNormTH = 16;
 
-__device__ __forceinline__ float load_frame_px(const NormJob& J, int x, int y) {
-  const int64_t o = static_cast<int64_t>(y) * J.in_pitch + x;
-  if (J.type == 0) {
-    const float v = static_cast<float>(static_cast<const uint8_t*>(J.in)[o]);
-    return v / static_cast<float>((1 << J.bits) - 1);
-  }
-  if (J.type == 1) {
-    const float v = static_cast<float>(static_cast<const uint16_t*>(J.in)[o]);
-    return v / static_cast<float>((1 << J.bits) - 1);
-  }
-  return static_cast<const float*>(J.in)[o];
+template <typename TI>
+__device__ __forceinline__ float frame_value(const void* base, int64_t o, float inv_max) {
+  return static_cast<float>(static_cast<const TI*>(base)[o]) * inv_max;
+}
+template <>
+__device__ __forceinline__ float frame_value<float>(const void* base, int64_t o, float) {
+  return static_cast<const float*>(base)[o];
 }
 
-template <typename TS>
+// Stage a tw x th tile whose pixel (0, 0) is frame pixel (x0, y0); up to 8
+// loads per lane are in flight before the first LDS store.
+template <typename TI>
+__device__ __forceinline__ void stage_frame_tile(const NormJob& J, float* tile, int x0, int y0, int tw, int th) {
+  const int n = tw * th;
+  const float inv_max = 1.0f / static_cast<float>((1 << J.bits) - 1);
+  for (int i0 = threadIdx.x; i0 < n; i0 += 8 * 256) {
+    float v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int i = min(i0 + 256 * k, n - 1);
+      const int ty = i / tw;
+      const int gx = x0 + (i - ty * tw);
+      const int gy = y0 + ty;
+      const bool in = static_cast<unsigned>(gx) < static_cast<unsigned>(J.w) &&
+                      static_cast<unsigned>(gy) < static_cast<unsigned>(J.h);
+      const int64_t o = static_cast<int64_t>(min(max(gy, 0), J.h - 1)) * J.in_pitch + min(max(gx, 0), J.w - 1);
+      v[k] = in ? frame_value<TI>(J.in, o, inv_max) : 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (i0 + 256 * k < n) tile[i0 + 256 * k] = v[k];
+  }
+}
+
+template <typename TS, int NRC>
 __global__ __launch_bounds__(256) void normalize_kernel(const NormArgs a) {
   extern __shared__ float tile[];
   const int j = find_job(a, blockIdx.x);
@@ -38,37 +69,77 @@ __global__ __launch_bounds__(256) void normalize_kernel(const NormArgs a) {
   const int ntx = (J.w + kNormTW - 1) / kNormTW;
   const int x0 = (t % ntx) * kNormTW;
   const int y0 = (t / ntx) * kNormTH;
-  const int nr = a.nr;
+  const int nr = NRC > 0 ? NRC : a.nr;
   const int tw = kNormTW + 2 * nr;
   const int th = kNormTH + 2 * nr;
-  // all loads of the tile are issued before any is stored (up to 8 per lane
-  // in flight); rows and columns outside the frame read as 0 and are never used
-  const int n = tw * th;
-  for (int i0 = threadIdx.x; i0 < n; i0 += 8 * 256) {
-    float v[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int i = min(i0 + 256 * k, n - 1);
-      const int gx = x0 - nr + i % tw;
-      const int gy = y0 - nr + i / tw;
-      const bool in = gx >= 0 && gx < J.w && gy >= 0 && gy < J.h;
-      v[k] = load_frame_px(J, min(max(gx, 0), J.w - 1), min(max(gy, 0), J.h - 1));
-      v[k] = in ? v[k] : 0.0f;
-    }
-#pragma unroll
-    for (int k = 0; k < 8; ++k)
-      if (i0 + 256 * k < n) tile[i0 + 256 * k] = v[k];
-  }
+  if (J.type == 0) stage_frame_tile<uint8_t>(J, tile, x0 - nr, y0 - nr, tw, th);
+  else if (J.type == 1) stage_frame_tile<uint16_t>(J, tile, x0 - nr, y0 - nr, tw, th);
+  else stage_frame_tile<float>(J, tile, x0 - nr, y0 - nr, tw, th);
   __syncthreads();
   const int lx = threadIdx.x & 63;
+  const int ly0 = 4 * (threadIdx.x >> 6);
   const int gx = x0 + lx;
-  if (gx >= J.w) return;
-  TS* out = static_cast<TS*>(J.out);
+  const int gy0 = y0 + ly0;
+  if (gx >= J.w || gy0 >= J.h) return;
+  TS* out = static_cast<TS*>(J.out) + static_cast<int64_t>(gy0) * J.out_pitch + gx;
+  if (NRC > 0) {
+    constexpr int R = NRC;
+    constexpr int NC = 2 * R + 1;
+    constexpr int NRW = 4 + 2 * R;
+    float pv[NRW][NC];
+    float vy[NRW], vx[NC];
+#pragma unroll
+    for (int r = 0; r < NRW; ++r) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) pv[r][c] = tile[(ly0 + r) * tw + lx + c];
+      vy[r] = static_cast<unsigned>(gy0 - R + r) < static_cast<unsigned>(J.h) ? 1.0f : 0.0f;
+    }
+    float ncol = 0.0f;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      vx[c] = static_cast<unsigned>(gx - R + c) < static_cast<unsigned>(J.w) ? 1.0f : 0.0f;
+      ncol += vx[c];
+    }
+    float hs[NRW];
+#pragma unroll
+    for (int r = 0; r < NRW; ++r) {
+      float acc = 0.0f;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) acc += pv[r][c];
+      hs[r] = acc;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (gy0 + k < J.h) {
+        float sm = 0.0f, nrow = 0.0f;
+#pragma unroll
+        for (int r = 0; r < NC; ++r) {
+          sm += hs[k + r];
+          nrow += vy[k + r];
+        }
+        const float rn = 1.0f / (nrow * ncol);
+        const float mu = sm * rn;
+        float q = 0.0f;
+#pragma unroll
+        for (int r = 0; r < NC; ++r) {
+          float qr = 0.0f;
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            const float d = pv[k + r][c] - mu;
+            qr = fmaf(vx[c] * d, d, qr);
+          }
+          q = fmaf(vy[k + r], qr, q);
+        }
+        Px<TS>::st(out + k * J.out_pitch, (pv[k + R][R] - mu) * __builtin_amdgcn_rsqf(fmaf(q, rn, a.eps)));
+      }
+    }
+    return;
+  }
   const int xa = max(-nr, -gx);
   const int xb = min(nr, J.w - 1 - gx);
   for (int k = 0; k < 4; ++k) {
-    const int ly = (threadIdx.x >> 6) + 4 * k;
-    const int gy = y0 + ly;
+    const int ly = ly0 + k;
+    const int gy = gy0 + k;
     if (gy >= J.h) break;
     const float* centre = tile + (ly + nr) * tw + (lx + nr);
     float nv = *centre;
@@ -92,55 +163,102 @@ __global__ __launch_bounds__(256) void normalize_kernel(const NormArgs a) {
       }
       nv = (nv - mu) / sqrtf(q / n + a.eps);
     }
-    Px<TS>::st(out + static_cast<int64_t>(gy) * J.out_pitch + gx, nv);
+    Px<TS>::st(out + k * J.out_pitch, nv);
   }
+}
+
+template <typename TS>
+hipError_t launch_normalize_typed(const NormArgs& a, int nblocks, size_t lds, hipStream_t s) {
+  switch (a.nr) {
+    case 1: hipLaunchKernelGGL((normalize_kernel<TS, 1>), dim3(nblocks), dim3(256), lds, s, a); break;
+    case 2: hipLaunchKernelGGL((normalize_kernel<TS, 2>), dim3(nblocks), dim3(256), lds, s, a); break;
+    case 3: hipLaunchKernelGGL((normalize_kernel<TS, 3>), dim3(nblocks), dim3(256), lds, s, a); break;
+    default: hipLaunchKernelGGL((normalize_kernel<TS, 0>), dim3(nblocks), dim3(256), lds, s, a); break;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_normalize(const NormArgs& a, int nblocks, hipStream_t s) {
   const size_t lds = sizeof(float) * (kNormTW + 2 * a.nr) * (kNormTH + 2 * a.nr);
   switch (a.storage) {
-    case ST_F32: hipLaunchKernelGGL(normalize_kernel<float>, dim3(nblocks), dim3(256), lds, s, a); break;
-    case ST_F16: hipLaunchKernelGGL(normalize_kernel<_Float16>, dim3(nblocks), dim3(256), lds, s, a); break;
-    default: hipLaunchKernelGGL(normalize_kernel<bf16_t>, dim3(nblocks), dim3(256), lds, s, a); break;
+    case ST_F32: return launch_normalize_typed<float>(a, nblocks, lds, s);
+    case ST_F16: return launch_normalize_typed<_Float16>(a, nblocks, lds, s);
+    default: return launch_normalize_typed<bf16_t>(a, nblocks, lds, s);
   }
-  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// Step 2: REDUCE.  One lane per output pixel, 64 x 4 outputs per workgroup;
-// the 5 x 5 binomial stencil reads through the caches (each input pixel is
-// touched by at most 9 outputs, all in neighbouring lanes and rows).
-// out(x, y) = scale * sum_j w_j sum_i w_i in(clamp(2x+i), clamp(2y+j)).
+// Step 2: REDUCE.  64 x 4 outputs per 256-lane workgroup:
+//   out(x, y) = scale * sum_j w_j sum_i w_i in(clamp(2x+i), clamp(2y+j)),
+// w = [1, 4, 6, 4, 1] / 16, i, j = -2..2.  The 131 x 11 input tile (indices
+// clamped into the plane) is staged in LDS with coalesced row loads, the
+// horizontal 5-tap pass writes 11 x 64 row sums to LDS and the vertical
+// pass combines 5 of them per output.
 // ---------------------------------------------------------------------------
 constexpr int kRedTW = 64;
 constexpr int kRedTH = 4;
+constexpr int kRedInW = 2 * kRedTW + 3;  // 131 input columns
+constexpr int kRedInH = 2 * kRedTH + 3;  // 11 input rows
 
 template <typename TS>
 __global__ __launch_bounds__(256) void reduce_kernel(const ReduceArgs a) {
+  __shared__ float tin[kRedInH][kRedInW + 1];
+  __shared__ float th[kRedInH][kRedTW + 1];
   const int j = find_job(a, blockIdx.x);
   const ReduceJob& J = a.job[j];
   const int wn = (J.w + 1) / 2;
   const int hn = (J.h + 1) / 2;
   const int t = blockIdx.x - J.tile_start;
   const int ntx = (wn + kRedTW - 1) / kRedTW;
-  const int x = (t % ntx) * kRedTW + (threadIdx.x & 63);
-  const int y = (t / ntx) * kRedTH + (threadIdx.x >> 6);
-  if (x >= wn || y >= hn) return;
+  const int x0 = (t % ntx) * kRedTW;
+  const int y0 = (t / ntx) * kRedTH;
+  const int bx = 2 * x0 - 2;
+  const int by = 2 * y0 - 2;
   const TS* in = static_cast<const TS*>(J.in);
-  const float w5[5] = {1.0f / 16, 4.0f / 16, 6.0f / 16, 4.0f / 16, 1.0f / 16};
-  int xs[5];
+  constexpr int NIN = kRedInH * kRedInW;
+  constexpr int NLD = (NIN + 255) / 256;
+  float v[NLD];
 #pragma unroll
-  for (int i = 0; i < 5; ++i) xs[i] = min(max(2 * x + i - 2, 0), J.w - 1);
-  float acc = 0.0f;
-#pragma unroll
-  for (int jj = 0; jj < 5; ++jj) {
-    const int yy = min(max(2 * y + jj - 2, 0), J.h - 1);
-    const TS* row = in + static_cast<int64_t>(yy) * J.in_pitch;
-    float r = 0.0f;
-#pragma unroll
-    for (int i = 0; i < 5; ++i) r += w5[i] * Px<TS>::ld(row + xs[i]);
-    acc += w5[jj] * r;
+  for (int k = 0; k < NLD; ++k) {
+    const int i = min(static_cast<int>(threadIdx.x) + 256 * k, NIN - 1);
+    const int r = i / kRedInW;
+    const int c = i - r * kRedInW;
+    const int gx = min(max(bx + c, 0), J.w - 1);
+    const int gy = min(max(by + r, 0), J.h - 1);
+    v[k] = Px<TS>::ld(in + static_cast<int64_t>(gy) * J.in_pitch + gx);
   }
+#pragma unroll
+  for (int k = 0; k < NLD; ++k) {
+    const int i = threadIdx.x + 256 * k;
+    if (i < NIN) {
+      const int r = i / kRedInW;
+      tin[r][i - r * kRedInW] = v[k];
+    }
+  }
+  __syncthreads();
+  constexpr float w0 = 1.0f / 16, w1 = 4.0f / 16, w2 = 6.0f / 16;
+  for (int i = threadIdx.x; i < kRedInH * kRedTW; i += 256) {
+    const int r = i / kRedTW;
+    const int c = i - r * kRedTW;
+    const float* p = &tin[r][2 * c];
+    float acc = w0 * p[0];
+    acc += w1 * p[1];
+    acc += w2 * p[2];
+    acc += w1 * p[3];
+    acc += w0 * p[4];
+    th[r][c] = acc;
+  }
+  __syncthreads();
+  const int lx = threadIdx.x & 63;
+  const int ly = threadIdx.x >> 6;
+  const int x = x0 + lx;
+  const int y = y0 + ly;
+  if (x >= wn || y >= hn) return;
+  float acc = w0 * th[2 * ly][lx];
+  acc += w1 * th[2 * ly + 1][lx];
+  acc += w2 * th[2 * ly + 2][lx];
+  acc += w1 * th[2 * ly + 3][lx];
+  acc += w0 * th[2 * ly + 4][lx];
   Px<TS>::st(static_cast<TS*>(J.out) + static_cast<int64_t>(y) * J.out_pitch + x, a.scale * acc);
 }
 

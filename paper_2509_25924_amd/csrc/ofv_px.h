@@ -10,18 +10,44 @@ struct bf16_t {
   uint16_t bits;
 };
 
+// Raw buffer view of one plane: the base and size sit in scalar registers
+// and every access is a 32-bit byte offset from the base; an access at or
+// beyond `bytes` reads 0 instead of touching memory (gfx9 raw-buffer
+// descriptor: stride 0, 32-bit data format).  Planes stay below 2 GiB.
+using PlaneView = __amdgpu_buffer_rsrc_t;
+
+__device__ __forceinline__ PlaneView plane_view(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, static_cast<int>(bytes), 0x00020000);
+}
+
+__device__ __forceinline__ float ld_f32(PlaneView v, uint32_t i) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(v, static_cast<int>(i * 4u), 0, 0));
+}
+
 template <typename T>
 struct Px;
 
 template <>
 struct Px<float> {
   static __device__ __forceinline__ float ld(const float* p) { return *p; }
+  static __device__ __forceinline__ float ldv(PlaneView v, uint32_t i) { return ld_f32(v, i); }
+  // element i + j of the plane, j a byte offset uniform across the wavefront
+  static __device__ __forceinline__ float ldvs(PlaneView v, uint32_t i, uint32_t jb) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(v, static_cast<int>(i * 4u), static_cast<int>(jb), 0));
+  }
+  static constexpr uint32_t bytes = 4;
   static __device__ __forceinline__ void st(float* p, float v) { *p = v; }
 };
 
 template <>
 struct Px<_Float16> {
   static __device__ __forceinline__ float ld(const _Float16* p) { return static_cast<float>(*p); }
+  static __device__ __forceinline__ float ldv(PlaneView v, uint32_t i) { return ldvs(v, i, 0); }
+  static __device__ __forceinline__ float ldvs(PlaneView v, uint32_t i, uint32_t jb) {
+    const uint16_t b = __builtin_amdgcn_raw_buffer_load_b16(v, static_cast<int>(i * 2u), static_cast<int>(jb), 0);
+    return static_cast<float>(__builtin_bit_cast(_Float16, b));
+  }
+  static constexpr uint32_t bytes = 2;
   static __device__ __forceinline__ void st(_Float16* p, float v) { *p = static_cast<_Float16>(v); }
 };
 
@@ -32,6 +58,12 @@ struct Px<bf16_t> {
   static __device__ __forceinline__ float ld(const bf16_t* p) {
     return __uint_as_float(static_cast<uint32_t>(p->bits) << 16);
   }
+  static __device__ __forceinline__ float ldv(PlaneView v, uint32_t i) { return ldvs(v, i, 0); }
+  static __device__ __forceinline__ float ldvs(PlaneView v, uint32_t i, uint32_t jb) {
+    const uint16_t b = __builtin_amdgcn_raw_buffer_load_b16(v, static_cast<int>(i * 2u), static_cast<int>(jb), 0);
+    return __uint_as_float(static_cast<uint32_t>(b) << 16);
+  }
+  static constexpr uint32_t bytes = 2;
   static __device__ __forceinline__ void st(bf16_t* p, float v) {
     uint32_t u = __float_as_uint(v);
     if ((u & 0x7f800000u) == 0x7f800000u) {
@@ -71,7 +103,8 @@ __device__ __forceinline__ float bilinear(const T* __restrict__ p, int64_t pitch
 
 // Damped 2x2 solve of one Gauss-Newton step (Eq. of_symmetric linearised):
 //   (A + lam I) V' = c + lam V(m),  lam = reg_rel (Sxx + Syy) + reg_abs,
-// by Cramer's rule in float32.  Where the system is ill-conditioned
+// by Cramer's rule in float32 (one reciprocal of the determinant).  Where
+// the system is ill-conditioned
 // (q = 4 det / trace^2 < 1e-2) the float32 determinant has lost leading
 // digits to cancellation; there the determinant and the solution are
 // recomputed in float64 from the same float32 sums (products of two floats
@@ -86,7 +119,9 @@ __device__ __forceinline__ void solve2x2(float sxx, float sxy, float syy, float 
   const float det = aa * dd - sxy * sxy;
   const float tr = aa + dd;
   if (det >= 2.5e-3f * tr * tr) {
-    const float inv = 1.0f / det;
+    // hardware reciprocal (1 ulp) refined by one Newton step
+    float inv = __builtin_amdgcn_rcpf(det);
+    inv = fmaf(inv, fmaf(-det, inv, 1.0f), inv);
     u = (dd * r1 - sxy * r2) * inv;
     v = (aa * r2 - sxy * r1) * inv;
   } else {
