@@ -22,7 +22,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
-GN_NAMES = {0: "march", 1: "tile64x32", 2: "tile64x16"}
+GN_NAMES = {0: "march", 1: "tile64x32", 2: "tile64x16", 3: "tile32x16", 4: "tile16x16", 5: "tile64x32w",
+            6: "tile64x16w"}
 GN_SOURCES = ["ofv_gn_impl.h", "ofv_gn_tile.h", "ofv_px.h", "ofv_internal.h"]
 
 
@@ -65,7 +66,7 @@ def parse():
     ap.add_argument("--workload", default="shear_1mp", choices=["shear_1mp", "rankine_256", "paper_1mp"])
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--no-graph", action="store_true", help="launch eagerly instead of replaying a hipGraph")
-    ap.add_argument("--variant", default="tuned", choices=["tuned", "auto", "march", "tile64x32", "tile64x16"],
+    ap.add_argument("--variant", default="tuned", choices=["tuned", "auto"] + list(GN_NAMES.values()),
                     help="Gauss-Newton work decomposition: autotuned per level (default) or forced")
     ap.add_argument("--kernel-launches", type=int, default=200, help="launches timed for the dominant kernel")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="budget of the CPU oracle sample")

@@ -67,7 +67,8 @@ typedef struct {
   const void* data;   /* device pointer to pixel (0, 0) */
   int32_t width;      /* >= 1 */
   int32_t height;     /* >= 1 */
-  int64_t pitch;      /* elements per row, >= width; a crop is an offset pointer with the parent's pitch */
+  int64_t pitch;      /* elements per row, >= width, < 2^24; a crop is an offset pointer with the parent's
+                         pitch; pitch * height * element size < 2 GiB (else OFV_ERR_UNSUPPORTED) */
   int32_t type;       /* ofv_pixel_type */
   int32_t bit_depth;  /* integer frames: significant bits, 1..8 for U8, 1..16 for U16 (right-aligned);
                          intensity = value / (2^bit_depth - 1).  Ignored for F32 (used as given). */
@@ -167,6 +168,10 @@ ofv_status ofv_compute_flow_backward(ofv_handle h, const ofv_image* frame0, cons
 #define OFV_GN_MARCH 0        /* 256-column strips marching down tile_h rows */
 #define OFV_GN_TILE_64x32 1   /* 64 x 32 output tiles, three LDS phases */
 #define OFV_GN_TILE_64x16 2   /* 64 x 16 output tiles, three LDS phases */
+#define OFV_GN_TILE_32x16 3   /* 32 x 16 output tiles (coarse levels) */
+#define OFV_GN_TILE_16x16 4   /* 16 x 16 output tiles (coarse levels) */
+#define OFV_GN_TILE_64x32W 5  /* 64 x 32 output tiles, 1024 lanes per workgroup */
+#define OFV_GN_TILE_64x16W 6  /* 64 x 16 output tiles, 512 lanes per workgroup */
 
 /* Force a decomposition for later calls on h (OFV_GN_AUTO restores the
  * default); tile_h (rows per strip for OFV_GN_MARCH) is 0 for automatic or
@@ -174,7 +179,8 @@ ofv_status ofv_compute_flow_backward(ofv_handle h, const ofv_image* frame0, cons
 ofv_status ofv_set_gn_variant(ofv_handle h, int variant, int tile_h);
 
 /* Autotuner: runs the estimator on this pair once per candidate
- * decomposition (64x16 tiles, 64x32 tiles, strips of 16/32/64 rows), `repeats`
+ * decomposition (16x16, 32x16, 64x16 and 64x32 tiles with 256 to 1024 lanes, strips of
+ * 16/32/64 rows), `repeats`
  * timed runs each, times every Gauss-Newton launch with HIP events, and
  * records the fastest candidate per (window radius, storage, flow mode, level
  * size, batch size) in the handle; later calls with matching geometry use it.

@@ -138,6 +138,9 @@ ofv_status check_image(ofv_ctx* h, const ofv_image* f, const char* name) {
   } else if (f->type != OFV_PIX_F32) {
     return fail(h, OFV_ERR_INVALID_ARG, "%s: unknown pixel type %d", name, f->type);
   }
+  if (f->pitch >= kMaxPitch ||
+      f->pitch * static_cast<int64_t>(f->height) * static_cast<int64_t>(pixel_bytes(f->type)) >= kMaxPlaneBytes)
+    return fail(h, OFV_ERR_UNSUPPORTED, "%s: pitch of 2^24 elements or more, or 2 GiB or more", name);
   return OFV_OK;
 }
 
@@ -227,6 +230,8 @@ void pick_gn(const ofv_ctx* h, const ofv_ctx::TuneKey& key, int64_t strips, int6
     if (!std::strcmp(e, "march")) { variant = GN_MARCH; return; }
     if (!std::strcmp(e, "tile32")) { variant = GN_TILE_64x32; return; }
     if (!std::strcmp(e, "tile16")) { variant = GN_TILE_64x16; return; }
+    if (!std::strcmp(e, "tile32x16")) { variant = GN_TILE_32x16; return; }
+    if (!std::strcmp(e, "tile16x16")) { variant = GN_TILE_16x16; return; }
   }
   if (h->forced_variant >= 0) {
     variant = h->forced_variant;
@@ -977,7 +982,7 @@ ofv_status ofv_destroy(ofv_handle h) {
 
 ofv_status ofv_set_gn_variant(ofv_handle h, int variant, int tile_h) {
   if (check_handle(h) != OFV_OK) return OFV_ERR_INVALID_ARG;
-  if (variant < -1 || variant > GN_TILE_64x16) return fail(h, OFV_ERR_INVALID_ARG, "unknown variant %d", variant);
+  if (variant < -1 || variant >= kGnVariants) return fail(h, OFV_ERR_INVALID_ARG, "unknown variant %d", variant);
   if (tile_h != 0 && (tile_h < 4 || tile_h > 1024)) return fail(h, OFV_ERR_INVALID_ARG, "tile_h %d outside 4..1024", tile_h);
   h->forced_variant = variant;
   h->forced_tile_h = tile_h;
@@ -996,7 +1001,9 @@ ofv_status ofv_autotune(ofv_handle h, const ofv_image* frame0, const ofv_image* 
     int variant, tile_h;
   };
   // tile variants ignore tile_h (their tile height is fixed); it is recorded as their height
-  const Cand cands[] = {{GN_TILE_64x16, 16}, {GN_TILE_64x32, 32}, {GN_MARCH, 16}, {GN_MARCH, 32}, {GN_MARCH, 64}};
+  const Cand cands[] = {{GN_TILE_16x16, 16},  {GN_TILE_32x16, 16},  {GN_TILE_64x16, 16}, {GN_TILE_64x32, 32},
+                        {GN_TILE_64x16W, 16}, {GN_TILE_64x32W, 32}, {GN_MARCH, 16},      {GN_MARCH, 32},
+                        {GN_MARCH, 64}};
   std::map<ofv_ctx::TuneKey, std::pair<float, ofv_ctx::Choice>> best;
   const int saved_v = h->forced_variant, saved_t = h->forced_tile_h;
   for (const Cand& c : cands) {
@@ -1058,7 +1065,7 @@ ofv_status ofv_tuning_import(ofv_handle h, const char* text) {
   int line = 0;
   while (is >> k.kr >> k.storage >> k.mode >> k.w >> k.hgt >> k.n >> c.variant >> c.tile_h) {
     ++line;
-    if (c.variant < GN_MARCH || c.variant > GN_TILE_64x16 || c.tile_h < 4 || c.tile_h > 1024)
+    if (c.variant < GN_MARCH || c.variant >= kGnVariants || c.tile_h < 4 || c.tile_h > 1024)
       return fail(h, OFV_ERR_INVALID_ARG, "tuning entry %d is invalid", line);
     add[k] = c;
   }

@@ -72,7 +72,9 @@ template <int KR, int TX, int TY, int NT>
 struct TileOcc {
   static constexpr int lds = 4 * TileGeom<KR, TX, TY>::LDS_FLOATS;
   static constexpr int fit = (163840 / lds) * (NT / 256);
-  static constexpr int value = fit < 1 ? 1 : (fit > 8 ? 8 : fit);
+  // at most 4 waves per SIMD: 128 registers per lane keep the gathers of a
+  // chunk in flight without spilling
+  static constexpr int value = fit < 1 ? 1 : (fit > 4 ? 4 : fit);
 };
 
 template <int KR, int MODE, typename TS, int TX, int TY, int SL, int SLV, int NT>
@@ -308,13 +310,25 @@ hipError_t launch_gn_tile_cfg(const GnArgs& a, int nblocks, hipStream_t s) {
 }
 
 // variant GN_TILE_64x32: 64 x 32 outputs, 512 lanes (segments 8 columns / 4 rows);
-// variant GN_TILE_64x16: 64 x 16 outputs, 256 lanes (segments 16 columns / 4 rows).
+// variant GN_TILE_64x16: 64 x 16 outputs, 256 lanes (segments 16 columns / 4 rows);
+// variant GN_TILE_32x16: 32 x 16 outputs, 256 lanes (segments 4 columns / 2 rows);
+// variant GN_TILE_16x16: 16 x 16 outputs, 256 lanes (segments 4 columns / 1 row);
+// variants GN_TILE_64x32W / 64x16W: the same tiles with 1024 / 512 lanes
+// (segments 8 columns / 2 rows), more waves to hide latency per compute unit.
+// The small tiles spread coarse levels over many compute units: there the
+// launch is bound by the instruction latency of few waves, not by traffic.
 template <int MODE, typename TS>
 hipError_t launch_gn_tile_typed(const GnArgs& a, int kr, int variant, int nblocks, hipStream_t s) {
 #define OFV_GNT_CASE(R)                                                                             \
   case R:                                                                                           \
-    return variant == GN_TILE_64x32 ? launch_gn_tile_cfg<R, MODE, TS, 64, 32, 8, 4, 512>(a, nblocks, s) \
-                                    : launch_gn_tile_cfg<R, MODE, TS, 64, 16, 16, 4, 256>(a, nblocks, s);
+    switch (variant) {                                                                              \
+      case GN_TILE_64x32: return launch_gn_tile_cfg<R, MODE, TS, 64, 32, 8, 4, 512>(a, nblocks, s);  \
+      case GN_TILE_64x16: return launch_gn_tile_cfg<R, MODE, TS, 64, 16, 16, 4, 256>(a, nblocks, s); \
+      case GN_TILE_32x16: return launch_gn_tile_cfg<R, MODE, TS, 32, 16, 4, 2, 256>(a, nblocks, s);  \
+      case GN_TILE_64x32W: return launch_gn_tile_cfg<R, MODE, TS, 64, 32, 8, 2, 1024>(a, nblocks, s); \
+      case GN_TILE_64x16W: return launch_gn_tile_cfg<R, MODE, TS, 64, 16, 8, 2, 512>(a, nblocks, s);  \
+      default: return launch_gn_tile_cfg<R, MODE, TS, 16, 16, 4, 1, 256>(a, nblocks, s);            \
+    }
   switch (kr) {
     OFV_GNT_CASE(1)
     OFV_GNT_CASE(2)

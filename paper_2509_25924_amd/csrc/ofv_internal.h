@@ -79,7 +79,16 @@ struct GnArgs {
 };
 
 // Work decompositions of the fused Gauss-Newton kernel.
-enum GnVariant { GN_MARCH = 0, GN_TILE_64x32 = 1, GN_TILE_64x16 = 2 };
+enum GnVariant {
+  GN_MARCH = 0,
+  GN_TILE_64x32 = 1,
+  GN_TILE_64x16 = 2,
+  GN_TILE_32x16 = 3,
+  GN_TILE_16x16 = 4,
+  GN_TILE_64x32W = 5,
+  GN_TILE_64x16W = 6
+};
+constexpr int kGnVariants = 7;
 
 // Columns of output produced by one 256-lane strip for window radius kr.
 inline int gn_tile_w(int kr) { return kGnThreads - 2 * kr - 2; }
@@ -87,7 +96,10 @@ inline int gn_tile_w(int kr) { return kGnThreads - 2 * kr - 2; }
 // Output tile of a variant: width and height (march: strip width, tile_h rows).
 inline void gn_tile_dims(int variant, int kr, int tile_h, int& tw, int& th) {
   if (variant == GN_TILE_64x32) { tw = 64; th = 32; }
-  else if (variant == GN_TILE_64x16) { tw = 64; th = 16; }
+  else if (variant == GN_TILE_64x16 || variant == GN_TILE_64x16W) { tw = 64; th = 16; }
+  else if (variant == GN_TILE_64x32W) { tw = 64; th = 32; }
+  else if (variant == GN_TILE_32x16) { tw = 32; th = 16; }
+  else if (variant == GN_TILE_16x16) { tw = 16; th = 16; }
   else { tw = gn_tile_w(kr); th = tile_h; }
 }
 

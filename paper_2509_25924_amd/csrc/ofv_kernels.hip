@@ -3,6 +3,8 @@
 // level of the Burt-Adelson pyramid, and flow up-sampling.  All three are
 // HBM-bound stencils; each workgroup stages its input tile (plus halo) in LDS
 // or reads it through the L1/L2 caches, and writes coalesced rows.
+#include <type_traits>
+
 #include "ofv_internal.h"
 #include "ofv_px.h"
 
@@ -60,6 +62,51 @@ __device__ __forceinline__ void stage_frame_tile(const NormJob& J, float* tile, 
   }
 }
 
+template <typename TI>
+__device__ __forceinline__ float frame_ldv(PlaneView v, uint32_t i);
+template <>
+__device__ __forceinline__ float frame_ldv<uint8_t>(PlaneView v, uint32_t i) {
+  return static_cast<float>(__builtin_amdgcn_raw_buffer_load_b8(v, static_cast<int>(i), 0, 0));
+}
+template <>
+__device__ __forceinline__ float frame_ldv<uint16_t>(PlaneView v, uint32_t i) {
+  return static_cast<float>(__builtin_amdgcn_raw_buffer_load_b16(v, static_cast<int>(i * 2u), 0, 0));
+}
+template <>
+__device__ __forceinline__ float frame_ldv<float>(PlaneView v, uint32_t i) {
+  return ld_f32(v, i);
+}
+
+// Same as stage_frame_tile for a TW x TH tile known at compile time: every
+// lane issues its ceil(TW TH / 256) loads at once through a buffer view of
+// the frame (32-bit offsets; frames stay below 2 GiB with pitches below 2^24).
+template <typename TI, int TW, int TH>
+__device__ __forceinline__ void stage_frame_tile_c(const NormJob& J, float* tile, int x0, int y0) {
+  constexpr int N = TW * TH;
+  constexpr int NLD = (N + 255) / 256;
+  const uint32_t pitch = static_cast<uint32_t>(J.in_pitch);
+  const PlaneView fv = plane_view(J.in, pitch * static_cast<uint32_t>(J.h) * static_cast<uint32_t>(sizeof(TI)));
+  const float inv_max = 1.0f / static_cast<float>((1 << J.bits) - 1);
+  float v[NLD];
+#pragma unroll
+  for (int k = 0; k < NLD; ++k) {
+    const int i = min(static_cast<int>(threadIdx.x) + 256 * k, N - 1);
+    const int ty = i / TW;
+    const int gx = x0 + (i - ty * TW);
+    const int gy = y0 + ty;
+    const bool in = static_cast<unsigned>(gx) < static_cast<unsigned>(J.w) &&
+                    static_cast<unsigned>(gy) < static_cast<unsigned>(J.h);
+    const uint32_t o = __umul24(static_cast<uint32_t>(min(max(gy, 0), J.h - 1)), pitch) +
+                       static_cast<uint32_t>(min(max(gx, 0), J.w - 1));
+    float x = frame_ldv<TI>(fv, o);
+    if (!std::is_same<TI, float>::value) x *= inv_max;
+    v[k] = in ? x : 0.0f;
+  }
+#pragma unroll
+  for (int k = 0; k < NLD; ++k)
+    if (static_cast<int>(threadIdx.x) + 256 * k < N) tile[threadIdx.x + 256 * k] = v[k];
+}
+
 template <typename TS, int NRC>
 __global__ __launch_bounds__(256) void normalize_kernel(const NormArgs a) {
   extern __shared__ float tile[];
@@ -72,9 +119,16 @@ __global__ __launch_bounds__(256) void normalize_kernel(const NormArgs a) {
   const int nr = NRC > 0 ? NRC : a.nr;
   const int tw = kNormTW + 2 * nr;
   const int th = kNormTH + 2 * nr;
-  if (J.type == 0) stage_frame_tile<uint8_t>(J, tile, x0 - nr, y0 - nr, tw, th);
-  else if (J.type == 1) stage_frame_tile<uint16_t>(J, tile, x0 - nr, y0 - nr, tw, th);
-  else stage_frame_tile<float>(J, tile, x0 - nr, y0 - nr, tw, th);
+  if (NRC > 0) {
+    constexpr int TW = kNormTW + 2 * NRC, TH = kNormTH + 2 * NRC;
+    if (J.type == 0) stage_frame_tile_c<uint8_t, TW, TH>(J, tile, x0 - nr, y0 - nr);
+    else if (J.type == 1) stage_frame_tile_c<uint16_t, TW, TH>(J, tile, x0 - nr, y0 - nr);
+    else stage_frame_tile_c<float, TW, TH>(J, tile, x0 - nr, y0 - nr);
+  } else {
+    if (J.type == 0) stage_frame_tile<uint8_t>(J, tile, x0 - nr, y0 - nr, tw, th);
+    else if (J.type == 1) stage_frame_tile<uint16_t>(J, tile, x0 - nr, y0 - nr, tw, th);
+    else stage_frame_tile<float>(J, tile, x0 - nr, y0 - nr, tw, th);
+  }
   __syncthreads();
   const int lx = threadIdx.x & 63;
   const int ly0 = 4 * (threadIdx.x >> 6);
@@ -107,6 +161,28 @@ __global__ __launch_bounds__(256) void normalize_kernel(const NormArgs a) {
 #pragma unroll
       for (int c = 0; c < NC; ++c) acc += pv[r][c];
       hs[r] = acc;
+    }
+    // block-uniform: every window of the tile lies inside the frame
+    if (x0 >= R && y0 >= R && x0 + kNormTW + R <= J.w && y0 + kNormTH + R <= J.h) {
+      constexpr float rn = 1.0f / static_cast<float>(NC * NC);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        float sm = 0.0f;
+#pragma unroll
+        for (int r = 0; r < NC; ++r) sm += hs[k + r];
+        const float mu = sm * rn;
+        float q = 0.0f;
+#pragma unroll
+        for (int r = 0; r < NC; ++r) {
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            const float d = pv[k + r][c] - mu;
+            q = fmaf(d, d, q);
+          }
+        }
+        Px<TS>::st(out + k * J.out_pitch, (pv[k + R][R] - mu) * __builtin_amdgcn_rsqf(fmaf(q, rn, a.eps)));
+      }
+      return;
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
