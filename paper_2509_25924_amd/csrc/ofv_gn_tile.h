@@ -4,19 +4,27 @@
 // ofv_gn_impl.h; a different work decomposition with far more independent
 // work per lane, for levels too small to give the march enough workgroups.
 //
-// A workgroup of NT lanes (256 or 512) computes a TX x TY tile of the new flow in three
-// phases separated by barriers:
-//  A. every pixel of the tile plus a (KR+1)-pixel halo, evaluated at its
-//     coordinates clamped into the level: input flow (loaded or up-sampled),
-//     the two midpoint bilinear warps, S and T -> LDS.  Because out-of-level
-//     halo pixels repeat their clamped neighbour exactly, the central
-//     differences of phase B reproduce the clamped-index gradient with no
-//     border logic;
-//  B. per (product row, segment of SL output columns): Gx^2, GxGy, Gy^2, Gx b,
-//     Gy b formed from LDS and summed over the horizontal window by running
-//     sums whose leaving terms sit in a register ring -> LDS;
-//  C. per (output column, segment of SLV output rows): running vertical
-//     window sums, damped 2x2 solve, coalesced store of u' and v'.
+// A workgroup of NT lanes computes a TX x TY tile of the new flow in five
+// steps separated by barriers, with one image plane and five product planes
+// in LDS:
+//  A1. every pixel of the tile plus a (KR+1)-pixel halo, evaluated at its
+//      coordinates clamped into the level: input flow (loaded or
+//      up-sampled) and the two midpoint bilinear warps; S -> LDS, while T
+//      and the flow stay in the registers of the lane that computed them.
+//      Because out-of-level halo pixels repeat their clamped neighbour
+//      exactly, the central differences of A2 reproduce the clamped-index
+//      gradient with no border logic;
+//  A2. the same lanes, for the pixels of the product region (tile plus a
+//      KR halo): Gx, Gy from S, b = G . V - T, and the five products Gx^2,
+//      GxGy, Gy^2, Gx b, Gy b (0 outside the level) -> five LDS planes;
+//  B.  per (product row, segment of SL output columns): horizontal window
+//      sums by running sums over the product planes, kept in registers ...
+//  B'. ... and written back over the product planes once every lane has
+//      read its inputs;
+//  C.  per (output column, segment of SLV output rows): running vertical
+//      window sums, damped 2x2 solve, coalesced store of u' and v'.
+// Every product is formed once; only the window sums repeat work at the
+// segment ends.
 #pragma once
 
 #include "ofv_gn_impl.h"
@@ -31,8 +39,9 @@ struct TileGeom {
   static constexpr int LP = EX | 1;           // odd LDS pitch: row-strided lanes hit distinct banks
   static constexpr int PY = TY + 2 * KR;      // product rows
   static constexpr int NE = EX * EY;
-  static constexpr int HP = TX + 1;           // pitch of the horizontal-sum planes
-  static constexpr int LDS_FLOATS = 4 * LP * EY + 5 * PY * HP;
+  static constexpr int PX = TX + 2 * KR;      // product columns
+  static constexpr int PP = PX | 1;           // odd pitch of the product planes
+  static constexpr int LDS_FLOATS = LP * EY + 5 * PY * PP;
 };
 
 // Bilinear sample at (x, y) clamped into a w x h plane, split into the
@@ -82,15 +91,19 @@ __global__ __launch_bounds__(NT)
 __attribute__((amdgpu_waves_per_eu(TileOcc<KR, TX, TY, NT>::value, TileOcc<KR, TX, TY, NT>::value)))
 void gn_tile_kernel(const GnArgs a) {
   using G = TileGeom<KR, TX, TY>;
-  constexpr int NWIN = G::NWIN, EX = G::EX, LP = G::LP, PY = G::PY, HP = G::HP, NE = G::NE;
+  constexpr int NWIN = G::NWIN, EX = G::EX, EY = G::EY, LP = G::LP, PY = G::PY, PP = G::PP, NE = G::NE;
+  constexpr int NSEG = TX / SL;
   static_assert(TX % SL == 0 && TY % SLV == 0, "segments must tile the output");
   static_assert(TX * (TY / SLV) <= NT, "phase C items");
+  constexpr int NIT = (NSEG * PY + NT - 1) / NT;  // phase B items per lane
+  // pixels per lane in A1/A2, and how many of them have their taps in flight at once
+  constexpr int NA = (NE + NT - 1) / NT;
+  constexpr int REGS = 512 / TileOcc<KR, TX, TY, NT>::value;
+  constexpr int CHF = (REGS - 48 - 3 * NA) / 18;
+  constexpr int CH = CHF < 1 ? 1 : (CHF > NA ? NA : CHF);
   extern __shared__ float lds[];
-  float* sS = lds;
-  float* sT = sS + LP * G::EY;
-  float* sU = sT + LP * G::EY;
-  float* sV = sU + LP * G::EY;
-  float* sH = sV + LP * G::EY;  // 5 planes of PY x HP
+  float* sS = lds;           // EY x LP
+  float* sP = lds + LP * EY; // 5 planes of PY x PP: products, then horizontal sums
 
   const int jb = find_job(a, blockIdx.x);
   const GnJob& J = a.job[jb];
@@ -108,30 +121,28 @@ void gn_tile_kernel(const GnArgs a) {
   const int gx0 = x0 - KR - 1;  // level column of ext column 0
   const int gy0 = y0 - KR - 1;
   const int tid = threadIdx.x;
+  const uint32_t fpitch = static_cast<uint32_t>(J.in_pitch);
+  const uint32_t frows = static_cast<uint32_t>(MODE == FLOW_UPSAMPLE ? J.ch : H);
+  const PlaneView vu = plane_view(J.in_u, MODE == FLOW_ZERO ? 0u : fpitch * frows * 4u);
+  const PlaneView vv = plane_view(J.in_v, MODE == FLOW_ZERO ? 0u : fpitch * frows * 4u);
+  const float cwm1 = static_cast<float>(J.cw - 1), chm1 = static_cast<float>(J.ch - 1);
+  const float cwm2 = static_cast<float>(J.cw - 2), chm2 = static_cast<float>(J.ch - 2);
+  const uint32_t csx = J.cw > 1 ? 1u : 0u;
+  const uint32_t csy = J.ch > 1 ? fpitch : 0u;
 
-  // ---- phase A: flow, warps, S, T over the ext region (clamped coordinates).
-  // A lane evaluates up to CH ext pixels at once: the input flow of all of
-  // them is loaded first, then the 8 bilinear taps of each of them are
-  // issued, and only then are any combined, so that a lane has up to 8 CH
-  // gathers in flight.
+  // ---- A1: flow, warps and S over the ext region; T, U, V kept per lane.
+  // A lane evaluates CH ext pixels at once: the input flow of all of them
+  // is loaded first, then the 8 bilinear taps of each are issued, and only
+  // then are any combined, so up to 8 CH gathers are in flight per lane.
+  float kT[NA], kU[NA], kV[NA];
   {
-    constexpr int NA = (NE + NT - 1) / NT;
-    constexpr int CH = NA <= 16 ? NA : 8;
     constexpr int DY = NT / EX, DX = NT % EX;
     int ey = tid / EX;
     int ex = tid - ey * EX;
-    const uint32_t fpitch = static_cast<uint32_t>(J.in_pitch);
     const uint32_t uip = static_cast<uint32_t>(ip);
     const uint32_t rowb = uip * Px<TS>::bytes;  // byte offset of the second tap row
-    const PlaneView v0 = plane_view(p0, uip * static_cast<uint32_t>(H) * sizeof(TS));
-    const PlaneView v1 = plane_view(p1, uip * static_cast<uint32_t>(H) * sizeof(TS));
-    const uint32_t frows = static_cast<uint32_t>(MODE == FLOW_UPSAMPLE ? J.ch : H);
-    const PlaneView vu = plane_view(J.in_u, MODE == FLOW_ZERO ? 0u : fpitch * frows * 4u);
-    const PlaneView vv = plane_view(J.in_v, MODE == FLOW_ZERO ? 0u : fpitch * frows * 4u);
-    const float cwm1 = static_cast<float>(J.cw - 1), chm1 = static_cast<float>(J.ch - 1);
-    const float cwm2 = static_cast<float>(J.cw - 2), chm2 = static_cast<float>(J.ch - 2);
-    const uint32_t csx = J.cw > 1 ? 1u : 0u;
-    const uint32_t csy = J.ch > 1 ? fpitch : 0u;
+    const PlaneView v0 = plane_view(p0, uip * static_cast<uint32_t>(H) * Px<TS>::bytes);
+    const PlaneView v1 = plane_view(p1, uip * static_cast<uint32_t>(H) * Px<TS>::bytes);
 #pragma unroll
     for (int k0 = 0; k0 < NA; k0 += CH) {
       float uu[CH], vv2[CH], fx[CH], fy[CH];
@@ -163,17 +174,17 @@ void gn_tile_kernel(const GnArgs a) {
         float cu[CH][4], cv[CH][4], wx[CH], wy[CH];
 #pragma unroll
         for (int k = 0; k < CH; ++k) {
-          const BilTap t = bil_setup(0.5f * fx[k], 0.5f * fy[k], cwm1, chm1, cwm2, chm2, fpitch);
-          wx[k] = t.ax;
-          wy[k] = t.ay;
-          cu[k][0] = ld_f32(vu, t.i);
-          cu[k][1] = ld_f32(vu, t.i + csx);
-          cu[k][2] = ld_f32(vu, t.i + csy);
-          cu[k][3] = ld_f32(vu, t.i + csy + csx);
-          cv[k][0] = ld_f32(vv, t.i);
-          cv[k][1] = ld_f32(vv, t.i + csx);
-          cv[k][2] = ld_f32(vv, t.i + csy);
-          cv[k][3] = ld_f32(vv, t.i + csy + csx);
+          const BilTap tp = bil_setup(0.5f * fx[k], 0.5f * fy[k], cwm1, chm1, cwm2, chm2, fpitch);
+          wx[k] = tp.ax;
+          wy[k] = tp.ay;
+          cu[k][0] = ld_f32(vu, tp.i);
+          cu[k][1] = ld_f32(vu, tp.i + csx);
+          cu[k][2] = ld_f32(vu, tp.i + csy);
+          cu[k][3] = ld_f32(vu, tp.i + csy + csx);
+          cv[k][0] = ld_f32(vv, tp.i);
+          cv[k][1] = ld_f32(vv, tp.i + csx);
+          cv[k][2] = ld_f32(vv, tp.i + csy);
+          cv[k][3] = ld_f32(vv, tp.i + csy + csx);
         }
 #pragma unroll
         for (int k = 0; k < CH; ++k) {
@@ -205,74 +216,120 @@ void gn_tile_kernel(const GnArgs a) {
       }
 #pragma unroll
       for (int k = 0; k < CH; ++k) {
-        if (k0 + k < NA && tid + NT * (k0 + k) < NE) {
+        if (k0 + k < NA) {
           const float w0 = bil_combine(g0[k][0], g0[k][1], g0[k][2], g0[k][3], a0x[k], a0y[k]);
           const float w1 = bil_combine(g1[k][0], g1[k][1], g1[k][2], g1[k][3], a1x[k], a1y[k]);
-          sS[oo[k]] = 0.5f * (w0 + w1);
-          sT[oo[k]] = w1 - w0;
-          sU[oo[k]] = uu[k];
-          sV[oo[k]] = vv2[k];
+          kT[k0 + k] = w1 - w0;
+          kU[k0 + k] = uu[k];
+          kV[k0 + k] = vv2[k];
+          if (tid + NT * (k0 + k) < NE) sS[oo[k]] = 0.5f * (w0 + w1);
         }
       }
     }
   }
   __syncthreads();
 
-  // ---- phase B: products and horizontal window sums, item = (product row, segment)
+  // ---- A2: gradients, b and the five products of the product-region pixels
   {
-    constexpr int NSEG = TX / SL;
-    constexpr int NITEM = NSEG * PY;
-    for (int item = tid; item < NITEM; item += NT) {
-      const int r = item % PY;  // product row r = ext row r + 1
-      const int sg = item / PY;
-      const int xs = sg * SL;   // first product column of the first output's window
-      const bool row_in = static_cast<unsigned>(gy0 + r + 1) < static_cast<unsigned>(H);
-      const int base = (r + 1) * LP + xs + 1;  // LDS index of ext (r + 1, xs + 1)
-      const int gxs = gx0 + xs + 1;           // level column of that pixel
-      float ring[5][NWIN];
-      float acc[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-      for (int k = 0; k < SL + 2 * KR; ++k) {
-        const int o = base + k;
-        const bool valid = row_in && static_cast<unsigned>(gxs + k) < static_cast<unsigned>(W);
+    for (int k = 0; k < NA; ++k) {
+      const int i = tid + NT * k;
+      const int ey = i / EX;
+      const int ex = i - ey * EX;
+      if (i < NE && ex >= 1 && ex <= EX - 2 && ey >= 1 && ey <= EY - 2) {
+        const int o = ey * LP + ex;
+        const bool valid = static_cast<unsigned>(gx0 + ex) < static_cast<unsigned>(W) &&
+                           static_cast<unsigned>(gy0 + ey) < static_cast<unsigned>(H);
         float gx = 0.5f * (sS[o + 1] - sS[o - 1]);
         float gy = 0.5f * (sS[o + LP] - sS[o - LP]);
         gx = valid ? gx : 0.0f;
         gy = valid ? gy : 0.0f;
-        const float b = fmaf(gx, sU[o], fmaf(gy, sV[o], -sT[o]));
-        const float p[5] = {gx * gx, gx * gy, gy * gy, gx * b, gy * b};
-#pragma unroll
-        for (int q = 0; q < 5; ++q) {
-          if (k >= NWIN) acc[q] -= ring[q][k % NWIN];
-          ring[q][k % NWIN] = p[q];
-          acc[q] += p[q];
-        }
-        if (k >= 2 * KR) {
-          const int j = xs + k - 2 * KR;  // output column
-#pragma unroll
-          for (int q = 0; q < 5; ++q) sH[(q * PY + r) * HP + j] = acc[q];
-        }
+        const float b = fmaf(gx, kU[k], fmaf(gy, kV[k], -kT[k]));
+        const int po = (ey - 1) * PP + (ex - 1);
+        sP[po] = gx * gx;
+        sP[po + PY * PP] = gx * gy;
+        sP[po + 2 * PY * PP] = gy * gy;
+        sP[po + 3 * PY * PP] = gx * b;
+        sP[po + 4 * PY * PP] = gy * b;
       }
     }
   }
   __syncthreads();
 
-  // ---- phase C: vertical window sums, solve, store; item = (output column, segment)
+  // ---- B: horizontal window sums, item = (product row, segment of SL outputs)
+  float hsum[NIT][5][SL];
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int item = tid + NT * it;
+    if (item < NSEG * PY) {
+      const float* row = sP + (item % PY) * PP + (item / PY) * SL;  // product column of the first window
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        float ring[NWIN];
+        float acc = 0.0f;
+#pragma unroll
+        for (int k = 0; k < SL + 2 * KR; ++k) {
+          const float pq = row[q * PY * PP + k];
+          if (k >= NWIN) acc -= ring[k % NWIN];
+          ring[k % NWIN] = pq;
+          acc += pq;
+          if (k >= 2 * KR) hsum[it][q][k - 2 * KR] = acc;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // ---- B': the sums of output column j of product row r go to plane column j
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int item = tid + NT * it;
+    if (item < NSEG * PY) {
+      float* row = sP + (item % PY) * PP + (item / PY) * SL;
+#pragma unroll
+      for (int q = 0; q < 5; ++q)
+#pragma unroll
+        for (int jj = 0; jj < SL; ++jj) row[q * PY * PP + jj] = hsum[it][q][jj];
+    }
+  }
+  __syncthreads();
+
+  // ---- C: vertical window sums, solve, store; item = (output column, segment)
   {
     constexpr int NSEGV = TY / SLV;
     const int j = tid % TX;
     const int sg = tid / TX;
     const int gx = x0 + j;
     if (sg < NSEGV && gx < W) {
+      const int rs = sg * SLV;  // first product row of the first output's window
+      // flow at the outputs (the damping anchor V(m)), loaded ahead of the sums
+      float um[SLV], vm[SLV];
+#pragma unroll
+      for (int k = 0; k < SLV; ++k) {
+        const int gy = min(y0 + rs + k, H - 1);
+        if (MODE == FLOW_DIRECT) {
+          const uint32_t o = __umul24(static_cast<uint32_t>(gy), fpitch) + static_cast<uint32_t>(gx);
+          um[k] = ld_f32(vu, o);
+          vm[k] = ld_f32(vv, o);
+        } else if (MODE == FLOW_UPSAMPLE) {
+          const BilTap tp = bil_setup(0.5f * static_cast<float>(gx), 0.5f * static_cast<float>(gy), cwm1, chm1,
+                                      cwm2, chm2, fpitch);
+          um[k] = 2.0f * bil_combine(ld_f32(vu, tp.i), ld_f32(vu, tp.i + csx), ld_f32(vu, tp.i + csy),
+                                     ld_f32(vu, tp.i + csy + csx), tp.ax, tp.ay);
+          vm[k] = 2.0f * bil_combine(ld_f32(vv, tp.i), ld_f32(vv, tp.i + csx), ld_f32(vv, tp.i + csy),
+                                     ld_f32(vv, tp.i + csy + csx), tp.ax, tp.ay);
+        } else {
+          um[k] = 0.0f;
+          vm[k] = 0.0f;
+        }
+      }
       float ring[5][NWIN];
       float acc[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-      const int rs = sg * SLV;  // first product row of the first output's window
 #pragma unroll
       for (int k = 0; k < SLV + 2 * KR; ++k) {
         const int r = rs + k;
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
-          const float hq = sH[(q * PY + r) * HP + j];
+          const float hq = sP[(q * PY + r) * PP + j];
           if (k >= NWIN) acc[q] -= ring[q][k % NWIN];
           ring[q][k % NWIN] = hq;
           acc[q] += hq;
@@ -281,11 +338,9 @@ void gn_tile_kernel(const GnArgs a) {
           const int oy = rs + k - 2 * KR;  // output row within the tile
           const int gy = y0 + oy;
           if (gy < H) {
-            const int o = (oy + KR + 1) * LP + (j + KR + 1);
-            const float um = sU[o];
-            const float vm = sV[o];
             float un, vn;
-            solve2x2(acc[0], acc[1], acc[2], acc[3], acc[4], um, vm, a.reg_rel, a.reg_abs, un, vn);
+            solve2x2(acc[0], acc[1], acc[2], acc[3], acc[4], um[k - 2 * KR], vm[k - 2 * KR], a.reg_rel, a.reg_abs,
+                     un, vn);
             const int64_t oo = static_cast<int64_t>(gy) * J.out_pitch + gx;
             J.out_u[oo] = un;
             J.out_v[oo] = vn;
