@@ -454,9 +454,23 @@ def main():
     fin = out.clone()
     for _ in range(10):
         ofv.stage_gn_iteration(p0, p1, fin, "direct", kr, prm["reg_rel"], prm["reg_abs"], handle=handle)
+    # a pair of events around the timed loop of back-to-back launches gives
+    # the average launch duration the roofline uses; an event pair around each
+    # launch of a second loop (one queue barrier per event, so slightly
+    # longer) is reported beside it
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.kernel_launches)]
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
+    ev0.record()
+    for a, b in evs:
+        a.record()
+        ofv.stage_gn_iteration(p0, p1, fin, "direct", kr, prm["reg_rel"], prm["reg_abs"], handle=handle)
+        b.record()
+    ev1.record()
+    torch.cuda.synchronize()
+    pair_s = sum(a.elapsed_time(b) for a, b in evs) / 1e3 / args.kernel_launches
     ev0.record()
     for _ in range(args.kernel_launches):
         ofv.stage_gn_iteration(p0, p1, fin, "direct", kr, prm["reg_rel"], prm["reg_abs"], handle=handle)
@@ -516,7 +530,8 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(args.workload, args.storage, decomp),
                      "kernel": f"Gauss-Newton iteration, {decomp}, KR {kr}, {args.storage}, full resolution {w}x{h}",
-                     "bytes_per_launch": algo_bytes, "us_per_launch": round(kern_s * 1e6, 3)},
+                     "bytes_per_launch": algo_bytes, "us_per_launch": round(kern_s * 1e6, 3),
+                     "us_event_pair_per_launch": round(pair_s * 1e6, 3)},
     }
 
     if not args.no_cpu_baseline:

@@ -74,6 +74,16 @@ __device__ __forceinline__ float bil_combine(float p00, float p01, float p10, fl
   return fmaf(ay, bot - top, top);
 }
 
+// Workgroups are handed to the 8 XCDs of the chip in turn (workgroup i to
+// XCD i mod 8), and each XCD has its own L2.  Tile l of a job of n tiles is
+// renumbered so that the workgroups of one XCD take a contiguous run of
+// row-major tiles: neighbours then share their halo rows and columns in one
+// L2 instead of fetching them from HBM once per XCD.
+__device__ __forceinline__ int xcd_tile(int l, int n) {
+  const int q = n >> 3;
+  return l < 8 * q ? (l & 7) * q + (l >> 3) : l;
+}
+
 // Waves per SIMD that the LDS of one NT-lane workgroup leaves room for
 // (160 KiB per compute unit, NT / 256 waves of each workgroup per SIMD):
 // the register budget of the kernel is sized for that occupancy.
@@ -114,8 +124,8 @@ void gn_tile_kernel(const GnArgs a) {
   const int H = J.h;
   const float wm1 = static_cast<float>(W - 1), hm1 = static_cast<float>(H - 1);
   const float wm2 = static_cast<float>(W - 2), hm2 = static_cast<float>(H - 2);
-  const int t = blockIdx.x - J.tile_start;
   const int ntx = (W + TX - 1) / TX;
+  const int t = xcd_tile(blockIdx.x - J.tile_start, ntx * ((H + TY - 1) / TY));
   const int x0 = (t % ntx) * TX;
   const int y0 = (t / ntx) * TY;
   const int gx0 = x0 - KR - 1;  // level column of ext column 0
