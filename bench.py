@@ -27,6 +27,19 @@ GN_NAMES = {0: "march", 1: "tile64x32", 2: "tile64x16", 3: "tile32x16", 4: "tile
 GN_SOURCES = ["ofv_gn_impl.h", "ofv_gn_tile.h", "ofv_px.h", "ofv_internal.h"]
 
 
+def host_cpu():
+    """Model name of the host CPU and its logical core count."""
+    name = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                name = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return f"{name}, {os.cpu_count()} logical cores"
+
+
 def gn_source_digest():
     """sha256 over the sources of the Gauss-Newton kernels (a traffic figure is valid for one digest only)."""
     import hashlib
@@ -48,7 +61,7 @@ def measured_traffic(workload, storage, decomposition):
         parts = line.strip().strip("|").split("|")
         if line.startswith("source digest:"):
             digest = line.split(":", 1)[1].strip()
-        elif len(parts) >= 5 and parts[0].strip() in GN_NAMES.values():
+        elif len(parts) >= 4 and parts[0].strip() in GN_NAMES.values():
             try:
                 table[parts[0].strip()] = int(parts[-1].strip())
             except ValueError:
@@ -135,13 +148,14 @@ def suite_batch4mp(args, dev):
     import synth
     from synth.gpu_render import make_pair_device
     n_distinct, n = 8, 64
-    f0s, f1s = [], []
-    gt0 = None
+    f0s, f1s, gts = [], [], {}
+    checked = (0, 21, 42, 63)                      # pairs whose accuracy is measured against the oracle
     for t in range(n_distinct):
         flow = synth.Turbulence(seed=3, rms=2.0, dmax_cap=8.0, ref_h=256, ref_w=256, t=float(t))
+        want_gt = any(c % n_distinct == t for c in checked)
         a, b, gt = make_pair_device(2048, 2048, flow, fwhm=2.5, ppp=0.1, seed=3000 + t, bit_depth=12,
-                                    noise=0.01 * 4095, device=dev, max_disp=8.0, with_gt=(t == 0))
-        gt0 = gt if t == 0 else gt0
+                                    noise=0.01 * 4095, device=dev, max_disp=8.0, with_gt=want_gt)
+        gts[t] = gt
         f0s.append(a)
         f1s.append(b)
     f0s = [f0s[i % n_distinct] for i in range(n)]
@@ -151,43 +165,47 @@ def suite_batch4mp(args, dev):
     hb = ofv.Handle(2048, 2048, n)
     res = {}
     for storage in ("f16", "f32"):
-        for variant in ("tile64x16", "tile64x32", "march"):
+        for variant in ("auto", "tile64x16", "tile64x32", "tile64x16w", "tile64x32w", "march"):
             hb.set_gn_variant(variant)
             p = dict(prm, storage=storage)
             sec = _timed(lambda: ofv.compute_flow_batch(f0s, f1s, p, bit_depth=12, outs=outs, handle=hb), 3, 1)
             res[f"{storage}/{variant}"] = sec
     best = min((v, k) for k, v in res.items() if k.startswith("f16"))
-    # accuracy on pair 0 of the FP16 and FP32 results against the FP64 oracle and the ground truth;
-    # the floor is the FP64 oracle with its image planes rounded to FP16 (the error that FP16
-    # storage causes by itself); "converged" pixels are those where the oracle's own endpoint
-    # error against the ground truth is at most 1 px
+    # accuracy of pairs 0, 21, 42 and 63 in FP16 and FP32 against the FP64 oracle and the ground truth;
+    # the floor is the FP64 oracle with its image planes rounded to FP16 (the error that FP16 storage
+    # causes by itself); "converged" pixels are those where the oracle's own endpoint error against the
+    # ground truth is at most 1 px
     import numpy as np
     import oracle
     hb.set_gn_variant("auto")
-    fr0 = f0s[0].cpu().numpy().astype(np.uint16)
-    fr1 = f1s[0].cpu().numpy().astype(np.uint16)
-    vor = oracle.compute_flow(fr0, fr1, prm, bit_depth0=12).numpy()
-    v_floor = oracle.compute_flow(fr0, fr1, prm, bit_depth0=12, plane_round="f16").numpy()
     bnd = 4 * 2 ** 4
     inner = (slice(None), slice(bnd, -bnd), slice(bnd, -bnd))
-    rms_orc = float(np.sqrt(np.mean((vor - gt0)[inner] ** 2)))
-    conv = np.sqrt(((vor - gt0) ** 2).sum(0)) <= 1.0
+    acc = {}
+    for c in checked:
+        gt0 = gts[c % n_distinct]
+        fr0 = f0s[c].cpu().numpy().astype(np.uint16)
+        fr1 = f1s[c].cpu().numpy().astype(np.uint16)
+        vor = oracle.compute_flow(fr0, fr1, prm, bit_depth0=12).numpy()
+        v_floor = oracle.compute_flow(fr0, fr1, prm, bit_depth0=12, plane_round="f16").numpy()
+        rms_orc = float(np.sqrt(np.mean((vor - gt0)[inner] ** 2)))
+        conv = np.sqrt(((vor - gt0) ** 2).sum(0)) <= 1.0
 
-    def stats(v, tol):
-        d = np.abs(v - vor).max(axis=0)
-        rms = float(np.sqrt(np.mean((v - gt0)[inner] ** 2)))
-        return {"max_abs_vs_oracle_px": round(float(d.max()), 5),
-                "max_abs_converged_px": round(float(d[conv].max()), 5),
-                "p99_99_abs_vs_oracle_px": round(float(np.quantile(d, 0.9999)), 6),
-                f"frac_over_{tol:g}": float(np.mean(d > tol)),
-                f"frac_over_{tol:g}_converged": float(np.mean(d[conv] > tol)),
-                "rms_vs_gt_px": round(rms, 5), "rms_ratio_vs_oracle": round(rms / rms_orc, 4)}
+        def stats(v, tol):
+            d = np.abs(v - vor).max(axis=0)
+            rms = float(np.sqrt(np.mean((v - gt0)[inner] ** 2)))
+            return {"max_abs_vs_oracle_px": round(float(d.max()), 5),
+                    "max_abs_converged_px": round(float(d[conv].max()), 5),
+                    "p99_99_abs_vs_oracle_px": round(float(np.quantile(d, 0.9999)), 6),
+                    f"frac_over_{tol:g}": float(np.mean(d > tol)),
+                    f"frac_over_{tol:g}_converged": float(np.mean(d[conv] > tol)),
+                    "rms_vs_gt_px": round(rms, 5), "rms_ratio_vs_oracle": round(rms / rms_orc, 4)}
 
-    acc = {"pair": 0, "rms_vs_gt_oracle_px": round(rms_orc, 5), "frac_converged": float(conv.mean()),
-           "floor_f16_planes": stats(v_floor, 2e-2)}
-    for st, tol in (("f16", 2e-2), ("f32", 1e-3)):
-        v = ofv.compute_flow_batch(f0s[:1], f1s[:1], dict(prm, storage=st), bit_depth=12, handle=hb)[0]
-        acc[st] = stats(v.cpu().double().numpy(), tol)
+        row = {"rms_vs_gt_oracle_px": round(rms_orc, 5), "frac_converged": float(conv.mean()),
+               "floor_f16_planes": stats(v_floor, 2e-2)}
+        for st, tol in (("f16", 2e-2), ("f32", 1e-3)):
+            v = ofv.compute_flow_batch(f0s[c:c + 1], f1s[c:c + 1], dict(prm, storage=st), bit_depth=12, handle=hb)[0]
+            row[st] = stats(v.cpu().double().numpy(), tol)
+        acc[f"pair{c}"] = row
     # the plain FP32 single-pair path on the same pairs
     h1 = ofv.Handle(2048, 2048, 1)
     h1.autotune(f0s[0], f1s[0], dict(prm, storage="f32"), bit_depth=12, repeats=2)
@@ -205,48 +223,56 @@ def suite_batch4mp(args, dev):
 
 
 def suite_live21mp(args, dev):
-    """21 Mp cylinder-wake frames, uneven batch {5120x4096, 2048^2 crop, 1024^2 crop} per step, hipGraph loop."""
+    """21 Mp cylinder-wake frames, uneven batch {5120x4096, 2048^2 crop, 1024^2 crop} per step, hipGraph loop;
+    compute-only and streaming (one new 12-bit frame per step uploaded from a pinned host ring while the
+    previous step computes)."""
+    import numpy as np
     import torch
     import paper_2509_25924_amd as ofv
+    import oracle
     import synth
     from synth.gpu_render import make_pair_device
     W, H = 5120, 4096
     phases = 16
-    pairs = []
+    pairs, gt0 = [], None
     for ph in range(phases):
         flow = synth.CylinderWake(H, W, t=200.0 * ph / phases, dmax=10.0)
-        pairs.append(make_pair_device(H, W, flow, fwhm=2.5, ppp=0.1, seed=4000 + ph, bit_depth=12,
-                                      noise=0.01 * 4095, device=dev, max_disp=10.0)[:2])
+        a, b, gt = make_pair_device(H, W, flow, fwhm=2.5, ppp=0.1, seed=4000 + ph, bit_depth=12,
+                                    noise=0.01 * 4095, device=dev, max_disp=10.0, with_gt=(ph == 0))
+        pairs.append((a, b))
+        gt0 = gt if ph == 0 else gt0
     prm = {"num_levels": 4, "kernel_radius": 10, "iterations": 3, "norm_radius": 2}
     hb = ofv.Handle(W, H, 3)
     outs = [torch.empty((2, H, W), dtype=torch.float32, device=dev),
             torch.empty((2, 2048, 2048), dtype=torch.float32, device=dev),
             torch.empty((2, 1024, 1024), dtype=torch.float32, device=dev)]
+    crop2 = (slice(1024, 3072), slice(1536, 3584))
+    crop1 = (slice(1536, 2560), slice(2048, 3072))
 
-    def batch(ph, p):
-        a, b = pairs[ph]
-        f0 = [a, a[1024:3072, 1536:3584], a[1536:2560, 2048:3072]]
-        f1 = [b, b[1024:3072, 1536:3584], b[1536:2560, 2048:3072]]
+    def batch_of(a, b, p):
+        f0 = [a, a[crop2], a[crop1]]
+        f1 = [b, b[crop2], b[crop1]]
         ofv.compute_flow_batch(f0, f1, p, bit_depth=12, outs=outs, handle=hb)
 
-    res = {}
+    def capture(fn):
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            fn()
+        torch.cuda.current_stream().wait_stream(s)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            fn()
+        hb.bind_stream()
+        return g
+
+    res, acc = {}, {}
     steps = 500
     for storage in ("bf16", "f32"):
         p = dict(prm, storage=storage)
-        for variant in ("tile64x32", "march"):
+        for variant in ("auto", "tile64x32", "tile64x32w", "tile64x16w", "march"):
             hb.set_gn_variant(variant)
-            graphs = []
-            s = torch.cuda.Stream()
-            s.wait_stream(torch.cuda.current_stream())
-            with torch.cuda.stream(s):
-                batch(0, p)
-            torch.cuda.current_stream().wait_stream(s)
-            for ph in range(phases):
-                g = torch.cuda.CUDAGraph()
-                with torch.cuda.graph(g):
-                    batch(ph, p)
-                graphs.append(g)
-            hb.bind_stream()
+            graphs = [capture(lambda ph=ph: batch_of(*pairs[ph], p)) for ph in range(phases)]
             k = [0]
 
             def step():
@@ -254,13 +280,78 @@ def suite_live21mp(args, dev):
                 k[0] += 1
             res[f"{storage}/{variant}"] = _timed(step, steps, 16)
             del graphs
-    best = min(res.values())
+        # accuracy of the 1024^2 crop of phase 0 against the FP64 oracle (default decomposition)
+        hb.set_gn_variant("auto")
+        batch_of(*pairs[0], p)
+        v = outs[2].cpu().double().numpy()
+        a0 = pairs[0][0][crop1].cpu().numpy().astype(np.uint16)
+        b0 = pairs[0][1][crop1].cpu().numpy().astype(np.uint16)
+        ref = oracle.compute_flow(a0, b0, prm, bit_depth0=12).numpy()
+        d = np.abs(v - ref).max(axis=0)
+        g = gt0[(slice(None),) + crop1]
+        rms = lambda x: float(np.sqrt(np.mean((x - g)[:, 80:-80, 80:-80] ** 2)))
+        acc[storage] = {"max_abs_vs_oracle_px": round(float(d.max()), 5),
+                        "p99_99_abs_vs_oracle_px": round(float(np.quantile(d, 0.9999)), 6),
+                        "frac_over_1e-3": float(np.mean(d > 1e-3)), "frac_over_2e-2": float(np.mean(d > 2e-2)),
+                        "rms_vs_gt_px": round(rms(v), 5), "rms_vs_gt_oracle_px": round(rms(ref), 5)}
+    best_key = min(res, key=res.get)
+    best = res[best_key]
     per = {k: round(1.0 / v, 1) for k, v in res.items()}
     vec = W * H + 2048 * 2048 + 1024 * 1024
+
+    # streaming: frame j of the sequence is phase j's frame 0; step k computes the pair (frame k,
+    # frame k+1) from a ring of three device frames while frame k+2 is copied in on a second stream
+    storage, variant = best_key.split("/")
+    p = dict(prm, storage=storage)
+    hb.set_gn_variant(variant)
+    nhost = 4
+    host = [torch.empty((H, W), dtype=torch.int16, pin_memory=True) for _ in range(nhost)]
+    for j in range(nhost):
+        host[j].copy_(pairs[j][0])
+    ring = [torch.empty((H, W), dtype=torch.int16, device=dev) for _ in range(3)]
+    for j in range(2):
+        ring[j].copy_(host[j])
+    graphs = [capture(lambda r=r: batch_of(ring[r], ring[(r + 1) % 3], p)) for r in range(3)]
+    copy_stream = torch.cuda.Stream()
+    comp = torch.cuda.current_stream()
+    done = [torch.cuda.Event() for _ in range(3)]      # compute that last read ring slot r has finished
+    ready = [torch.cuda.Event() for _ in range(3)]     # ring slot r holds its frame
+    for r in range(3):
+        done[r].record(comp)
+        ready[r].record(comp)
+    ks = [0]
+
+    def stream_step():
+        k = ks[0]
+        nxt = (k + 2) % 3
+        with torch.cuda.stream(copy_stream):
+            copy_stream.wait_event(done[nxt])
+            ring[nxt].copy_(host[(k + 2) % nhost], non_blocking=True)
+            ready[nxt].record(copy_stream)
+        comp.wait_event(ready[k % 3])
+        comp.wait_event(ready[(k + 1) % 3])
+        graphs[k % 3].replay()
+        done[k % 3].record(comp)
+        done[(k + 1) % 3].record(comp)
+        ks[0] += 1
+    sec_stream = _timed(stream_step, steps, 16)
+    t0 = time.perf_counter()
+    for _ in range(20):
+        ring[0].copy_(host[0], non_blocking=True)
+    torch.cuda.synchronize()
+    h2d = 20 * ring[0].numel() * 2 / (time.perf_counter() - t0) / 1e9
+    byts = (_sweep_bytes(4, W, H, 3, 2 if storage != "f32" else 4, 2) + _sweep_bytes(4, 2048, 2048, 3, 2 if storage != "f32" else 4, 2)
+            + _sweep_bytes(4, 1024, 1024, 3, 2 if storage != "f32" else 4, 2))
     return {"metric": "live steps/s (5120x4096 + 2048^2 + 1024^2 uneven batch per step, hipGraph)",
-            "value": round(1.0 / best, 1), "unit": "steps/s", "steps": steps,
+            "value": round(1.0 / best, 1), "unit": "steps/s", "steps": steps, "best": best_key,
             "gvectors_per_s": round(vec / best / 1e9, 3), "steps_per_s_by_config": per,
             "fields_per_s_each_size": round(1.0 / best, 1),
+            "step_algorithmic_GBps": round(byts / best / 1e9, 1),
+            "streaming_steps_per_s": round(1.0 / sec_stream, 1),
+            "streaming": "one new 12-bit 5120x4096 frame (42 MB) per step, pinned host ring -> 3 device slots, "
+                         "copy stream overlapped with the graph replay",
+            "h2d_GBps_pinned": round(h2d, 1),
+            "accuracy_1024_crop": acc,
             "data": "synthetic: 16 phases of a cylinder wake (potential flow + Lamb-Oseen street, max 10 px)"}
 
 
@@ -320,8 +411,11 @@ def suite_paper(args, dev):
                     ofv.compute_flow(a, b, prm, bit_depth=8, out=out, handle=hd)
                     k[0] += 1
                 sec = _timed(one, 40 if w * h > 4 << 20 else 200, 5)
+                byts = _sweep_bytes(levels, w, h, 3, 4 if storage == "f32" else 2, 1)
                 rows.append({"size": f"{w}x{h}", "psl": levels - 1, "storage": storage,
-                             "fields_per_s": round(1.0 / sec, 1), "mvectors_per_s": round(w * h / sec / 1e6, 1)})
+                             "fields_per_s": round(1.0 / sec, 1), "mvectors_per_s": round(w * h / sec / 1e6, 1),
+                             "algorithmic_GBps": round(byts / sec / 1e9, 1),
+                             "frac_of_8TBps": round(byts / sec / 8e12, 4)})
         hd.close()
     return {"metric": "fields/s at the paper's throughput setting (NR 2, KR 10, IT 3)", "rows": rows,
             "paper_rtx5090_offline_fields_per_s": {"1Mp": [1100, 1800], "4Mp": [400, 500], "21Mp": [80, 99]},
@@ -546,7 +640,7 @@ def main():
         result["cpu_baseline"] = {"value": round(runs * w * h / t_cpu / 1e6, 4), "unit": "Mvectors/s",
                                   "cores": nthreads, "kind": "oracle",
                                   "sample": f"{runs} run(s) of the FP64 oracle on the same {w}x{h} pair "
-                                            f"({t_cpu:.1f} s)"}
+                                            f"({t_cpu:.1f} s)", "host": host_cpu()}
     print(json.dumps(result), flush=True)
 
 
