@@ -109,7 +109,7 @@ void gn_tile_kernel(const GnArgs a) {
   // pixels per lane in A1/A2, and how many of them have their taps in flight at once
   constexpr int NA = (NE + NT - 1) / NT;
   constexpr int REGS = 512 / TileOcc<KR, TX, TY, NT>::value;
-  constexpr int CHF = (REGS - 48 - 3 * NA) / 18;
+  constexpr int CHF = (REGS - 48 - 3 * NA) / (MODE == FLOW_UPSAMPLE ? 26 : 20);
   constexpr int CH = CHF < 1 ? 1 : (CHF > NA ? NA : CHF);
   extern __shared__ float lds[];
   float* sS = lds;           // EY x LP
@@ -215,14 +215,10 @@ void gn_tile_kernel(const GnArgs a) {
         a1y[k] = t1.ay;
         // levels are at least 2 x 2 here (the host sends thinner ones to
         // the march): the taps are (i, i + 1) on rows iy and iy + 1
-        g0[k][0] = Px<TS>::ldv(v0, t0.i);
-        g0[k][1] = Px<TS>::ldv(v0, t0.i + 1);
-        g0[k][2] = Px<TS>::ldvs(v0, t0.i, rowb);
-        g0[k][3] = Px<TS>::ldvs(v0, t0.i + 1, rowb);
-        g1[k][0] = Px<TS>::ldv(v1, t1.i);
-        g1[k][1] = Px<TS>::ldv(v1, t1.i + 1);
-        g1[k][2] = Px<TS>::ldvs(v1, t1.i, rowb);
-        g1[k][3] = Px<TS>::ldvs(v1, t1.i + 1, rowb);
+        Px<TS>::ld2(v0, t0.i, 0, g0[k][0], g0[k][1]);
+        Px<TS>::ld2(v0, t0.i, rowb, g0[k][2], g0[k][3]);
+        Px<TS>::ld2(v1, t1.i, 0, g1[k][0], g1[k][1]);
+        Px<TS>::ld2(v1, t1.i, rowb, g1[k][2], g1[k][3]);
       }
 #pragma unroll
       for (int k = 0; k < CH; ++k) {
@@ -375,7 +371,7 @@ hipError_t launch_gn_tile_cfg(const GnArgs& a, int nblocks, hipStream_t s) {
 }
 
 // variant GN_TILE_64x32: 64 x 32 outputs, 512 lanes (segments 8 columns / 4 rows);
-// variant GN_TILE_64x16: 64 x 16 outputs, 256 lanes (segments 16 columns / 4 rows);
+// variant GN_TILE_64x16: 64 x 16 outputs, 256 lanes (segments 8 columns / 4 rows);
 // variant GN_TILE_32x16: 32 x 16 outputs, 256 lanes (segments 4 columns / 2 rows);
 // variant GN_TILE_16x16: 16 x 16 outputs, 256 lanes (segments 4 columns / 1 row);
 // variants GN_TILE_64x32W / 64x16W: the same tiles with 1024 / 512 lanes
@@ -388,7 +384,7 @@ hipError_t launch_gn_tile_typed(const GnArgs& a, int kr, int variant, int nblock
   case R:                                                                                           \
     switch (variant) {                                                                              \
       case GN_TILE_64x32: return launch_gn_tile_cfg<R, MODE, TS, 64, 32, 8, 4, 512>(a, nblocks, s);  \
-      case GN_TILE_64x16: return launch_gn_tile_cfg<R, MODE, TS, 64, 16, 16, 4, 256>(a, nblocks, s); \
+      case GN_TILE_64x16: return launch_gn_tile_cfg<R, MODE, TS, 64, 16, 8, 4, 256>(a, nblocks, s);  \
       case GN_TILE_32x16: return launch_gn_tile_cfg<R, MODE, TS, 32, 16, 4, 2, 256>(a, nblocks, s);  \
       case GN_TILE_64x32W: return launch_gn_tile_cfg<R, MODE, TS, 64, 32, 8, 2, 1024>(a, nblocks, s); \
       case GN_TILE_64x16W: return launch_gn_tile_cfg<R, MODE, TS, 64, 16, 8, 2, 512>(a, nblocks, s);  \

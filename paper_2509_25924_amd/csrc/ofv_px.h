@@ -36,6 +36,11 @@ struct Px<float> {
     return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(v, static_cast<int>(i * 4u), static_cast<int>(jb), 0));
   }
   static constexpr uint32_t bytes = 4;
+  // elements i and i + 1 (j a uniform byte offset)
+  static __device__ __forceinline__ void ld2(PlaneView v, uint32_t i, uint32_t jb, float& a, float& b) {
+    a = ldvs(v, i, jb);
+    b = ldvs(v, i + 1, jb);
+  }
   static __device__ __forceinline__ void st(float* p, float v) { *p = v; }
 };
 
@@ -48,6 +53,13 @@ struct Px<_Float16> {
     return static_cast<float>(__builtin_bit_cast(_Float16, b));
   }
   static constexpr uint32_t bytes = 2;
+  // elements i and i + 1 in one 32-bit load (2-byte aligned: buffer accesses
+  // need no natural alignment on gfx9)
+  static __device__ __forceinline__ void ld2(PlaneView v, uint32_t i, uint32_t jb, float& a, float& b) {
+    const uint32_t w = __builtin_amdgcn_raw_buffer_load_b32(v, static_cast<int>(i * 2u), static_cast<int>(jb), 0);
+    a = static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(w & 0xffffu)));
+    b = static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(w >> 16)));
+  }
   static __device__ __forceinline__ void st(_Float16* p, float v) { *p = static_cast<_Float16>(v); }
 };
 
@@ -64,6 +76,13 @@ struct Px<bf16_t> {
     return __uint_as_float(static_cast<uint32_t>(b) << 16);
   }
   static constexpr uint32_t bytes = 2;
+  // elements i and i + 1 in one 32-bit load (2-byte aligned: buffer accesses
+  // need no natural alignment on gfx9)
+  static __device__ __forceinline__ void ld2(PlaneView v, uint32_t i, uint32_t jb, float& a, float& b) {
+    const uint32_t w = __builtin_amdgcn_raw_buffer_load_b32(v, static_cast<int>(i * 2u), static_cast<int>(jb), 0);
+    a = __uint_as_float(w << 16);
+    b = __uint_as_float(w & 0xffff0000u);
+  }
   static __device__ __forceinline__ void st(bf16_t* p, float v) {
     uint32_t u = __float_as_uint(v);
     if ((u & 0x7f800000u) == 0x7f800000u) {
