@@ -39,9 +39,9 @@ struct TileGeom {
   static constexpr int LP = EX | 1;           // odd LDS pitch: row-strided lanes hit distinct banks
   static constexpr int PY = TY + 2 * KR;      // product rows
   static constexpr int NE = EX * EY;
-  static constexpr int PX = TX + 2 * KR;      // product columns
-  static constexpr int PP = PX | 1;           // odd pitch of the product planes
-  static constexpr int LDS_FLOATS = LP * EY + 5 * PY * PP;
+  static constexpr int PLANE = LP * EY;       // one ext-sized LDS plane
+  // the S plane and five product planes, all indexed by ext coordinates
+  static constexpr int LDS_FLOATS = 6 * PLANE;
 };
 
 // Bilinear sample at (x, y) clamped into a w x h plane, split into the
@@ -101,7 +101,7 @@ __global__ __launch_bounds__(NT)
 __attribute__((amdgpu_waves_per_eu(TileOcc<KR, TX, TY, NT>::value, TileOcc<KR, TX, TY, NT>::value)))
 void gn_tile_kernel(const GnArgs a) {
   using G = TileGeom<KR, TX, TY>;
-  constexpr int NWIN = G::NWIN, EX = G::EX, EY = G::EY, LP = G::LP, PY = G::PY, PP = G::PP, NE = G::NE;
+  constexpr int NWIN = G::NWIN, EX = G::EX, EY = G::EY, LP = G::LP, PY = G::PY, PL = G::PLANE, NE = G::NE;
   constexpr int NSEG = TX / SL;
   static_assert(TX % SL == 0 && TY % SLV == 0, "segments must tile the output");
   static_assert(TX * (TY / SLV) <= NT, "phase C items");
@@ -109,11 +109,14 @@ void gn_tile_kernel(const GnArgs a) {
   // pixels per lane in A1/A2, and how many of them have their taps in flight at once
   constexpr int NA = (NE + NT - 1) / NT;
   constexpr int REGS = 512 / TileOcc<KR, TX, TY, NT>::value;
-  constexpr int CHF = (REGS - 48 - 3 * NA) / (MODE == FLOW_UPSAMPLE ? 26 : 20);
+  // registers per pixel in flight: taps and weights, more when the flow is
+  // up-sampled and when 16-bit taps are unpacked (values measured without spills)
+  constexpr int PER = MODE == FLOW_UPSAMPLE ? (sizeof(TS) == 2 ? 28 : 20) : (sizeof(TS) == 2 ? 13 : 10);
+  constexpr int CHF = (REGS - 48 - 3 * NA) / PER;
   constexpr int CH = CHF < 1 ? 1 : (CHF > NA ? NA : CHF);
   extern __shared__ float lds[];
   float* sS = lds;           // EY x LP
-  float* sP = lds + LP * EY; // 5 planes of PY x PP: products, then horizontal sums
+  float* sP = lds + PL;      // 5 planes: products, then horizontal sums (ext coordinates)
 
   const int jb = find_job(a, blockIdx.x);
   const GnJob& J = a.job[jb];
@@ -145,6 +148,8 @@ void gn_tile_kernel(const GnArgs a) {
   // is loaded first, then the 8 bilinear taps of each are issued, and only
   // then are any combined, so up to 8 CH gathers are in flight per lane.
   float kT[NA], kU[NA], kV[NA];
+  int kO[NA];      // LDS offset of each pixel of the lane
+  uint32_t kF = 0; // bit 2k: pixel k is in the product region; bit 2k+1: it lies inside the level
   {
     constexpr int DY = NT / EX, DX = NT % EX;
     int ey = tid / EX;
@@ -164,6 +169,16 @@ void gn_tile_kernel(const GnArgs a) {
         fx[k] = static_cast<float>(gx);
         fy[k] = static_cast<float>(gy);
         oo[k] = ey * LP + ex;
+        if (k0 + k < NA) {
+          const bool prod = static_cast<unsigned>(ex - 1) < static_cast<unsigned>(EX - 2) &&
+                            static_cast<unsigned>(ey - 1) < static_cast<unsigned>(EY - 2) &&
+                            tid + NT * (k0 + k) < NE;
+          const bool inl = static_cast<unsigned>(gx0 + ex) < static_cast<unsigned>(W) &&
+                           static_cast<unsigned>(gy0 + ey) < static_cast<unsigned>(H);
+          kO[k0 + k] = oo[k];
+          kF |= (prod ? 1u : 0u) << (2 * (k0 + k));
+          kF |= (inl ? 2u : 0u) << (2 * (k0 + k));
+        }
         if (MODE == FLOW_DIRECT) {
           const uint32_t o = __umul24(static_cast<uint32_t>(gy), fpitch) + static_cast<uint32_t>(gx);
           uu[k] = ld_f32(vu, o);
@@ -239,24 +254,19 @@ void gn_tile_kernel(const GnArgs a) {
   {
 #pragma unroll
     for (int k = 0; k < NA; ++k) {
-      const int i = tid + NT * k;
-      const int ey = i / EX;
-      const int ex = i - ey * EX;
-      if (i < NE && ex >= 1 && ex <= EX - 2 && ey >= 1 && ey <= EY - 2) {
-        const int o = ey * LP + ex;
-        const bool valid = static_cast<unsigned>(gx0 + ex) < static_cast<unsigned>(W) &&
-                           static_cast<unsigned>(gy0 + ey) < static_cast<unsigned>(H);
+      if (kF & (1u << (2 * k))) {
+        const int o = kO[k];
+        const bool valid = kF & (2u << (2 * k));
         float gx = 0.5f * (sS[o + 1] - sS[o - 1]);
         float gy = 0.5f * (sS[o + LP] - sS[o - LP]);
         gx = valid ? gx : 0.0f;
         gy = valid ? gy : 0.0f;
         const float b = fmaf(gx, kU[k], fmaf(gy, kV[k], -kT[k]));
-        const int po = (ey - 1) * PP + (ex - 1);
-        sP[po] = gx * gx;
-        sP[po + PY * PP] = gx * gy;
-        sP[po + 2 * PY * PP] = gy * gy;
-        sP[po + 3 * PY * PP] = gx * b;
-        sP[po + 4 * PY * PP] = gy * b;
+        sP[o] = gx * gx;
+        sP[o + PL] = gx * gy;
+        sP[o + 2 * PL] = gy * gy;
+        sP[o + 3 * PL] = gx * b;
+        sP[o + 4 * PL] = gy * b;
       }
     }
   }
@@ -268,14 +278,15 @@ void gn_tile_kernel(const GnArgs a) {
   for (int it = 0; it < NIT; ++it) {
     const int item = tid + NT * it;
     if (item < NSEG * PY) {
-      const float* row = sP + (item % PY) * PP + (item / PY) * SL;  // product column of the first window
+      // ext column of the first product of the first window: product column c is ext column c + 1
+      const float* row = sP + (item % PY + 1) * LP + 1 + (item / PY) * SL;
 #pragma unroll
       for (int q = 0; q < 5; ++q) {
         float ring[NWIN];
         float acc = 0.0f;
 #pragma unroll
         for (int k = 0; k < SL + 2 * KR; ++k) {
-          const float pq = row[q * PY * PP + k];
+          const float pq = row[q * PL + k];
           if (k >= NWIN) acc -= ring[k % NWIN];
           ring[k % NWIN] = pq;
           acc += pq;
@@ -285,16 +296,16 @@ void gn_tile_kernel(const GnArgs a) {
     }
   }
   __syncthreads();
-  // ---- B': the sums of output column j of product row r go to plane column j
+  // ---- B': the sums of output column j of product row r go to ext column j + 1 of ext row r + 1
 #pragma unroll
   for (int it = 0; it < NIT; ++it) {
     const int item = tid + NT * it;
     if (item < NSEG * PY) {
-      float* row = sP + (item % PY) * PP + (item / PY) * SL;
+      float* row = sP + (item % PY + 1) * LP + 1 + (item / PY) * SL;
 #pragma unroll
       for (int q = 0; q < 5; ++q)
 #pragma unroll
-        for (int jj = 0; jj < SL; ++jj) row[q * PY * PP + jj] = hsum[it][q][jj];
+        for (int jj = 0; jj < SL; ++jj) row[q * PL + jj] = hsum[it][q][jj];
     }
   }
   __syncthreads();
@@ -335,7 +346,7 @@ void gn_tile_kernel(const GnArgs a) {
         const int r = rs + k;
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
-          const float hq = sP[(q * PY + r) * PP + j];
+          const float hq = sP[q * PL + (r + 1) * LP + j + 1];
           if (k >= NWIN) acc[q] -= ring[q][k % NWIN];
           ring[q][k % NWIN] = hq;
           acc[q] += hq;
