@@ -111,7 +111,7 @@ void gn_tile_kernel(const GnArgs a) {
   constexpr int REGS = 512 / TileOcc<KR, TX, TY, NT>::value;
   // registers per pixel in flight: taps and weights, more when the flow is
   // up-sampled and when 16-bit taps are unpacked (values measured without spills)
-  constexpr int PER = MODE == FLOW_UPSAMPLE ? (sizeof(TS) == 2 ? 28 : 20) : (sizeof(TS) == 2 ? 13 : 10);
+  constexpr int PER = MODE == FLOW_UPSAMPLE ? (sizeof(TS) == 2 ? 28 : 20) : (sizeof(TS) == 2 ? 15 : 10);
   constexpr int CHF = (REGS - 48 - 3 * NA) / PER;
   constexpr int CH = CHF < 1 ? 1 : (CHF > NA ? NA : CHF);
   extern __shared__ float lds[];
@@ -250,23 +250,41 @@ void gn_tile_kernel(const GnArgs a) {
   }
   __syncthreads();
 
-  // ---- A2: gradients, b and the five products of the product-region pixels
+  // ---- A2: gradients, b and the five products of the product-region pixels.
+  // The S reads of up to four of the lane's pixels are issued before any is
+  // used (a pixel outside the product region reads an interior dummy and
+  // stores nothing), so the LDS latency is not paid once per pixel.
   {
+    constexpr int C2 = 4;
 #pragma unroll
-    for (int k = 0; k < NA; ++k) {
-      if (kF & (1u << (2 * k))) {
-        const int o = kO[k];
-        const bool valid = kF & (2u << (2 * k));
-        float gx = 0.5f * (sS[o + 1] - sS[o - 1]);
-        float gy = 0.5f * (sS[o + LP] - sS[o - LP]);
-        gx = valid ? gx : 0.0f;
-        gy = valid ? gy : 0.0f;
-        const float b = fmaf(gx, kU[k], fmaf(gy, kV[k], -kT[k]));
-        sP[o] = gx * gx;
-        sP[o + PL] = gx * gy;
-        sP[o + 2 * PL] = gy * gy;
-        sP[o + 3 * PL] = gx * b;
-        sP[o + 4 * PL] = gy * b;
+    for (int k0 = 0; k0 < NA; k0 += C2) {
+      float sxp[C2], sxm[C2], syp[C2], sym[C2];
+#pragma unroll
+      for (int k = 0; k < C2; ++k) {
+        if (k0 + k < NA) {
+          const int o = (kF & (1u << (2 * (k0 + k)))) ? kO[k0 + k] : LP + 1;
+          sxp[k] = sS[o + 1];
+          sxm[k] = sS[o - 1];
+          syp[k] = sS[o + LP];
+          sym[k] = sS[o - LP];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < C2; ++k) {
+        if (k0 + k < NA) {
+          const bool valid = kF & (2u << (2 * (k0 + k)));
+          const float gx = valid ? 0.5f * (sxp[k] - sxm[k]) : 0.0f;
+          const float gy = valid ? 0.5f * (syp[k] - sym[k]) : 0.0f;
+          const float b = fmaf(gx, kU[k0 + k], fmaf(gy, kV[k0 + k], -kT[k0 + k]));
+          if (kF & (1u << (2 * (k0 + k)))) {
+            const int o = kO[k0 + k];
+            sP[o] = gx * gx;
+            sP[o + PL] = gx * gy;
+            sP[o + 2 * PL] = gy * gy;
+            sP[o + 3 * PL] = gx * b;
+            sP[o + 4 * PL] = gy * b;
+          }
+        }
       }
     }
   }
