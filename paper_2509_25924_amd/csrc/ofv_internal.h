@@ -86,18 +86,28 @@ enum GnVariant {
   GN_TILE_32x16 = 3,
   GN_TILE_16x16 = 4,
   GN_TILE_64x32W = 5,
-  GN_TILE_64x16W = 6
+  GN_TILE_64x16W = 6,
+  GN_TILE_64x64 = 7
 };
-constexpr int kGnVariants = 7;
+constexpr int kGnVariants = 8;
 
 // Columns of output produced by one 256-lane strip for window radius kr.
 inline int gn_tile_w(int kr) { return kGnThreads - 2 * kr - 2; }
 
 // Output tile of a variant: width and height (march: strip width, tile_h rows).
+// 64 x 64 tiles need (64 + 2 KR + 3)^2 x 24 B of LDS: above KR 7 they would
+// exceed the 160 KiB of a compute unit, and 64 x 32 tiles with 1024 lanes run
+// instead.  Host block counts and device launches both go through this.
+inline int gn_variant_for(int variant, int kr) {
+  return variant == GN_TILE_64x64 && kr > 7 ? GN_TILE_64x32W : variant;
+}
+
 inline void gn_tile_dims(int variant, int kr, int tile_h, int& tw, int& th) {
+  variant = gn_variant_for(variant, kr);
   if (variant == GN_TILE_64x32) { tw = 64; th = 32; }
   else if (variant == GN_TILE_64x16 || variant == GN_TILE_64x16W) { tw = 64; th = 16; }
   else if (variant == GN_TILE_64x32W) { tw = 64; th = 32; }
+  else if (variant == GN_TILE_64x64) { tw = 64; th = 64; }
   else if (variant == GN_TILE_32x16) { tw = 32; th = 16; }
   else if (variant == GN_TILE_16x16) { tw = 16; th = 16; }
   else { tw = gn_tile_w(kr); th = tile_h; }

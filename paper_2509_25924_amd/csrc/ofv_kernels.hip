@@ -398,6 +398,7 @@ OFV_DECLT(bf16, upsample)
 #undef OFV_DECLT
 
 hipError_t launch_gn(const GnArgs& a, int kr, int storage, int mode, int variant, int nblocks, hipStream_t s) {
+  variant = gn_variant_for(variant, kr);
   if (variant != GN_MARCH) {
 #define OFV_PICKT(ST)                                                                     \
   if (mode == FLOW_ZERO) return launch_gnt_##ST##_zero(a, kr, variant, nblocks, s);     \
