@@ -37,6 +37,15 @@ ofv_status ofv_stage_normalize(ofv_handle h, const ofv_image* frame, int norm_ra
 ofv_status ofv_stage_reduce(ofv_handle h, int storage, const void* in, int width, int height,
                             int64_t in_pitch, void* out, int64_t out_pitch);
 
+/* Pipeline step 2 as the estimator runs it: `levels` (1..3) successive
+ * REDUCE levels of `in` in one launch.  out[k] receives level k + 1
+ * (ceil(width / 2^(k+1)) x ceil(height / 2^(k+1)), pitch out_pitch[k]);
+ * each level is rounded to `storage` before the next is formed, so the
+ * result equals `levels` chained ofv_stage_reduce calls bit for bit.  The
+ * output planes must not overlap the input or each other. */
+ofv_status ofv_stage_pyramid(ofv_handle h, int storage, const void* in, int width, int height, int64_t in_pitch,
+                             int levels, void* const* out, const int64_t* out_pitch);
+
 /* Initial-flow restriction: out = REDUCE(in) / 2 for both flow planes
  * (float32 pairs).  Output size ceil(width/2) x ceil(height/2). */
 ofv_status ofv_stage_restrict_flow(ofv_handle h, const float* in, int width, int height, int64_t in_pitch,

@@ -52,6 +52,8 @@ EXPORTS = {
     "ofv_compute_flow_backward": (c_int, [c_void_p, POINTER(OfvImage), POINTER(OfvImage), POINTER(OfvParams),
                                           c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "ofv_set_gn_variant": (c_int, [c_void_p, c_int, c_int]),
+    "ofv_stage_pyramid": (c_int, [c_void_p, c_int, c_void_p, c_int, c_int, c_int64, c_int, POINTER(c_void_p),
+                                  POINTER(c_int64)]),
     "ofv_autotune": (c_int, [c_void_p, POINTER(OfvImage), POINTER(OfvImage), POINTER(OfvParams), c_void_p, c_int]),
     "ofv_tuning_export": (c_int, [c_void_p, c_char_p, c_size_t, POINTER(c_size_t)]),
     "ofv_tuning_import": (c_int, [c_void_p, c_char_p]),

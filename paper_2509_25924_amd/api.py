@@ -7,7 +7,7 @@ current torch stream.  Tensors must live on a ROCm device.
 from __future__ import annotations
 
 import ctypes
-from ctypes import byref, c_size_t, c_void_p
+from ctypes import byref, c_int64, c_size_t, c_void_p
 from typing import Dict, List, Optional, Sequence
 
 import torch
@@ -287,6 +287,25 @@ def stage_reduce(plane: torch.Tensor, handle: Optional[Handle] = None) -> torch.
     check(load().ofv_stage_reduce(hd.ptr, _lib.STORE[storage], c_void_p(plane.data_ptr()), w, h, plane.stride(0),
                                   c_void_p(out.data_ptr()), out.stride(0)), hd.ptr)
     return out
+
+
+def stage_pyramid(plane: torch.Tensor, levels: int, handle: Optional[Handle] = None) -> List[torch.Tensor]:
+    """`levels` (1..3) successive REDUCE levels of `plane` in one launch;
+    equals chained `stage_reduce` calls bit for bit."""
+    _plane_check(plane)
+    storage = {v: k for k, v in _STORE_DTYPE.items()}[plane.dtype]
+    hd = _stage_handle(plane, handle)
+    h, w = plane.shape
+    outs = []
+    for _ in range(max(int(levels), 1)):
+        h, w = (h + 1) // 2, (w + 1) // 2
+        outs.append(torch.empty((h, w), dtype=plane.dtype, device=plane.device))
+    n = len(outs)
+    ptrs = (c_void_p * n)(*[o.data_ptr() for o in outs])
+    pitches = (c_int64 * n)(*[o.stride(0) for o in outs])
+    check(load().ofv_stage_pyramid(hd.ptr, _lib.STORE[storage], c_void_p(plane.data_ptr()), plane.shape[1],
+                                   plane.shape[0], plane.stride(0), int(levels), ptrs, pitches), hd.ptr)
+    return outs
 
 
 def stage_restrict_flow(flow: torch.Tensor, handle: Optional[Handle] = None) -> torch.Tensor:

@@ -309,24 +309,49 @@ ofv_status run_pipeline(ofv_ctx* h, int n, PairPlan* pp, const ofv_params* p, fl
                                [&](const NormArgs& a, int b) { return launch_normalize(a, b, s); }, "normalize");
     if (r != OFV_OK) return r;
   }
-  // Step 2: pyramid levels 1..L-1 of both frames.
-  for (int l = 1; l < L; ++l) {
-    ReduceArgs ra{};
-    ra.storage = st;
-    ra.scale = 1.0f;
-    auto fill = [&](int i, ReduceJob& J) {
-      const PairPlan& q = pp[i / 2];
-      J.in = img_plane(h, q, i % 2, l - 1, ts);
-      J.out = img_plane(h, q, i % 2, l, ts);
-      J.in_pitch = h->lpitch[l - 1];
-      J.out_pitch = h->lpitch[l];
-      J.w = q.lw[l - 1];
-      J.h = q.lh[l - 1];
-      return ((q.lw[l] + 63) / 64) * ((q.lh[l] + 3) / 4);
-    };
-    ofv_status r = run_chunked(h, 2 * n, ra, fill,
-                               [&](const ReduceArgs& a, int b) { return launch_reduce(a, b, s); }, "reduce");
+  // Step 2: pyramid levels 1..L-1 of both frames, up to three levels per launch.
+  for (int l = 1; l < L;) {
+    const int nlev = std::min(kMaxReduceLevels, L - l);
+    ofv_status r = OFV_OK;
+    if (nlev == 1) {
+      ReduceArgs ra{};
+      ra.storage = st;
+      ra.scale = 1.0f;
+      auto fill = [&](int i, ReduceJob& J) {
+        const PairPlan& q = pp[i / 2];
+        J.in = img_plane(h, q, i % 2, l - 1, ts);
+        J.out = img_plane(h, q, i % 2, l, ts);
+        J.in_pitch = h->lpitch[l - 1];
+        J.out_pitch = h->lpitch[l];
+        J.w = q.lw[l - 1];
+        J.h = q.lh[l - 1];
+        return ((q.lw[l] + 63) / 64) * ((q.lh[l] + 3) / 4);
+      };
+      r = run_chunked(h, 2 * n, ra, fill, [&](const ReduceArgs& a, int b) { return launch_reduce(a, b, s); },
+                      "reduce");
+    } else {
+      ReduceMArgs ra{};
+      ra.storage = st;
+      int tw = 0, th = 0;
+      reduce_multi_tile(nlev, tw, th);
+      auto fill = [&](int i, ReduceMJob& J) {
+        const PairPlan& q = pp[i / 2];
+        J.in = img_plane(h, q, i % 2, l - 1, ts);
+        J.in_pitch = h->lpitch[l - 1];
+        for (int k = 0; k < nlev; ++k) {
+          J.out[k] = img_plane(h, q, i % 2, l + k, ts);
+          J.out_pitch[k] = h->lpitch[l + k];
+        }
+        J.w = q.lw[l - 1];
+        J.h = q.lh[l - 1];
+        const int d = l + nlev - 1;  // deepest level of the launch
+        return ((q.lw[d] + tw - 1) / tw) * ((q.lh[d] + th - 1) / th);
+      };
+      r = run_chunked(h, 2 * n, ra, fill,
+                      [&](const ReduceMArgs& a, int b) { return launch_reduce_multi(a, nlev, b, s); }, "reduce");
+    }
     if (r != OFV_OK) return r;
+    l += nlev;
   }
   // Initial flow: restricted to the coarsest level by REDUCE / 2 (pairs that have one).
   std::vector<int> cur(n, -1);  // flow buffer holding the current field, -1 = zero field
@@ -1154,6 +1179,45 @@ ofv_status ofv_stage_reduce(ofv_handle h, int storage, const void* in, int width
   if (stage_prologue(h) != OFV_OK) return OFV_ERR_INVALID_ARG;
   if (storage < 0 || storage > 2) return fail(h, OFV_ERR_INVALID_ARG, "unknown storage %d", storage);
   return reduce_common(h, storage, in, width, height, in_pitch, out, out_pitch, 1.0f, 1, 0, 0);
+}
+
+ofv_status ofv_stage_pyramid(ofv_handle h, int storage, const void* in, int width, int height, int64_t in_pitch,
+                             int levels, void* const* out, const int64_t* out_pitch) {
+  if (stage_prologue(h) != OFV_OK) return OFV_ERR_INVALID_ARG;
+  if (storage < 0 || storage > 2) return fail(h, OFV_ERR_INVALID_ARG, "unknown storage %d", storage);
+  if (levels < 1 || levels > kMaxReduceLevels)
+    return fail(h, OFV_ERR_INVALID_ARG, "levels %d outside 1..%d", levels, kMaxReduceLevels);
+  if (!in || !out || !out_pitch) return fail(h, OFV_ERR_INVALID_ARG, "in, out or out_pitch is NULL");
+  if (width < 1 || height < 1) return fail(h, OFV_ERR_INVALID_ARG, "size %dx%d invalid", width, height);
+  if (in_pitch < width) return fail(h, OFV_ERR_INVALID_ARG, "in_pitch < width");
+  int w = width, hh = height;
+  for (int k = 0; k < levels; ++k) {
+    w = (w + 1) / 2;
+    hh = (hh + 1) / 2;
+    if (!out[k]) return fail(h, OFV_ERR_INVALID_ARG, "out[%d] is NULL", k);
+    if (out_pitch[k] < w) return fail(h, OFV_ERR_INVALID_ARG, "out_pitch[%d] < %d", k, w);
+  }
+  if (levels == 1) return reduce_common(h, storage, in, width, height, in_pitch, out[0], out_pitch[0], 1.0f, 1, 0, 0);
+  ofv_status r = stage_device(h);
+  if (r != OFV_OK) return r;
+  DeviceGuard g(h->device);
+  ReduceMArgs ra{};
+  ra.njobs = 1;
+  ra.storage = storage;
+  ReduceMJob& J = ra.job[0];
+  J.in = in;
+  J.in_pitch = in_pitch;
+  for (int k = 0; k < levels; ++k) {
+    J.out[k] = out[k];
+    J.out_pitch[k] = out_pitch[k];
+  }
+  J.w = width;
+  J.h = height;
+  J.tile_start = 0;
+  int tw = 0, th = 0;
+  reduce_multi_tile(levels, tw, th);
+  const hipError_t e = launch_reduce_multi(ra, levels, ((w + tw - 1) / tw) * ((hh + th - 1) / th), h->stream);
+  return e == hipSuccess ? OFV_OK : device_error(h, e, "pyramid");
 }
 
 ofv_status ofv_stage_restrict_flow(ofv_handle h, const float* in, int width, int height, int64_t in_pitch,

@@ -52,6 +52,29 @@ struct ReduceArgs {
   ReduceJob job[kMaxJobs];
 };
 
+// Several pyramid levels from one input level in one launch (image pyramids).
+constexpr int kMaxReduceLevels = 3;
+struct ReduceMJob {
+  const void* in;
+  void* out[kMaxReduceLevels];     // levels 1..nlev below the input
+  int64_t in_pitch;
+  int64_t out_pitch[kMaxReduceLevels];
+  int w, h;                        // input size
+  int tile_start;
+  int pad_;
+};
+struct ReduceMArgs {
+  int njobs;
+  int storage;
+  int pad_[2];
+  ReduceMJob job[kMaxJobs];
+};
+// output tile of the deepest level per workgroup for nlev levels
+inline void reduce_multi_tile(int nlev, int& tw, int& th) {
+  tw = nlev == 3 ? 16 : 32;
+  th = 8;
+}
+
 // ---------------------------------------------------------------- up-sampling (stage entry point)
 struct UpsampleArgs {
   const float* in_u; const float* in_v;
@@ -115,6 +138,7 @@ inline void gn_tile_dims(int variant, int kr, int tile_h, int& tw, int& th) {
 
 hipError_t launch_normalize(const NormArgs& a, int nblocks, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, int nblocks, hipStream_t s);
+hipError_t launch_reduce_multi(const ReduceMArgs& a, int nlev, int nblocks, hipStream_t s);
 hipError_t launch_upsample(const UpsampleArgs& a, hipStream_t s);
 // All jobs of one launch share the input-flow mode (a compile-time parameter of the kernel).
 hipError_t launch_gn(const GnArgs& a, int kr, int storage, int mode, int variant, int nblocks, hipStream_t s);

@@ -348,6 +348,161 @@ hipError_t launch_reduce(const ReduceArgs& a, int nblocks, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
+// Step 2, NLEV levels per launch.  A workgroup owns a TW x TH tile of the
+// deepest level and the matching tiles of the levels above it (2x, 4x the
+// size).  Level k (input k = 0) is held in LDS over a region of
+// rw(k) x rh(k) pixels whose origin is 2 * origin(k + 1) - 2: exactly the
+// taps that level k + 1's region reads.  A region pixel outside its level
+// stands for its clamped position (replicate border), so every tap reads
+// its region directly.  Each level is rounded to the storage type before
+// the next one is formed, as a separate REDUCE launch would read it, so the
+// levels equal level-by-level REDUCE bit for bit.
+// ---------------------------------------------------------------------------
+template <int NLEV, int TW, int TH>
+struct RChain {
+  static constexpr int rw(int k) { return k >= NLEV ? TW : 2 * rw(k + 1) + 3; }
+  static constexpr int rh(int k) { return k >= NLEV ? TH : 2 * rh(k + 1) + 3; }
+  static constexpr int off(int k) { return k >= NLEV ? 0 : 2 * off(k + 1) + 2; }  // owned tile within region k
+  // region buffers of levels 0 .. NLEV-1 and one horizontal-pass buffer
+  static constexpr int buf(int k) { return k <= 0 ? 0 : buf(k - 1) + rw(k - 1) * rh(k - 1); }
+  static constexpr int tmp_size() {
+    int m = 0;
+    for (int k = 1; k <= NLEV; ++k) m = rh(k - 1) * rw(k) > m ? rh(k - 1) * rw(k) : m;
+    return m;
+  }
+  static constexpr int LDS_FLOATS = buf(NLEV) + tmp_size();
+};
+
+template <typename TS, int NLEV, int TW, int TH, int NT>
+__global__ __launch_bounds__(NT) void reduce_multi_kernel(const ReduceMArgs a) {
+  using C = RChain<NLEV, TW, TH>;
+  extern __shared__ float lds[];
+  constexpr int TMP = C::buf(NLEV);
+  float* tmp = lds + TMP;
+  const ReduceMJob& J = a.job[find_job(a, blockIdx.x)];
+  int lw[NLEV + 1], lh[NLEV + 1];
+  lw[0] = J.w;
+  lh[0] = J.h;
+#pragma unroll
+  for (int k = 1; k <= NLEV; ++k) {
+    lw[k] = (lw[k - 1] + 1) / 2;
+    lh[k] = (lh[k - 1] + 1) / 2;
+  }
+  const int t = blockIdx.x - J.tile_start;
+  const int ntx = (lw[NLEV] + TW - 1) / TW;
+  int ox[NLEV + 1], oy[NLEV + 1];  // region origins
+  ox[NLEV] = (t % ntx) * TW;
+  oy[NLEV] = (t / ntx) * TH;
+#pragma unroll
+  for (int k = NLEV - 1; k >= 0; --k) {
+    ox[k] = 2 * ox[k + 1] - 2;
+    oy[k] = 2 * oy[k + 1] - 2;
+  }
+  // stage the input region (indices clamped into the input level)
+  {
+    constexpr int RW0 = C::rw(0);
+    constexpr int N = RW0 * C::rh(0);
+    constexpr int B = 8;
+    const TS* in = static_cast<const TS*>(J.in);
+    for (int i0 = threadIdx.x; i0 < N; i0 += B * NT) {
+      float v[B];
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        const int i = min(i0 + u * NT, N - 1);
+        const int r = i / RW0;
+        const int c = i - r * RW0;
+        const int gx = min(max(ox[0] + c, 0), lw[0] - 1);
+        const int gy = min(max(oy[0] + r, 0), lh[0] - 1);
+        v[u] = Px<TS>::ld(in + static_cast<int64_t>(gy) * J.in_pitch + gx);
+      }
+#pragma unroll
+      for (int u = 0; u < B; ++u)
+        if (i0 + u * NT < N) lds[i0 + u * NT] = v[u];
+    }
+  }
+  // one level; K is a compile-time constant so every region size folds
+  auto level = [&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    constexpr float w0 = 1.0f / 16, w1 = 4.0f / 16, w2 = 6.0f / 16;
+    constexpr int sw = C::rw(k - 1), sh = C::rh(k - 1);
+    constexpr int dw = C::rw(k), dh = C::rh(k);
+    constexpr int own_w = TW << (NLEV - k), own_h = TH << (NLEV - k);  // owned tile at level k
+    constexpr int offk = C::off(k);
+    __syncthreads();
+    constexpr int SRC = C::buf(k - 1), DST = C::buf(k);
+    const float* src = lds + SRC;
+    // horizontal pass: rows of region k-1, columns of region k (value at the clamped column)
+    for (int i = threadIdx.x; i < sh * dw; i += NT) {
+      const int r = i / dw;
+      const int c = i - r * dw;
+      const int q = min(max(ox[k] + c, 0), lw[k] - 1);
+      const float* p = src + r * sw + (2 * q - 2 - ox[k - 1]);
+      float acc = w0 * p[0];
+      acc += w1 * p[1];
+      acc += w2 * p[2];
+      acc += w1 * p[3];
+      acc += w0 * p[4];
+      tmp[i] = acc;
+    }
+    __syncthreads();
+    // vertical pass: region k, rounded to the storage type; the owned tile goes to memory
+    float* dst = lds + DST;
+    TS* out = static_cast<TS*>(J.out[k - 1]);
+    const int64_t opitch = J.out_pitch[k - 1];
+    for (int i = threadIdx.x; i < dh * dw; i += NT) {
+      const int r = i / dw;
+      const int c = i - r * dw;
+      const int qy = min(max(oy[k] + r, 0), lh[k] - 1);
+      const float* p = tmp + (2 * qy - 2 - oy[k - 1]) * dw + c;
+      float acc = w0 * p[0];
+      acc += w1 * p[dw];
+      acc += w2 * p[2 * dw];
+      acc += w1 * p[3 * dw];
+      acc += w0 * p[4 * dw];
+      const float v = Px<TS>::round(acc);
+      if (k < NLEV) dst[i] = v;
+      const int cx = c - offk, cy = r - offk;
+      const int gx = ox[k] + c, gy = oy[k] + r;
+      if (static_cast<unsigned>(cx) < static_cast<unsigned>(own_w) &&
+          static_cast<unsigned>(cy) < static_cast<unsigned>(own_h) && gx < lw[k] && gy < lh[k])
+        Px<TS>::st(out + static_cast<int64_t>(gy) * opitch + gx, v);
+    }
+  };
+  level(std::integral_constant<int, 1>{});
+  if constexpr (NLEV >= 2) level(std::integral_constant<int, 2>{});
+  if constexpr (NLEV >= 3) level(std::integral_constant<int, 3>{});
+}
+
+template <typename TS, int NLEV>
+hipError_t launch_reduce_multi_typed(const ReduceMArgs& a, int nblocks, hipStream_t s) {
+  constexpr int TW = NLEV == 3 ? 16 : 32, TH = 8;
+  constexpr int NT = NLEV == 3 ? 1024 : 256;
+  constexpr size_t lds = sizeof(float) * RChain<NLEV, TW, TH>::LDS_FLOATS;
+  auto kern = reduce_multi_kernel<TS, NLEV, TW, TH, NT>;
+  static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                     static_cast<int>(lds));
+  if (attr != hipSuccess) return attr;
+  hipLaunchKernelGGL(kern, dim3(nblocks), dim3(NT), lds, s, a);
+  return hipGetLastError();
+}
+
+template <typename TS>
+hipError_t launch_reduce_multi_st(const ReduceMArgs& a, int nlev, int nblocks, hipStream_t s) {
+  if (nlev == 2) return launch_reduce_multi_typed<TS, 2>(a, nblocks, s);
+  if (nlev == 3) return launch_reduce_multi_typed<TS, 3>(a, nblocks, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_reduce_multi(const ReduceMArgs& a, int nlev, int nblocks, hipStream_t s) {
+  switch (a.storage) {
+    case ST_F32: return launch_reduce_multi_st<float>(a, nlev, nblocks, s);
+    case ST_F16: return launch_reduce_multi_st<_Float16>(a, nlev, nblocks, s);
+    default: return launch_reduce_multi_st<bf16_t>(a, nlev, nblocks, s);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Step 4 (stand-alone form): V_fine(X, Y) = 2 * bilinear(V_coarse, X/2, Y/2).
 // The estimator itself fuses this read into the first Gauss-Newton
 // iteration of each finer level.

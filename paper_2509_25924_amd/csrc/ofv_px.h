@@ -30,6 +30,7 @@ struct Px;
 template <>
 struct Px<float> {
   static __device__ __forceinline__ float ld(const float* p) { return *p; }
+  static __device__ __forceinline__ float round(float v) { return v; }
   static __device__ __forceinline__ float ldv(PlaneView v, uint32_t i) { return ld_f32(v, i); }
   // element i + j of the plane, j a byte offset uniform across the wavefront
   static __device__ __forceinline__ float ldvs(PlaneView v, uint32_t i, uint32_t jb) {
@@ -47,6 +48,7 @@ struct Px<float> {
 template <>
 struct Px<_Float16> {
   static __device__ __forceinline__ float ld(const _Float16* p) { return static_cast<float>(*p); }
+  static __device__ __forceinline__ float round(float v) { return static_cast<float>(static_cast<_Float16>(v)); }
   static __device__ __forceinline__ float ldv(PlaneView v, uint32_t i) { return ldvs(v, i, 0); }
   static __device__ __forceinline__ float ldvs(PlaneView v, uint32_t i, uint32_t jb) {
     const uint16_t b = __builtin_amdgcn_raw_buffer_load_b16(v, static_cast<int>(i * 2u), static_cast<int>(jb), 0);
@@ -69,6 +71,11 @@ template <>
 struct Px<bf16_t> {
   static __device__ __forceinline__ float ld(const bf16_t* p) {
     return __uint_as_float(static_cast<uint32_t>(p->bits) << 16);
+  }
+  static __device__ __forceinline__ float round(float v) {
+    bf16_t b;
+    st(&b, v);
+    return ld(&b);
   }
   static __device__ __forceinline__ float ldv(PlaneView v, uint32_t i) { return ldvs(v, i, 0); }
   static __device__ __forceinline__ float ldvs(PlaneView v, uint32_t i, uint32_t jb) {

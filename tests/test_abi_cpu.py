@@ -8,7 +8,7 @@ import ctypes
 import os
 import re
 import subprocess
-from ctypes import byref, c_size_t, c_void_p
+from ctypes import byref, c_int64, c_size_t, c_void_p
 
 import pytest
 
@@ -200,6 +200,18 @@ def test_stage_validation(lib, vhandle):
     assert lib.ofv_stage_normalize(vhandle, byref(img), 99, 1e-4, 0, c_void_p(OUT), 64) == _lib.OFV_ERR_INVALID_ARG
     assert lib.ofv_stage_reduce(vhandle, 0, c_void_p(0x1000), 10, 10, 9, c_void_p(OUT), 5) == _lib.OFV_ERR_INVALID_ARG
     assert lib.ofv_stage_reduce(vhandle, 0, c_void_p(0x1000), 10, 10, 10, c_void_p(OUT), 5) == _lib.OFV_ERR_UNSUPPORTED
+    outs = (c_void_p * 3)(OUT, OUT + 0x10000, OUT + 0x20000)
+    pitches = (c_int64 * 3)(5, 3, 2)
+    for levels in (0, 4):
+        assert lib.ofv_stage_pyramid(vhandle, 0, c_void_p(0x1000), 10, 10, 10, levels, outs, pitches) == \
+            _lib.OFV_ERR_INVALID_ARG
+    assert lib.ofv_stage_pyramid(vhandle, 0, c_void_p(0x1000), 10, 10, 10, 3, None, pitches) == _lib.OFV_ERR_INVALID_ARG
+    pitches[1] = 2
+    assert lib.ofv_stage_pyramid(vhandle, 0, c_void_p(0x1000), 10, 10, 10, 3, outs, pitches) == _lib.OFV_ERR_INVALID_ARG
+    pitches[1] = 3
+    assert lib.ofv_stage_pyramid(vhandle, 3, c_void_p(0x1000), 10, 10, 10, 3, outs, pitches) == _lib.OFV_ERR_INVALID_ARG
+    assert lib.ofv_stage_pyramid(vhandle, 0, c_void_p(0x1000), 10, 10, 10, 3, outs, pitches) == \
+        _lib.OFV_ERR_UNSUPPORTED
     assert lib.ofv_stage_upsample(vhandle, c_void_p(0x1000), 5, 5, 5, c_void_p(OUT), 10, 10, 10) == \
         _lib.OFV_ERR_UNSUPPORTED
     args = [vhandle, 0, c_void_p(0x1000), c_void_p(0x2000), 16, 16, 16, _lib.FLOW_IN_DIRECT, c_void_p(OUT), 16, 16,

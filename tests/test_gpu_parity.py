@@ -84,6 +84,35 @@ def test_reduce_stage(ofv, shape):
     assert torch.max(torch.abs(o64(got) - ref)).item() < 2e-6
 
 
+@pytest.mark.parametrize("storage,dt", [("f32", torch.float32), ("f16", torch.float16), ("bf16", torch.bfloat16)])
+@pytest.mark.parametrize("shape", [(1, 1), (3, 5), (9, 1), (65, 130), (257, 255), (1024, 1024), (1000, 1366)])
+def test_pyramid_stage_equals_chained_reduce(ofv, storage, dt, shape):
+    """Several REDUCE levels in one launch give the chained single-level
+    result bit for bit (each level rounded to the storage type before the
+    next is formed), and match the oracle's pyramid with the same rounding."""
+    say("pyramid", storage, shape)
+    p = torch.as_tensor(np.random.default_rng(15).normal(size=shape).astype(np.float32)).to(dt)
+    dp = p.to("cuda")
+    for levels in (1, 2, 3):
+        got = ofv.stage_pyramid(dp, levels)
+        chain, cur = [], dp
+        for _ in range(levels):
+            cur = ofv.stage_reduce(cur)
+            chain.append(cur)
+        for g, c in zip(got, chain):
+            assert g.shape == c.shape and g.dtype == dt
+            assert torch.equal(g.view(torch.int16 if dt != torch.float32 else torch.int32),
+                               c.view(torch.int16 if dt != torch.float32 else torch.int32))
+    ref = oracle.pyramid(p.to(torch.float64), 4, plane_round=None if storage == "f32" else storage)
+    for k, g in enumerate(got):
+        if storage == "f32":
+            assert torch.max(torch.abs(o64(g) - ref[k + 1])).item() < 2e-6
+        else:   # float32 arithmetic before the rounding may land one storage ulp away
+            ulp = 2.0 ** -10 if storage == "f16" else 2.0 ** -7
+            rel = torch.abs(o64(g.float()) - ref[k + 1]) / (ref[k + 1].abs() + 1e-3)
+            assert torch.max(rel).item() <= ulp
+
+
 def test_restrict_and_upsample_stages(ofv):
     say("restrict/upsample")
     rng = np.random.default_rng(14)
