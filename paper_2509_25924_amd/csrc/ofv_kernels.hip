@@ -17,13 +17,18 @@ namespace ofv {
 // float32 rounding errors of the exact quotients);
 // the (64 + 2 NR) x (16 + 2 NR) input tile is staged in LDS once (frame
 // pixels outside the frame stored as 0) and each lane evaluates 4
-// vertically adjacent outputs of one column:
-//   mu = S / n,  var = sum over the truncated window of (I - mu)^2 / n,
-//   N = (I - mu) / sqrt(var + eps)      (second-pass variance)
+// vertically adjacent outputs of one column.  Every normalisation kernel
+// evaluates one pixel by the same sequence of float32 operations over the
+// window truncated to the frame (n pixels), so that all of them agree bit
+// for bit:
+//   row sums left to right, S = their sum top to bottom, rn = 1 / n,
+//   mu = S rn,  q = fma chain of (I - mu)^2 in row-major order,
+//   N = (I - mu) rsq(q rn + eps)        (second-pass variance)
+// Taps outside the frame are stored as 0 (exact in the sums) and masked by
+// a 0/1 weight in the q chain (fma(0, d, q) = q).
 // For NR <= 3 the lane's (4 + 2 NR) x (2 NR + 1) patch is read into
-// registers once; row sums are shared between the 4 outputs and window
-// taps outside the frame are masked by 0/1 row and column weights.
-// Larger radii take the generic path that walks the window in LDS.
+// registers once and row sums are shared between the 4 outputs.  Larger
+// radii take the generic path that walks the window in LDS.
 // ---------------------------------------------------------------------------
 constexpr int kNormTW = 64;
 constexpr int kNormTH = 16;
@@ -109,6 +114,7 @@ __device__ __forceinline__ void stage_frame_tile_c(const NormJob& J, float* tile
 
 template <typename TS, int NRC>
 __global__ __launch_bounds__(256) void normalize_kernel(const NormArgs a) {
+#pragma clang fp contract(off)
   extern __shared__ float tile[];
   const int j = find_job(a, blockIdx.x);
   const NormJob& J = a.job[j];
@@ -198,13 +204,11 @@ __global__ __launch_bounds__(256) void normalize_kernel(const NormArgs a) {
         float q = 0.0f;
 #pragma unroll
         for (int r = 0; r < NC; ++r) {
-          float qr = 0.0f;
 #pragma unroll
           for (int c = 0; c < NC; ++c) {
             const float d = pv[k + r][c] - mu;
-            qr = fmaf(vx[c] * d, d, qr);
+            q = fmaf(vy[k + r] * vx[c] * d, d, q);
           }
-          q = fmaf(vy[k + r], qr, q);
         }
         Px<TS>::st(out + k * J.out_pitch, (pv[k + R][R] - mu) * __builtin_amdgcn_rsqf(fmaf(q, rn, a.eps)));
       }
@@ -222,22 +226,22 @@ __global__ __launch_bounds__(256) void normalize_kernel(const NormArgs a) {
     if (nr > 0) {
       const int ya = max(-nr, -gy);
       const int yb = min(nr, J.h - 1 - gy);
-      const float n = static_cast<float>((yb - ya + 1) * (xb - xa + 1));
+      const float rn = 1.0f / static_cast<float>((yb - ya + 1) * (xb - xa + 1));
       float s = 0.0f;
       for (int dy = ya; dy <= yb; ++dy) {
         float row = 0.0f;
         for (int dx = xa; dx <= xb; ++dx) row += centre[dy * tw + dx];
         s += row;
       }
-      const float mu = s / n;
+      const float mu = s * rn;
       float q = 0.0f;
       for (int dy = ya; dy <= yb; ++dy) {
         for (int dx = xa; dx <= xb; ++dx) {
           const float d = centre[dy * tw + dx] - mu;
-          q += d * d;
+          q = fmaf(d, d, q);
         }
       }
-      nv = (nv - mu) / sqrtf(q / n + a.eps);
+      nv = (nv - mu) * __builtin_amdgcn_rsqf(fmaf(q, rn, a.eps));
     }
     Px<TS>::st(out + k * J.out_pitch, nv);
   }
@@ -373,24 +377,78 @@ struct RChain {
   static constexpr int LDS_FLOATS = buf(NLEV) + tmp_size();
 };
 
-template <typename TS, int NLEV, int TW, int TH, int NT>
-__global__ __launch_bounds__(NT) void reduce_multi_kernel(const ReduceMArgs a) {
+// Level K of the chain: region K from region K - 1 (both in LDS), rounded
+// to the storage type; the owned tile is stored to `out` (pitch `opitch`).
+template <typename TS, int NLEV, int TW, int TH, int NT, int K>
+__device__ __forceinline__ void chain_level(float* lds, const int* ox, const int* oy, const int* lw, const int* lh,
+                                            void* outp, int64_t opitch) {
   using C = RChain<NLEV, TW, TH>;
-  extern __shared__ float lds[];
-  constexpr int TMP = C::buf(NLEV);
+  constexpr float w0 = 1.0f / 16, w1 = 4.0f / 16, w2 = 6.0f / 16;
+  constexpr int sw = C::rw(K - 1), sh = C::rh(K - 1);
+  constexpr int dw = C::rw(K), dh = C::rh(K);
+  constexpr int own_w = TW << (NLEV - K), own_h = TH << (NLEV - K);  // owned tile at level K
+  constexpr int offk = C::off(K);
+  constexpr int SRC = C::buf(K - 1), DST = C::buf(K), TMP = C::buf(NLEV);
+  const float* src = lds + SRC;
+  float* dst = lds + DST;
   float* tmp = lds + TMP;
-  const ReduceMJob& J = a.job[find_job(a, blockIdx.x)];
-  int lw[NLEV + 1], lh[NLEV + 1];
-  lw[0] = J.w;
-  lh[0] = J.h;
+  __syncthreads();
+  // horizontal pass: rows of region K-1, columns of region K (value at the clamped column)
+  for (int i = threadIdx.x; i < sh * dw; i += NT) {
+    const int r = i / dw;
+    const int c = i - r * dw;
+    const int q = min(max(ox[K] + c, 0), lw[K] - 1);
+    const float* p = src + r * sw + (2 * q - 2 - ox[K - 1]);
+    float acc = w0 * p[0];
+    acc += w1 * p[1];
+    acc += w2 * p[2];
+    acc += w1 * p[3];
+    acc += w0 * p[4];
+    tmp[i] = acc;
+  }
+  __syncthreads();
+  // vertical pass: region K, rounded to the storage type; the owned tile goes to memory
+  TS* out = static_cast<TS*>(outp);
+  for (int i = threadIdx.x; i < dh * dw; i += NT) {
+    const int r = i / dw;
+    const int c = i - r * dw;
+    const int qy = min(max(oy[K] + r, 0), lh[K] - 1);
+    const float* p = tmp + (2 * qy - 2 - oy[K - 1]) * dw + c;
+    float acc = w0 * p[0];
+    acc += w1 * p[dw];
+    acc += w2 * p[2 * dw];
+    acc += w1 * p[3 * dw];
+    acc += w0 * p[4 * dw];
+    const float v = Px<TS>::round(acc);
+    if (K < NLEV) dst[i] = v;
+    const int cx = c - offk, cy = r - offk;
+    const int gx = ox[K] + c, gy = oy[K] + r;
+    if (static_cast<unsigned>(cx) < static_cast<unsigned>(own_w) &&
+        static_cast<unsigned>(cy) < static_cast<unsigned>(own_h) && gx < lw[K] && gy < lh[K])
+      Px<TS>::st(out + static_cast<int64_t>(gy) * opitch + gx, v);
+  }
+}
+
+// Levels 1..NLEV from region 0 in LDS; level k goes to out[k - 1].
+template <typename TS, int NLEV, int TW, int TH, int NT>
+__device__ __forceinline__ void chain_levels(float* lds, const int* ox, const int* oy, const int* lw, const int* lh,
+                                             void* const* out, const int64_t* opitch) {
+  chain_level<TS, NLEV, TW, TH, NT, 1>(lds, ox, oy, lw, lh, out[0], opitch[0]);
+  if constexpr (NLEV >= 2) chain_level<TS, NLEV, TW, TH, NT, 2>(lds, ox, oy, lw, lh, out[1], opitch[1]);
+  if constexpr (NLEV >= 3) chain_level<TS, NLEV, TW, TH, NT, 3>(lds, ox, oy, lw, lh, out[2], opitch[2]);
+}
+
+// Level sizes and region origins for deepest-level tile t of a w x h input.
+template <int NLEV, int TW, int TH>
+__device__ __forceinline__ void chain_geometry(int w, int h, int t, int* lw, int* lh, int* ox, int* oy) {
+  lw[0] = w;
+  lh[0] = h;
 #pragma unroll
   for (int k = 1; k <= NLEV; ++k) {
     lw[k] = (lw[k - 1] + 1) / 2;
     lh[k] = (lh[k - 1] + 1) / 2;
   }
-  const int t = blockIdx.x - J.tile_start;
   const int ntx = (lw[NLEV] + TW - 1) / TW;
-  int ox[NLEV + 1], oy[NLEV + 1];  // region origins
   ox[NLEV] = (t % ntx) * TW;
   oy[NLEV] = (t / ntx) * TH;
 #pragma unroll
@@ -398,6 +456,15 @@ __global__ __launch_bounds__(NT) void reduce_multi_kernel(const ReduceMArgs a) {
     ox[k] = 2 * ox[k + 1] - 2;
     oy[k] = 2 * oy[k + 1] - 2;
   }
+}
+
+template <typename TS, int NLEV, int TW, int TH, int NT>
+__global__ __launch_bounds__(NT) void reduce_multi_kernel(const ReduceMArgs a) {
+  using C = RChain<NLEV, TW, TH>;
+  extern __shared__ float lds[];
+  const ReduceMJob& J = a.job[find_job(a, blockIdx.x)];
+  int lw[NLEV + 1], lh[NLEV + 1], ox[NLEV + 1], oy[NLEV + 1];
+  chain_geometry<NLEV, TW, TH>(J.w, J.h, blockIdx.x - J.tile_start, lw, lh, ox, oy);
   // stage the input region (indices clamped into the input level)
   {
     constexpr int RW0 = C::rw(0);
@@ -420,57 +487,7 @@ __global__ __launch_bounds__(NT) void reduce_multi_kernel(const ReduceMArgs a) {
         if (i0 + u * NT < N) lds[i0 + u * NT] = v[u];
     }
   }
-  // one level; K is a compile-time constant so every region size folds
-  auto level = [&](auto kc) {
-    constexpr int k = decltype(kc)::value;
-    constexpr float w0 = 1.0f / 16, w1 = 4.0f / 16, w2 = 6.0f / 16;
-    constexpr int sw = C::rw(k - 1), sh = C::rh(k - 1);
-    constexpr int dw = C::rw(k), dh = C::rh(k);
-    constexpr int own_w = TW << (NLEV - k), own_h = TH << (NLEV - k);  // owned tile at level k
-    constexpr int offk = C::off(k);
-    __syncthreads();
-    constexpr int SRC = C::buf(k - 1), DST = C::buf(k);
-    const float* src = lds + SRC;
-    // horizontal pass: rows of region k-1, columns of region k (value at the clamped column)
-    for (int i = threadIdx.x; i < sh * dw; i += NT) {
-      const int r = i / dw;
-      const int c = i - r * dw;
-      const int q = min(max(ox[k] + c, 0), lw[k] - 1);
-      const float* p = src + r * sw + (2 * q - 2 - ox[k - 1]);
-      float acc = w0 * p[0];
-      acc += w1 * p[1];
-      acc += w2 * p[2];
-      acc += w1 * p[3];
-      acc += w0 * p[4];
-      tmp[i] = acc;
-    }
-    __syncthreads();
-    // vertical pass: region k, rounded to the storage type; the owned tile goes to memory
-    float* dst = lds + DST;
-    TS* out = static_cast<TS*>(J.out[k - 1]);
-    const int64_t opitch = J.out_pitch[k - 1];
-    for (int i = threadIdx.x; i < dh * dw; i += NT) {
-      const int r = i / dw;
-      const int c = i - r * dw;
-      const int qy = min(max(oy[k] + r, 0), lh[k] - 1);
-      const float* p = tmp + (2 * qy - 2 - oy[k - 1]) * dw + c;
-      float acc = w0 * p[0];
-      acc += w1 * p[dw];
-      acc += w2 * p[2 * dw];
-      acc += w1 * p[3 * dw];
-      acc += w0 * p[4 * dw];
-      const float v = Px<TS>::round(acc);
-      if (k < NLEV) dst[i] = v;
-      const int cx = c - offk, cy = r - offk;
-      const int gx = ox[k] + c, gy = oy[k] + r;
-      if (static_cast<unsigned>(cx) < static_cast<unsigned>(own_w) &&
-          static_cast<unsigned>(cy) < static_cast<unsigned>(own_h) && gx < lw[k] && gy < lh[k])
-        Px<TS>::st(out + static_cast<int64_t>(gy) * opitch + gx, v);
-    }
-  };
-  level(std::integral_constant<int, 1>{});
-  if constexpr (NLEV >= 2) level(std::integral_constant<int, 2>{});
-  if constexpr (NLEV >= 3) level(std::integral_constant<int, 3>{});
+  chain_levels<TS, NLEV, TW, TH, NT>(lds, ox, oy, lw, lh, J.out, J.out_pitch);
 }
 
 template <typename TS, int NLEV>
