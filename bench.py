@@ -81,6 +81,10 @@ def parse():
     ap.add_argument("--no-graph", action="store_true", help="launch eagerly instead of replaying a hipGraph")
     ap.add_argument("--variant", default="tuned", choices=["tuned", "auto"] + list(GN_NAMES.values()),
                     help="Gauss-Newton work decomposition: autotuned per level (default) or forced")
+    ap.add_argument("--tuning-table", default=None,
+                    help="with --variant tuned: load this decomposition table (ofv tuning-table text) instead of "
+                         "autotuning, e.g. to run a profiled command with the decompositions of an unprofiled one")
+    ap.add_argument("--save-tuning", default=None, help="write the decomposition table the run used to this file")
     ap.add_argument("--kernel-launches", type=int, default=200, help="launches timed for the dominant kernel")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -472,8 +476,14 @@ def main():
     out = torch.empty((2, h, w), dtype=torch.float32, device=dev)
     handle = ofv.Handle(w, h, 1)
     if args.variant == "tuned":
-        if not args.pmc_probe:
+        if args.tuning_table:
+            with open(args.tuning_table) as fh:
+                handle.load_tuning_table(fh.read())
+        elif not args.pmc_probe:
             handle.autotune(f0, f1, prm, bit_depth=bits, repeats=3)
+        if args.save_tuning:
+            with open(args.save_tuning, "w") as fh:
+                fh.write(handle.tuning_table())
     else:
         handle.set_gn_variant(args.variant)
 
