@@ -173,6 +173,8 @@ ofv_status ofv_compute_flow_backward(ofv_handle h, const ofv_image* frame0, cons
 #define OFV_GN_TILE_64x32W 5  /* 64 x 32 output tiles, 1024 lanes per workgroup */
 #define OFV_GN_TILE_64x16W 6  /* 64 x 16 output tiles, 512 lanes per workgroup */
 #define OFV_GN_TILE_64x64 7   /* 64 x 64 output tiles, 1024 lanes per workgroup */
+#define OFV_GN_TILE_16x16W 8  /* 16 x 16 output tiles, 1024 lanes per workgroup (coarse levels) */
+#define OFV_GN_TILE_32x16W 9  /* 32 x 16 output tiles, 512 lanes per workgroup (coarse levels) */
 
 /* Force a decomposition for later calls on h (OFV_GN_AUTO restores the
  * default); tile_h (rows per strip for OFV_GN_MARCH) is 0 for automatic or

@@ -233,6 +233,8 @@ void pick_gn(const ofv_ctx* h, const ofv_ctx::TuneKey& key, int64_t strips, int6
     if (!std::strcmp(e, "tile32x16")) { variant = GN_TILE_32x16; return; }
     if (!std::strcmp(e, "tile16x16")) { variant = GN_TILE_16x16; return; }
     if (!std::strcmp(e, "tile64x64")) { variant = GN_TILE_64x64; return; }
+    if (!std::strcmp(e, "tile16x16w")) { variant = GN_TILE_16x16W; return; }
+    if (!std::strcmp(e, "tile32x16w")) { variant = GN_TILE_32x16W; return; }
   }
   if (h->forced_variant >= 0) {
     variant = h->forced_variant;
@@ -1027,9 +1029,9 @@ ofv_status ofv_autotune(ofv_handle h, const ofv_image* frame0, const ofv_image* 
     int variant, tile_h;
   };
   // tile variants ignore tile_h (their tile height is fixed); it is recorded as their height
-  const Cand cands[] = {{GN_TILE_16x16, 16},  {GN_TILE_32x16, 16},  {GN_TILE_64x16, 16}, {GN_TILE_64x32, 32},
-                        {GN_TILE_64x16W, 16}, {GN_TILE_64x32W, 32}, {GN_TILE_64x64, 64}, {GN_MARCH, 16},
-                        {GN_MARCH, 32},       {GN_MARCH, 64}};
+  const Cand cands[] = {{GN_TILE_16x16, 16},  {GN_TILE_16x16W, 16}, {GN_TILE_32x16, 16}, {GN_TILE_32x16W, 16},
+                        {GN_TILE_64x16, 16},  {GN_TILE_64x32, 32},  {GN_TILE_64x16W, 16}, {GN_TILE_64x32W, 32},
+                        {GN_TILE_64x64, 64},  {GN_MARCH, 16},       {GN_MARCH, 32},       {GN_MARCH, 64}};
   std::map<ofv_ctx::TuneKey, std::pair<float, ofv_ctx::Choice>> best;
   const int saved_v = h->forced_variant, saved_t = h->forced_tile_h;
   for (const Cand& c : cands) {

@@ -406,7 +406,9 @@ hipError_t launch_gn_tile_cfg(const GnArgs& a, int nblocks, hipStream_t s) {
 // variants GN_TILE_64x32W / 64x16W: the same tiles with 1024 / 512 lanes
 // (segments 8 columns / 2 rows), more waves to hide latency per compute unit;
 // variant GN_TILE_64x64: 64 x 64 outputs, 1024 lanes (segments 8 columns / 4
-// rows), the smallest halo, one workgroup per compute unit.
+// rows), the smallest halo, one workgroup per compute unit;
+// variants GN_TILE_16x16W / 32x16W: the coarse-level tiles with 1024 / 512
+// lanes, so that the warps of a tile are spread over more waves per SIMD.
 // The small tiles spread coarse levels over many compute units: there the
 // launch is bound by the instruction latency of few waves, not by traffic.
 template <int MODE, typename TS>
@@ -420,6 +422,8 @@ hipError_t launch_gn_tile_typed(const GnArgs& a, int kr, int variant, int nblock
       case GN_TILE_64x32W: return launch_gn_tile_cfg<R, MODE, TS, 64, 32, 8, 2, 1024>(a, nblocks, s); \
       case GN_TILE_64x16W: return launch_gn_tile_cfg<R, MODE, TS, 64, 16, 8, 2, 512>(a, nblocks, s);  \
       case GN_TILE_64x64: return launch_gn_tile_cfg<R, MODE, TS, 64, 64, 8, 4, 1024>(a, nblocks, s);  \
+      case GN_TILE_16x16W: return launch_gn_tile_cfg<R, MODE, TS, 16, 16, 4, 1, 1024>(a, nblocks, s); \
+      case GN_TILE_32x16W: return launch_gn_tile_cfg<R, MODE, TS, 32, 16, 4, 2, 512>(a, nblocks, s);  \
       default: return launch_gn_tile_cfg<R, MODE, TS, 16, 16, 4, 1, 256>(a, nblocks, s);            \
     }
   switch (kr) {

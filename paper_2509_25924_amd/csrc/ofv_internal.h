@@ -110,9 +110,11 @@ enum GnVariant {
   GN_TILE_16x16 = 4,
   GN_TILE_64x32W = 5,
   GN_TILE_64x16W = 6,
-  GN_TILE_64x64 = 7
+  GN_TILE_64x64 = 7,
+  GN_TILE_16x16W = 8,
+  GN_TILE_32x16W = 9
 };
-constexpr int kGnVariants = 8;
+constexpr int kGnVariants = 10;
 
 // Columns of output produced by one 256-lane strip for window radius kr.
 inline int gn_tile_w(int kr) { return kGnThreads - 2 * kr - 2; }
@@ -131,8 +133,8 @@ inline void gn_tile_dims(int variant, int kr, int tile_h, int& tw, int& th) {
   else if (variant == GN_TILE_64x16 || variant == GN_TILE_64x16W) { tw = 64; th = 16; }
   else if (variant == GN_TILE_64x32W) { tw = 64; th = 32; }
   else if (variant == GN_TILE_64x64) { tw = 64; th = 64; }
-  else if (variant == GN_TILE_32x16) { tw = 32; th = 16; }
-  else if (variant == GN_TILE_16x16) { tw = 16; th = 16; }
+  else if (variant == GN_TILE_32x16 || variant == GN_TILE_32x16W) { tw = 32; th = 16; }
+  else if (variant == GN_TILE_16x16 || variant == GN_TILE_16x16W) { tw = 16; th = 16; }
   else { tw = gn_tile_w(kr); th = tile_h; }
 }
 
