@@ -42,7 +42,10 @@ ofv_status ofv_stage_reduce(ofv_handle h, int storage, const void* in, int width
  * (ceil(width / 2^(k+1)) x ceil(height / 2^(k+1)), pitch out_pitch[k]);
  * each level is rounded to `storage` before the next is formed, so the
  * result equals `levels` chained ofv_stage_reduce calls bit for bit.  The
- * output planes must not overlap the input or each other. */
+ * output planes must not overlap the input or each other.  `out` and
+ * `out_pitch` are host arrays of `levels` entries.  OFV_ERR_INVALID_ARG for
+ * levels outside 1..3, a NULL pointer, a size below 1 or a pitch below its
+ * plane's width. */
 ofv_status ofv_stage_pyramid(ofv_handle h, int storage, const void* in, int width, int height, int64_t in_pitch,
                              int levels, void* const* out, const int64_t* out_pitch);
 
