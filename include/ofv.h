@@ -203,6 +203,48 @@ ofv_status ofv_tuning_export(ofv_handle h, char* buf, size_t cap, size_t* needed
  * any entry is malformed (OFV_ERR_INVALID_ARG). */
 ofv_status ofv_tuning_import(ofv_handle h, const char* text);
 
+/* ---- Live derived quantities (cylinder-wake experiment of the paper's
+ * section on live measurements; Eq. RA): observables computed from each
+ * measured field as it streams, so that no field needs to be stored. */
+typedef struct {
+  float dx, dz;             /* pixel size along x (columns) and along y (rows), any length unit; > 0 */
+  float dt;                 /* time between the two frames of a pair; > 0 */
+  int32_t streamwise_sign;  /* +1: the free stream runs along +x, -1: along -x */
+} ofv_derived_params;
+
+/* dx = dz = dt = 1 (results in pixels and frame pairs), streamwise_sign = +1. */
+void ofv_default_derived_params(ofv_derived_params* p);
+
+/* One pass over a flow field (device, [2][height][pitch] float32, u plane
+ * then v plane, displacement in pixels per pair, as ofv_compute_flow writes
+ * it) that produces any of:
+ *  - vorticity (device float32 plane, pitch vort_pitch): in image
+ *    coordinates (x along columns, y along rows, y down) of the physical
+ *    velocity (U, V) = (u dx / dt, v dz / dt):
+ *      omega = ((dz / dx) dv/di - (dx / dz) du/dj) / dt,
+ *    d/di the per-pixel central difference (f[i+1] - f[i-1]) / 2, one-sided
+ *    f[1] - f[0] and f[n-1] - f[n-2] at the edges, 0 along a dimension of one
+ *    pixel; 0 at masked pixels.
+ *  - area (device, one double): the recirculation area of Eq. (RA),
+ *    dx dz times the number of unmasked pixels with streamwise_sign * u < 0
+ *    (strictly); the pixel count is exact.
+ *  - probe_uv (device float32 [n_probes][2]): (u dx / dt, v dz / dt) by
+ *    bilinear interpolation with clamped coordinates at the points
+ *    probe_xy (device float32 [n_probes][2], (x, y) in pixels).
+ * mask (device uint8 plane, pitch mask_pitch; NULL = every pixel valid):
+ * 0 marks a masked pixel.  Each output is skipped when its pointer is NULL
+ * (probes when n_probes == 0).  One kernel launch; the area's partial counts
+ * meet in a small counter of the handle that the last workgroup reads and
+ * clears, so calls on one handle must not overlap (one handle per stream).
+ * OFV_ERR_INVALID_ARG for NULL flow, sizes below 1, pitches below width,
+ * non-positive or non-finite dx, dz, dt, a sign other than +-1,
+ * n_probes outside 0..2^20, NULL probe arrays with n_probes > 0, or an
+ * output overlapping the flow; OFV_ERR_UNSUPPORTED for planes of 2 GiB or
+ * more. */
+ofv_status ofv_derived(ofv_handle h, const float* flow, int width, int height, int64_t pitch, const uint8_t* mask,
+                       int64_t mask_pitch, const ofv_derived_params* params, float* vorticity, int64_t vort_pitch,
+                       const float* probe_xy, int n_probes, float* probe_uv, double* area);
+
 /* Release the handle and its workspace.  NULL is accepted.  Synchronises the
  * handle's stream first. */
 ofv_status ofv_destroy(ofv_handle h);

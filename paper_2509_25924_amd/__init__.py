@@ -6,8 +6,8 @@ C ABI in ``include/ofv.h``; this package only marshals torch tensors into
 those calls.
 """
 from .api import (Handle, OFVFunction, compute_flow, compute_flow_backward, compute_flow_batch, default_handle,
-                  stage_gn_iteration, stage_normalize, stage_pyramid, stage_reduce, stage_restrict_flow, stage_upsample)
+                  stage_gn_iteration, stage_normalize, stage_pyramid, derived, stage_reduce, stage_restrict_flow, stage_upsample)
 from ._lib import OfvError, load
 
 __all__ = ["Handle", "OFVFunction", "compute_flow", "compute_flow_backward", "compute_flow_batch", "default_handle", "stage_gn_iteration",
-           "stage_normalize", "stage_pyramid", "stage_reduce", "stage_restrict_flow", "stage_upsample", "OfvError", "load"]
+           "stage_normalize", "stage_pyramid", "derived", "stage_reduce", "stage_restrict_flow", "stage_upsample", "OfvError", "load"]

@@ -36,6 +36,10 @@ class OfvParams(ctypes.Structure):
                 ("storage", c_int32), ("flags", c_uint32)]
 
 
+class OfvDerivedParams(ctypes.Structure):
+    _fields_ = [("dx", c_float), ("dz", c_float), ("dt", c_float), ("streamwise_sign", c_int32)]
+
+
 EXPORTS = {
     # name: (restype, argtypes)
     "ofv_default_params": (None, [POINTER(OfvParams)]),
@@ -52,6 +56,9 @@ EXPORTS = {
     "ofv_compute_flow_backward": (c_int, [c_void_p, POINTER(OfvImage), POINTER(OfvImage), POINTER(OfvParams),
                                           c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "ofv_set_gn_variant": (c_int, [c_void_p, c_int, c_int]),
+    "ofv_default_derived_params": (None, [POINTER(OfvDerivedParams)]),
+    "ofv_derived": (c_int, [c_void_p, c_void_p, c_int, c_int, c_int64, c_void_p, c_int64, POINTER(OfvDerivedParams),
+                            c_void_p, c_int64, c_void_p, c_int, c_void_p, c_void_p]),
     "ofv_stage_pyramid": (c_int, [c_void_p, c_int, c_void_p, c_int, c_int, c_int64, c_int, POINTER(c_void_p),
                                   POINTER(c_int64)]),
     "ofv_autotune": (c_int, [c_void_p, POINTER(OfvImage), POINTER(OfvImage), POINTER(OfvParams), c_void_p, c_int]),

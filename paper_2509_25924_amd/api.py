@@ -13,7 +13,7 @@ from typing import Dict, List, Optional, Sequence
 import torch
 
 from . import _lib
-from ._lib import OfvImage, OfvParams, check, load
+from ._lib import OfvDerivedParams, OfvImage, OfvParams, check, load
 
 _PIX = {torch.uint8: _lib.PIX_U8, torch.uint16: _lib.PIX_U16, torch.int16: _lib.PIX_U16,
         torch.float32: _lib.PIX_F32}
@@ -351,3 +351,40 @@ def stage_gn_iteration(p0: torch.Tensor, p1: torch.Tensor, flow_in: Optional[tor
                                         c_void_p(p1.data_ptr()), w, h, p0.stride(0), m, fin, iw, ih, iw,
                                         c_void_p(out.data_ptr()), w, kernel_radius, reg_rel, reg_abs), hd.ptr)
     return out
+
+
+def derived(flow: torch.Tensor, mask: Optional[torch.Tensor] = None, dx: float = 1.0, dz: float = 1.0,
+            dt: float = 1.0, streamwise_sign: int = 1, probes: Optional[torch.Tensor] = None,
+            vorticity: bool = True, area: bool = True, handle: Optional[Handle] = None) -> Dict:
+    """Live derived quantities of a [2, H, W] float32 flow in one kernel launch:
+    {'vorticity': [H, W] float32 or None, 'area': [1] float64 (recirculation
+    area of Eq. RA) or None, 'probes': [n, 2] float32 or None}.  mask: [H, W]
+    uint8, 0 = masked.  probes: [n, 2] float32 points (x, y) in pixels."""
+    if flow.dim() != 3 or flow.shape[0] != 2 or flow.dtype != torch.float32 or not flow.is_cuda:
+        raise ValueError("flow must be a [2, H, W] float32 CUDA tensor")
+    if flow.stride(2) != 1 or flow.stride(0) != flow.shape[1] * flow.stride(1):
+        raise ValueError("flow planes must be row-major with the v plane height * pitch after the u plane")
+    _, h, w = flow.shape
+    hd = _stage_handle(flow, handle)
+    prm = OfvDerivedParams()
+    load().ofv_default_derived_params(byref(prm))
+    prm.dx, prm.dz, prm.dt, prm.streamwise_sign = float(dx), float(dz), float(dt), int(streamwise_sign)
+    mptr, mpitch = None, 0
+    if mask is not None:
+        if mask.dtype != torch.uint8 or mask.shape != (h, w) or mask.stride(1) != 1 or mask.device != flow.device:
+            raise ValueError("mask must be an [H, W] uint8 tensor with unit column stride on the flow's device")
+        mptr, mpitch = c_void_p(mask.data_ptr()), mask.stride(0)
+    om = torch.empty((h, w), dtype=torch.float32, device=flow.device) if vorticity else None
+    ar = torch.empty(1, dtype=torch.float64, device=flow.device) if area else None
+    n = 0
+    pxy = puv = None
+    if probes is not None:
+        pxy = probes.to(device=flow.device, dtype=torch.float32).contiguous().reshape(-1, 2)
+        n = pxy.shape[0]
+        puv = torch.empty((n, 2), dtype=torch.float32, device=flow.device)
+    check(load().ofv_derived(hd.ptr, c_void_p(flow.data_ptr()), w, h, flow.stride(1), mptr, mpitch, byref(prm),
+                             c_void_p(om.data_ptr()) if om is not None else None, w,
+                             c_void_p(pxy.data_ptr()) if n else None, n,
+                             c_void_p(puv.data_ptr()) if n else None,
+                             c_void_p(ar.data_ptr()) if ar is not None else None), hd.ptr)
+    return {"vorticity": om, "area": ar, "probes": puv if n else None}

@@ -51,6 +51,8 @@ struct ofv_ctx {
   size_t slot_bytes = 0;                   // one pair: 2 slabs + 2 flow buffers
   char* ws = nullptr;
   size_t ws_bytes = 0;
+  // two 64-bit counters of ofv_derived at the end of the workspace (zero between calls)
+  unsigned long long* acc = nullptr;
   std::string err;
   // work decomposition of the Gauss-Newton kernel: tuned table, forced choice
   struct TuneKey {
@@ -655,7 +657,7 @@ ofv_status ofv_create(ofv_handle* out, int device, int max_width, int max_height
   h->frame_bytes = round_up(off * 4, kSlabAlign);
   h->flow_bytes = round_up(2 * h->lpitch[0] * h->lh[0] * 4, kSlabAlign);
   h->slot_bytes = 2 * h->frame_bytes + 2 * h->flow_bytes;
-  h->ws_bytes = h->slot_bytes * static_cast<size_t>(max_batch);
+  h->ws_bytes = h->slot_bytes * static_cast<size_t>(max_batch) + kSlabAlign;
   if (device >= 0) {
     if (fault_injected("alloc")) {
       delete h;
@@ -675,6 +677,14 @@ ofv_status ofv_create(ofv_handle* out, int device, int max_width, int max_height
       const size_t h_bytes_tmp = h->ws_bytes;
       delete h;
       return fail(nullptr, OFV_ERR_OUT_OF_MEMORY, "hipMalloc(%zu bytes): %s", h_bytes_tmp, hipGetErrorString(e));
+    }
+    h->acc = reinterpret_cast<unsigned long long*>(h->ws + h->ws_bytes - kSlabAlign);
+    e = hipMemset(h->acc, 0, 2 * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+      (void)hipFree(h->ws);
+      delete h;
+      return fail(nullptr, OFV_ERR_DEVICE, "clearing the workspace counters: %s", hipGetErrorString(e));
     }
   }
   *out = h;
@@ -1004,6 +1014,84 @@ ofv_status ofv_destroy(ofv_handle h) {
   }
   delete h;
   return r;
+}
+
+// ------------------------------------------------------------------ live derived quantities
+
+void ofv_default_derived_params(ofv_derived_params* p) {
+  if (!p) return;
+  p->dx = 1.0f;
+  p->dz = 1.0f;
+  p->dt = 1.0f;
+  p->streamwise_sign = 1;
+}
+
+ofv_status ofv_derived(ofv_handle h, const float* flow, int width, int height, int64_t pitch, const uint8_t* mask,
+                       int64_t mask_pitch, const ofv_derived_params* params, float* vorticity, int64_t vort_pitch,
+                       const float* probe_xy, int n_probes, float* probe_uv, double* area) {
+  if (check_handle(h) != OFV_OK) return OFV_ERR_INVALID_ARG;
+  if (!flow) return fail(h, OFV_ERR_INVALID_ARG, "flow is NULL");
+  if (!params) return fail(h, OFV_ERR_INVALID_ARG, "params is NULL");
+  if (width < 1 || height < 1) return fail(h, OFV_ERR_INVALID_ARG, "size %dx%d invalid", width, height);
+  if (pitch < width) return fail(h, OFV_ERR_INVALID_ARG, "pitch < width");
+  if (mask && mask_pitch < width) return fail(h, OFV_ERR_INVALID_ARG, "mask_pitch < width");
+  if (vorticity && vort_pitch < width) return fail(h, OFV_ERR_INVALID_ARG, "vort_pitch < width");
+  const ofv_derived_params& p = *params;
+  for (float q : {p.dx, p.dz, p.dt})
+    if (!std::isfinite(q) || !(q > 0.0f)) return fail(h, OFV_ERR_INVALID_ARG, "dx, dz and dt must be finite and > 0");
+  if (p.streamwise_sign != 1 && p.streamwise_sign != -1)
+    return fail(h, OFV_ERR_INVALID_ARG, "streamwise_sign %d is not +1 or -1", p.streamwise_sign);
+  if (n_probes < 0 || n_probes > (1 << 20)) return fail(h, OFV_ERR_INVALID_ARG, "n_probes %d outside 0..2^20", n_probes);
+  if (n_probes > 0 && (!probe_xy || !probe_uv)) return fail(h, OFV_ERR_INVALID_ARG, "probe arrays are NULL");
+  if (2 * pitch * static_cast<int64_t>(height) * 4 >= 2 * kMaxPlaneBytes ||
+      (vorticity && vort_pitch * static_cast<int64_t>(height) * 4 >= kMaxPlaneBytes))
+    return fail(h, OFV_ERR_UNSUPPORTED, "planes of 2 GiB or more");
+  const uintptr_t f0 = reinterpret_cast<uintptr_t>(flow);
+  const uintptr_t f1 = f0 + static_cast<uintptr_t>(2 * pitch * static_cast<int64_t>(height) * 4);
+  if (vorticity) {
+    const uintptr_t o0 = reinterpret_cast<uintptr_t>(vorticity);
+    if (overlap(o0, o0 + static_cast<uintptr_t>(vort_pitch * static_cast<int64_t>(height) * 4), f0, f1))
+      return fail(h, OFV_ERR_INVALID_ARG, "vorticity overlaps the flow");
+  }
+  if (n_probes > 0) {
+    const uintptr_t o0 = reinterpret_cast<uintptr_t>(probe_uv);
+    if (overlap(o0, o0 + static_cast<uintptr_t>(n_probes) * 8, f0, f1))
+      return fail(h, OFV_ERR_INVALID_ARG, "probe_uv overlaps the flow");
+  }
+  if (area) {
+    const uintptr_t o0 = reinterpret_cast<uintptr_t>(area);
+    if (overlap(o0, o0 + sizeof(double), f0, f1)) return fail(h, OFV_ERR_INVALID_ARG, "area overlaps the flow");
+  }
+  if (!vorticity && !area && n_probes == 0) return OFV_OK;  // nothing requested
+  if (fault_injected("launch")) return fail(h, OFV_ERR_DEVICE, "injected launch failure");
+  if (h->device < 0) return fail(h, OFV_ERR_UNSUPPORTED, "validation-only handle (created with device -1)");
+  DeviceGuard g(h->device);
+  DerivedArgs a{};
+  a.u = flow;
+  a.v = flow + pitch * static_cast<int64_t>(height);
+  a.pitch = pitch;
+  a.w = width;
+  a.h = height;
+  a.mask = mask;
+  a.mask_pitch = mask_pitch;
+  a.cx = static_cast<float>((static_cast<double>(p.dz) / p.dx) / p.dt);
+  a.cy = static_cast<float>((static_cast<double>(p.dx) / p.dz) / p.dt);
+  a.sign = p.streamwise_sign;
+  a.ntiles = ((width + kDerivedTW - 1) / kDerivedTW) * ((height + kDerivedTH - 1) / kDerivedTH);
+  a.omega = vorticity;
+  a.omega_pitch = vort_pitch;
+  a.probe_xy = probe_xy;
+  a.probe_uv = probe_uv;
+  a.n_probes = n_probes;
+  a.su = static_cast<float>(static_cast<double>(p.dx) / p.dt);
+  a.sv = static_cast<float>(static_cast<double>(p.dz) / p.dt);
+  a.acc = h->acc;
+  a.area = area;
+  a.dx = p.dx;
+  a.dz = p.dz;
+  const int nblocks = std::max(a.ntiles, (n_probes + 255) / 256);
+  const hipError_t e = launch_derived(a, nblocks, h->stream);
+  return e == hipSuccess ? OFV_OK : device_error(h, e, "derived");
 }
 
 // ------------------------------------------------------------------ work-decomposition tuning

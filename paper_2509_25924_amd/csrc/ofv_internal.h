@@ -75,6 +75,29 @@ inline void reduce_multi_tile(int nlev, int& tw, int& th) {
   th = 8;
 }
 
+// ---------------------------------------------------------------- live derived quantities
+struct DerivedArgs {
+  const float* u;
+  const float* v;
+  int64_t pitch;
+  int w, h;
+  const uint8_t* mask;              // NULL: every pixel valid
+  int64_t mask_pitch;
+  float cx, cy;                     // (dz / dx) / dt and (dx / dz) / dt
+  int sign;                         // streamwise sign, +1 or -1
+  int ntiles;                       // workgroups covering the field
+  float* omega;                     // NULL: no vorticity
+  int64_t omega_pitch;
+  const float* probe_xy;
+  float* probe_uv;
+  int n_probes;
+  float su, sv;                     // dx / dt and dz / dt
+  unsigned long long* acc;          // [0] pixel count, [1] workgroups done (handle counter; 0 between calls)
+  double* area;                     // NULL: no area
+  double dx, dz;
+};
+constexpr int kDerivedTW = 64, kDerivedTH = 16;
+
 // ---------------------------------------------------------------- up-sampling (stage entry point)
 struct UpsampleArgs {
   const float* in_u; const float* in_v;
@@ -142,6 +165,7 @@ hipError_t launch_normalize(const NormArgs& a, int nblocks, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, int nblocks, hipStream_t s);
 hipError_t launch_reduce_multi(const ReduceMArgs& a, int nlev, int nblocks, hipStream_t s);
 hipError_t launch_upsample(const UpsampleArgs& a, hipStream_t s);
+hipError_t launch_derived(const DerivedArgs& a, int nblocks, hipStream_t s);
 // All jobs of one launch share the input-flow mode (a compile-time parameter of the kernel).
 hipError_t launch_gn(const GnArgs& a, int kr, int storage, int mode, int variant, int nblocks, hipStream_t s);
 

@@ -240,3 +240,34 @@ def test_missing_library_fails_loudly(tmp_path, monkeypatch):
     monkeypatch.setattr(_lib, "_lib", None)
     with pytest.raises(RuntimeError, match="missing"):
         _lib.load(str(tmp_path / "nope.so"))
+
+
+def test_derived_validation(lib, vhandle):
+    p = _lib.OfvDerivedParams()
+    lib.ofv_default_derived_params(byref(p))
+    assert (p.dx, p.dz, p.dt, p.streamwise_sign) == (1.0, 1.0, 1.0, 1)
+    flow, vort, area = c_void_p(0x100000), c_void_p(0x900000), c_void_p(0xA00000)
+    args = [vhandle, flow, 64, 32, 64, None, 0, byref(p), vort, 64, None, 0, None, area]
+    assert lib.ofv_derived(*args) == _lib.OFV_ERR_UNSUPPORTED             # valid, validation-only handle
+    bad = list(args); bad[1] = None
+    assert lib.ofv_derived(*bad) == _lib.OFV_ERR_INVALID_ARG
+    bad = list(args); bad[4] = 63
+    assert lib.ofv_derived(*bad) == _lib.OFV_ERR_INVALID_ARG
+    bad = list(args); bad[9] = 10
+    assert lib.ofv_derived(*bad) == _lib.OFV_ERR_INVALID_ARG
+    bad = list(args); bad[5] = c_void_p(0x800000)                           # mask with pitch 0
+    assert lib.ofv_derived(*bad) == _lib.OFV_ERR_INVALID_ARG
+    bad = list(args); bad[8] = c_void_p(0x100000 + 64 * 4)                  # vorticity inside the flow
+    assert lib.ofv_derived(*bad) == _lib.OFV_ERR_INVALID_ARG
+    assert b"overlaps" in lib.ofv_last_error(vhandle)
+    bad = list(args); bad[11] = 3                                           # probes without arrays
+    assert lib.ofv_derived(*bad) == _lib.OFV_ERR_INVALID_ARG
+    bad = list(args); bad[11] = (1 << 20) + 1
+    assert lib.ofv_derived(*bad) == _lib.OFV_ERR_INVALID_ARG
+    for field, val in (("dx", 0.0), ("dz", -1.0), ("dt", float("inf")), ("streamwise_sign", 2)):
+        q = _lib.OfvDerivedParams(p.dx, p.dz, p.dt, p.streamwise_sign)
+        setattr(q, field, val)
+        bad = list(args); bad[7] = byref(q)
+        assert lib.ofv_derived(*bad) == _lib.OFV_ERR_INVALID_ARG, field
+    none = [vhandle, flow, 64, 32, 64, None, 0, byref(p), None, 0, None, 0, None, None]
+    assert lib.ofv_derived(*none) == _lib.OFV_OK                            # nothing requested
