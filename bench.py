@@ -346,6 +346,56 @@ def suite_live21mp(args, dev):
     h2d = 20 * ring[0].numel() * 2 / (time.perf_counter() - t0) / 1e9
     byts = (_sweep_bytes(4, W, H, 3, 2 if storage != "f32" else 4, 2) + _sweep_bytes(4, 2048, 2048, 3, 2 if storage != "f32" else 4, 2)
             + _sweep_bytes(4, 1024, 1024, 3, 2 if storage != "f32" else 4, 2))
+
+    # live derived quantities of the 21 Mp field in every step (vorticity plane, recirculation area
+    # outside the cylinder, 64 probes along the wake centre line), captured in the same graph
+    yy, xx = torch.meshgrid(torch.arange(H, device=dev), torch.arange(W, device=dev), indexing="ij")
+    dmask = (((xx - 1024.0) ** 2 + (yy - 2048.0) ** 2) > 200.0 ** 2).to(torch.uint8)
+    del yy, xx
+    dprobes = torch.stack([torch.linspace(1300.0, 5000.0, 64), torch.full((64,), 2048.0)], 1).to(dev)
+    dkw = dict(mask=dmask, dx=1e-4, dz=1e-4, dt=0.01, probes=dprobes, handle=hb)   # 0.1 mm pixels, 100 Hz
+    held = {}
+
+    def batch_derived(a, b, p, ph):
+        batch_of(a, b, p)
+        held[ph] = ofv.derived(outs[0], **dkw)
+    graphs = [capture(lambda ph=ph: batch_derived(*pairs[ph], p, ph)) for ph in range(phases)]
+    k = [0]
+
+    def dstep():
+        graphs[k[0] % phases].replay()
+        k[0] += 1
+    sec_derived = _timed(dstep, steps, 16)
+    torch.cuda.synchronize()
+    eager = ofv.derived(outs[0], **dkw)
+    torch.cuda.synchronize()
+    last = held[(k[0] - 1) % phases]    # outputs of the graph replayed last
+    if not (torch.equal(eager["vorticity"], last["vorticity"]) and torch.equal(eager["area"], last["area"])
+            and torch.equal(eager["probes"], last["probes"])):
+        raise RuntimeError("derived quantities of the graph replay differ from an eager call")
+    del graphs
+    nrep = 50
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(nrep):
+            ofv.derived(outs[0], **dkw)
+    hb.bind_stream()
+    g.replay()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    d_us = e0.elapsed_time(e1) * 1e3 / nrep
+    del g
+    d_bytes = (8 + 1 + 4) * W * H          # flow in, mask in, vorticity out
+    derived_info = {"steps_per_s_with_derived": round(1.0 / sec_derived, 1),
+                    "kernel_us_5120x4096": round(d_us, 2), "bytes_per_call": d_bytes,
+                    "algorithmic_GBps": round(d_bytes / d_us / 1e3, 1),
+                    "frac_of_8TBps": round(d_bytes / d_us / 1e3 / HBM_PEAK_GBS, 4),
+                    "outputs": "vorticity plane, recirculation area (pixels outside the cylinder), 64 probes",
+                    "recirculation_area_cm2": round(float(eager["area"].item()) * 1e4, 3)}
     return {"metric": "live steps/s (5120x4096 + 2048^2 + 1024^2 uneven batch per step, hipGraph)",
             "value": round(1.0 / best, 1), "unit": "steps/s", "steps": steps, "best": best_key,
             "gvectors_per_s": round(vec / best / 1e9, 3), "steps_per_s_by_config": per,
@@ -355,6 +405,7 @@ def suite_live21mp(args, dev):
             "streaming": "one new 12-bit 5120x4096 frame (42 MB) per step, pinned host ring -> 3 device slots, "
                          "copy stream overlapped with the graph replay",
             "h2d_GBps_pinned": round(h2d, 1),
+            "derived": derived_info,
             "accuracy_1024_crop": acc,
             "data": "synthetic: 16 phases of a cylinder wake (potential flow + Lamb-Oseen street, max 10 px)"}
 

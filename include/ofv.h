@@ -233,9 +233,10 @@ void ofv_default_derived_params(ofv_derived_params* p);
  *    probe_xy (device float32 [n_probes][2], (x, y) in pixels).
  * mask (device uint8 plane, pitch mask_pitch; NULL = every pixel valid):
  * 0 marks a masked pixel.  Each output is skipped when its pointer is NULL
- * (probes when n_probes == 0).  One kernel launch; the area's partial counts
- * meet in a small counter of the handle that the last workgroup reads and
- * clears, so calls on one handle must not overlap (one handle per stream).
+ * (probes when n_probes == 0).  One kernel launch, plus a one-workgroup
+ * launch that sums the per-workgroup pixel counts (kept in the handle's
+ * workspace, so calls on one handle must not overlap: one handle per
+ * stream) when the area is requested.
  * OFV_ERR_INVALID_ARG for NULL flow, sizes below 1, pitches below width,
  * non-positive or non-finite dx, dz, dt, a sign other than +-1,
  * n_probes outside 0..2^20, NULL probe arrays with n_probes > 0, or an

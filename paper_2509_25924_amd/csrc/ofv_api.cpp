@@ -51,8 +51,8 @@ struct ofv_ctx {
   size_t slot_bytes = 0;                   // one pair: 2 slabs + 2 flow buffers
   char* ws = nullptr;
   size_t ws_bytes = 0;
-  // two 64-bit counters of ofv_derived at the end of the workspace (zero between calls)
-  unsigned long long* acc = nullptr;
+  // per-workgroup pixel counts of ofv_derived at the end of the workspace
+  unsigned int* derived_counts = nullptr;
   std::string err;
   // work decomposition of the Gauss-Newton kernel: tuned table, forced choice
   struct TuneKey {
@@ -657,7 +657,7 @@ ofv_status ofv_create(ofv_handle* out, int device, int max_width, int max_height
   h->frame_bytes = round_up(off * 4, kSlabAlign);
   h->flow_bytes = round_up(2 * h->lpitch[0] * h->lh[0] * 4, kSlabAlign);
   h->slot_bytes = 2 * h->frame_bytes + 2 * h->flow_bytes;
-  h->ws_bytes = h->slot_bytes * static_cast<size_t>(max_batch) + kSlabAlign;
+  h->ws_bytes = h->slot_bytes * static_cast<size_t>(max_batch) + kDerivedMaxBlocks * sizeof(unsigned int);
   if (device >= 0) {
     if (fault_injected("alloc")) {
       delete h;
@@ -678,14 +678,7 @@ ofv_status ofv_create(ofv_handle* out, int device, int max_width, int max_height
       delete h;
       return fail(nullptr, OFV_ERR_OUT_OF_MEMORY, "hipMalloc(%zu bytes): %s", h_bytes_tmp, hipGetErrorString(e));
     }
-    h->acc = reinterpret_cast<unsigned long long*>(h->ws + h->ws_bytes - kSlabAlign);
-    e = hipMemset(h->acc, 0, 2 * sizeof(unsigned long long));
-    if (e == hipSuccess) e = hipDeviceSynchronize();
-    if (e != hipSuccess) {
-      (void)hipFree(h->ws);
-      delete h;
-      return fail(nullptr, OFV_ERR_DEVICE, "clearing the workspace counters: %s", hipGetErrorString(e));
-    }
+    h->derived_counts = reinterpret_cast<unsigned int*>(h->ws + h->slot_bytes * static_cast<size_t>(max_batch));
   }
   *out = h;
   return OFV_OK;
@@ -1085,11 +1078,11 @@ ofv_status ofv_derived(ofv_handle h, const float* flow, int width, int height, i
   a.n_probes = n_probes;
   a.su = static_cast<float>(static_cast<double>(p.dx) / p.dt);
   a.sv = static_cast<float>(static_cast<double>(p.dz) / p.dt);
-  a.acc = h->acc;
+  a.partial = area ? h->derived_counts : nullptr;
   a.area = area;
   a.dx = p.dx;
   a.dz = p.dz;
-  const int nblocks = std::max(a.ntiles, (n_probes + 255) / 256);
+  const int nblocks = std::max(1, std::min(kDerivedMaxBlocks, std::max(a.ntiles, (n_probes + 255) / 256)));
   const hipError_t e = launch_derived(a, nblocks, h->stream);
   return e == hipSuccess ? OFV_OK : device_error(h, e, "derived");
 }

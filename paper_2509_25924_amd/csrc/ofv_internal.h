@@ -85,18 +85,19 @@ struct DerivedArgs {
   int64_t mask_pitch;
   float cx, cy;                     // (dz / dx) / dt and (dx / dz) / dt
   int sign;                         // streamwise sign, +1 or -1
-  int ntiles;                       // workgroups covering the field
+  int ntiles;                       // 64 x 16 tiles covering the field
   float* omega;                     // NULL: no vorticity
   int64_t omega_pitch;
   const float* probe_xy;
   float* probe_uv;
   int n_probes;
   float su, sv;                     // dx / dt and dz / dt
-  unsigned long long* acc;          // [0] pixel count, [1] workgroups done (handle counter; 0 between calls)
-  double* area;                     // NULL: no area
+  unsigned int* partial;            // per-workgroup pixel counts (handle workspace); NULL: no area
+  double* area;
   double dx, dz;
 };
-constexpr int kDerivedTW = 64, kDerivedTH = 16;
+constexpr int kDerivedTW = 64, kDerivedTH = 16;   // a lane: one column, 4 consecutive rows
+constexpr int kDerivedMaxBlocks = 2048;   // grid bound of the derived-quantities kernel (slots of partial counts)
 
 // ---------------------------------------------------------------- up-sampling (stage entry point)
 struct UpsampleArgs {

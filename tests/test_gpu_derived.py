@@ -79,7 +79,7 @@ def test_estimated_wake_field(ofv):
 
 
 def test_repeated_calls_and_graph_replays_keep_the_count(ofv):
-    """The handle's counters are cleared by every call: repeated eager calls
+    """The per-workgroup counts kept in the handle are rewritten by every call: repeated eager calls
     and several replays of a captured call (with other work in between)
     give the same exact area each time."""
     say("derived counters across calls and graph replays")
