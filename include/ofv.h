@@ -203,6 +203,27 @@ ofv_status ofv_tuning_export(ofv_handle h, char* buf, size_t cap, size_t* needed
  * any entry is malformed (OFV_ERR_INVALID_ARG). */
 ofv_status ofv_tuning_import(ofv_handle h, const char* text);
 
+/* ---- Time-resolved streaming (the paper's live regime: consecutive frames
+ * of one camera, pairs (t, t+1)).  Each pushed frame is normalised and its
+ * pyramid built once, into slot 0 of the handle's workspace; the next push
+ * pairs it with the new frame.  ofv_stream_push(h, frame, ...) returns with
+ * *produced = 0 on the first push after ofv_create, ofv_stream_reset or any
+ * other compute call on h (those reuse the same workspace), and otherwise
+ * writes to flow_out exactly what ofv_compute_flow_ex(previous frame, frame,
+ * params, flow_init, flow_out) writes, bit for bit, with *produced = 1.
+ * flow_init (nullable, e.g. the previous field as a warm start) and
+ * flow_out follow ofv_compute_flow_ex; flow_out must be valid on every push.
+ * num_levels, norm_radius, norm_eps and storage and the frame size must stay
+ * those of the retained frame (OFV_ERR_INVALID_ARG otherwise); the window
+ * radius, iterations and damping may change.  Host-side state: a push
+ * captured in a hipGraph replays with the slab roles it had when captured,
+ * so a graph loop alternates two captured pushes. */
+ofv_status ofv_stream_push(ofv_handle h, const ofv_image* frame, const ofv_params* params, const float* flow_init,
+                           float* flow_out, int* produced);
+
+/* Forget the retained frame (the next push produces no flow). */
+ofv_status ofv_stream_reset(ofv_handle h);
+
 /* ---- Live derived quantities (cylinder-wake experiment of the paper's
  * section on live measurements; Eq. RA): observables computed from each
  * measured field as it streams, so that no field needs to be stored. */

@@ -57,6 +57,9 @@ EXPORTS = {
                                           c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "ofv_set_gn_variant": (c_int, [c_void_p, c_int, c_int]),
     "ofv_default_derived_params": (None, [POINTER(OfvDerivedParams)]),
+    "ofv_stream_push": (c_int, [c_void_p, POINTER(OfvImage), POINTER(OfvParams), c_void_p, c_void_p,
+                                POINTER(c_int)]),
+    "ofv_stream_reset": (c_int, [c_void_p]),
     "ofv_derived": (c_int, [c_void_p, c_void_p, c_int, c_int, c_int64, c_void_p, c_int64, POINTER(OfvDerivedParams),
                             c_void_p, c_int64, c_void_p, c_int, c_void_p, c_void_p]),
     "ofv_stage_pyramid": (c_int, [c_void_p, c_int, c_void_p, c_int, c_int, c_int64, c_int, POINTER(c_void_p),

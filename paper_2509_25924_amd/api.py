@@ -83,6 +83,29 @@ class Handle:
     def load_tuning_table(self, text: str) -> None:
         check(load().ofv_tuning_import(self.ptr, text.encode()), self.ptr)
 
+    def stream_push(self, frame: torch.Tensor, params: Dict, flow_init: Optional[torch.Tensor] = None,
+                    bit_depth: Optional[int] = None, out: Optional[torch.Tensor] = None) -> Optional[torch.Tensor]:
+        """Push the next frame of a sequence: the flow from the previous pushed
+        frame to this one ([2, H, W]), or None on the first push.  Each frame
+        is normalised and reduced once."""
+        h, w = frame.shape
+        self.bind_stream()
+        if out is None:
+            out = torch.empty((2, h, w), dtype=torch.float32, device=frame.device)
+        _check_flow(out, h, w, "out")
+        if flow_init is not None:
+            _check_flow(flow_init, h, w, "flow_init")
+        img = image_desc(frame, bit_depth)
+        p = params_struct(params)
+        produced = ctypes.c_int(0)
+        check(load().ofv_stream_push(self.ptr, byref(img), byref(p),
+                                     c_void_p(flow_init.data_ptr()) if flow_init is not None else None,
+                                     c_void_p(out.data_ptr()), byref(produced)), self.ptr)
+        return out if produced.value else None
+
+    def stream_reset(self) -> None:
+        check(load().ofv_stream_reset(self.ptr), self.ptr)
+
     def fits(self, w: int, h: int, n: int = 1) -> bool:
         return w <= self.max_width and h <= self.max_height and n <= self.max_batch
 

@@ -53,6 +53,11 @@ struct ofv_ctx {
   size_t ws_bytes = 0;
   // per-workgroup pixel counts of ofv_derived at the end of the workspace
   unsigned int* derived_counts = nullptr;
+  // streaming (ofv_stream_push): slab of slot 0 holding the last pushed frame's pyramid
+  bool stream_valid = false;
+  int stream_slab = 0;
+  int stream_w = 0, stream_h = 0;
+  ofv_params stream_params{};
   std::string err;
   // work decomposition of the Gauss-Newton kernel: tuned table, forced choice
   struct TuneKey {
@@ -184,6 +189,8 @@ struct PairPlan {
   float* out;
   int lw[OFV_MAX_LEVELS], lh[OFV_MAX_LEVELS];
   char* slot;
+  int slab[2] = {0, 1};          // pyramid slab of the slot that holds frame k
+  bool built[2] = {false, false};  // frame k's pyramid is already in its slab (streaming)
 };
 
 void level_dims(int w, int hgt, int levels, int* lw, int* lh) {
@@ -196,7 +203,7 @@ void level_dims(int w, int hgt, int levels, int* lw, int* lh) {
 }
 
 char* img_plane(const ofv_ctx* h, const PairPlan& pp, int frame, int level, size_t ts) {
-  return pp.slot + frame * h->frame_bytes + static_cast<size_t>(h->img_off[level]) * ts;
+  return pp.slot + pp.slab[frame] * h->frame_bytes + static_cast<size_t>(h->img_off[level]) * ts;
 }
 
 float* flow_buf(const ofv_ctx* h, const PairPlan& pp, int which) {
@@ -282,7 +289,10 @@ ofv_status run_chunked(ofv_ctx* h, int njobs, Args& args, Fill fill, Launch laun
 
 // save (optional, n == 1): per (level l, iteration k) at index l * IT + k, the u plane
 // that receives that iteration's output (v plane lpitch[l] * lh[l] further).
-ofv_status run_pipeline(ofv_ctx* h, int n, PairPlan* pp, const ofv_params* p, float* const* save = nullptr) {
+ofv_status run_pipeline(ofv_ctx* h, int n, PairPlan* pp, const ofv_params* p, float* const* save = nullptr,
+                        bool pyramid_only = false) {
+  // any run rewrites the slabs of the slots it uses: a retained streaming frame is gone
+  h->stream_valid = false;
   const int L = p->num_levels;
   const int kr = p->kernel_radius;
   const int it = p->iterations;
@@ -290,6 +300,12 @@ ofv_status run_pipeline(ofv_ctx* h, int n, PairPlan* pp, const ofv_params* p, fl
   const size_t ts = storage_bytes(st);
   hipStream_t s = h->stream;
 
+  // frames whose pyramid is still to be built: (pair, frame)
+  std::vector<std::pair<int, int>> fj;
+  for (int j = 0; j < n; ++j)
+    for (int k = 0; k < 2; ++k)
+      if (!pp[j].built[k]) fj.emplace_back(j, k);
+  const int nf = static_cast<int>(fj.size());
   // Step 1: normalisation of both frames of every pair -> level 0.
   {
     NormArgs na{};
@@ -297,19 +313,19 @@ ofv_status run_pipeline(ofv_ctx* h, int n, PairPlan* pp, const ofv_params* p, fl
     na.eps = p->norm_eps;
     na.storage = st;
     auto fill = [&](int i, NormJob& J) {
-      const PairPlan& q = pp[i / 2];
-      const ofv_image* f = q.f[i % 2];
+      const PairPlan& q = pp[fj[i].first];
+      const ofv_image* f = q.f[fj[i].second];
       J.in = f->data;
       J.in_pitch = f->pitch;
       J.type = f->type;
       J.bits = f->bit_depth;
       J.w = f->width;
       J.h = f->height;
-      J.out = img_plane(h, q, i % 2, 0, ts);
+      J.out = img_plane(h, q, fj[i].second, 0, ts);
       J.out_pitch = h->lpitch[0];
       return ((J.w + 63) / 64) * ((J.h + 15) / 16);
     };
-    ofv_status r = run_chunked(h, 2 * n, na, fill,
+    ofv_status r = run_chunked(h, nf, na, fill,
                                [&](const NormArgs& a, int b) { return launch_normalize(a, b, s); }, "normalize");
     if (r != OFV_OK) return r;
   }
@@ -322,16 +338,16 @@ ofv_status run_pipeline(ofv_ctx* h, int n, PairPlan* pp, const ofv_params* p, fl
       ra.storage = st;
       ra.scale = 1.0f;
       auto fill = [&](int i, ReduceJob& J) {
-        const PairPlan& q = pp[i / 2];
-        J.in = img_plane(h, q, i % 2, l - 1, ts);
-        J.out = img_plane(h, q, i % 2, l, ts);
+        const PairPlan& q = pp[fj[i].first];
+        J.in = img_plane(h, q, fj[i].second, l - 1, ts);
+        J.out = img_plane(h, q, fj[i].second, l, ts);
         J.in_pitch = h->lpitch[l - 1];
         J.out_pitch = h->lpitch[l];
         J.w = q.lw[l - 1];
         J.h = q.lh[l - 1];
         return ((q.lw[l] + 63) / 64) * ((q.lh[l] + 3) / 4);
       };
-      r = run_chunked(h, 2 * n, ra, fill, [&](const ReduceArgs& a, int b) { return launch_reduce(a, b, s); },
+      r = run_chunked(h, nf, ra, fill, [&](const ReduceArgs& a, int b) { return launch_reduce(a, b, s); },
                       "reduce");
     } else {
       ReduceMArgs ra{};
@@ -339,11 +355,11 @@ ofv_status run_pipeline(ofv_ctx* h, int n, PairPlan* pp, const ofv_params* p, fl
       int tw = 0, th = 0;
       reduce_multi_tile(nlev, tw, th);
       auto fill = [&](int i, ReduceMJob& J) {
-        const PairPlan& q = pp[i / 2];
-        J.in = img_plane(h, q, i % 2, l - 1, ts);
+        const PairPlan& q = pp[fj[i].first];
+        J.in = img_plane(h, q, fj[i].second, l - 1, ts);
         J.in_pitch = h->lpitch[l - 1];
         for (int k = 0; k < nlev; ++k) {
-          J.out[k] = img_plane(h, q, i % 2, l + k, ts);
+          J.out[k] = img_plane(h, q, fj[i].second, l + k, ts);
           J.out_pitch[k] = h->lpitch[l + k];
         }
         J.w = q.lw[l - 1];
@@ -351,12 +367,13 @@ ofv_status run_pipeline(ofv_ctx* h, int n, PairPlan* pp, const ofv_params* p, fl
         const int d = l + nlev - 1;  // deepest level of the launch
         return ((q.lw[d] + tw - 1) / tw) * ((q.lh[d] + th - 1) / th);
       };
-      r = run_chunked(h, 2 * n, ra, fill,
+      r = run_chunked(h, nf, ra, fill,
                       [&](const ReduceMArgs& a, int b) { return launch_reduce_multi(a, nlev, b, s); }, "reduce");
     }
     if (r != OFV_OK) return r;
     l += nlev;
   }
+  if (pyramid_only) return OFV_OK;
   // Initial flow: restricted to the coarsest level by REDUCE / 2 (pairs that have one).
   std::vector<int> cur(n, -1);  // flow buffer holding the current field, -1 = zero field
   std::vector<int> with_init;
@@ -1007,6 +1024,60 @@ ofv_status ofv_destroy(ofv_handle h) {
   }
   delete h;
   return r;
+}
+
+// ------------------------------------------------------------------ time-resolved streaming
+
+ofv_status ofv_stream_reset(ofv_handle h) {
+  if (check_handle(h) != OFV_OK) return OFV_ERR_INVALID_ARG;
+  h->stream_valid = false;
+  return OFV_OK;
+}
+
+ofv_status ofv_stream_push(ofv_handle h, const ofv_image* frame, const ofv_params* params, const float* flow_init,
+                           float* flow_out, int* produced) {
+  if (check_handle(h) != OFV_OK) return OFV_ERR_INVALID_ARG;
+  if (!frame || !produced) return fail(h, OFV_ERR_INVALID_ARG, "frame or produced is NULL");
+  *produced = 0;
+  ofv_status r = check_params(h, params);
+  if (r != OFV_OK) return r;
+  r = validate_pair(h, frame, frame, flow_init, flow_out, 0);
+  if (r != OFV_OK) return r;
+  const ofv_params& p = *params;
+  const bool have = h->stream_valid;
+  if (have) {
+    const ofv_params& q = h->stream_params;
+    if (frame->width != h->stream_w || frame->height != h->stream_h)
+      return fail(h, OFV_ERR_INVALID_ARG, "frame is %dx%d, the retained frame %dx%d (ofv_stream_reset first)",
+                  frame->width, frame->height, h->stream_w, h->stream_h);
+    if (p.num_levels != q.num_levels || p.norm_radius != q.norm_radius || p.norm_eps != q.norm_eps ||
+        p.storage != q.storage)
+      return fail(h, OFV_ERR_INVALID_ARG,
+                  "num_levels, norm_radius, norm_eps and storage must match the retained frame (ofv_stream_reset first)");
+  }
+  if (fault_injected("launch")) return fail(h, OFV_ERR_DEVICE, "injected launch failure");
+  if (h->device < 0) return fail(h, OFV_ERR_UNSUPPORTED, "validation-only handle (created with device -1)");
+  DeviceGuard g(h->device);
+  PairPlan pp;
+  pp.f[0] = nullptr;  // the retained frame: its pyramid is in slab stream_slab
+  pp.f[1] = frame;
+  pp.init = flow_init;
+  pp.out = flow_out;
+  pp.slot = h->ws;
+  level_dims(frame->width, frame->height, p.num_levels, pp.lw, pp.lh);
+  const int new_slab = have ? 1 - h->stream_slab : 0;
+  pp.slab[0] = h->stream_slab;
+  pp.slab[1] = new_slab;
+  pp.built[0] = true;
+  r = run_pipeline(h, 1, &pp, params, nullptr, !have);
+  if (r != OFV_OK) return r;
+  h->stream_valid = true;
+  h->stream_slab = new_slab;
+  h->stream_w = frame->width;
+  h->stream_h = frame->height;
+  h->stream_params = p;
+  *produced = have ? 1 : 0;
+  return OFV_OK;
 }
 
 // ------------------------------------------------------------------ live derived quantities

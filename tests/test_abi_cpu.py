@@ -271,3 +271,21 @@ def test_derived_validation(lib, vhandle):
         assert lib.ofv_derived(*bad) == _lib.OFV_ERR_INVALID_ARG, field
     none = [vhandle, flow, 64, 32, 64, None, 0, byref(p), None, 0, None, 0, None, None]
     assert lib.ofv_derived(*none) == _lib.OFV_OK                            # nothing requested
+
+
+def test_stream_validation(lib, vhandle):
+    img = _img()
+    p = _params()
+    produced = ctypes.c_int(7)
+    assert lib.ofv_stream_push(vhandle, byref(img), byref(p), None, c_void_p(OUT), None) == _lib.OFV_ERR_INVALID_ARG
+    assert lib.ofv_stream_push(vhandle, None, byref(p), None, c_void_p(OUT), byref(produced)) == \
+        _lib.OFV_ERR_INVALID_ARG
+    bad = _params(num_levels=0)
+    assert lib.ofv_stream_push(vhandle, byref(img), byref(bad), None, c_void_p(OUT), byref(produced)) == \
+        _lib.OFV_ERR_INVALID_ARG
+    assert produced.value == 0
+    assert lib.ofv_stream_push(vhandle, byref(img), byref(p), None, None, byref(produced)) == _lib.OFV_ERR_INVALID_ARG
+    assert lib.ofv_stream_push(vhandle, byref(img), byref(p), None, c_void_p(OUT), byref(produced)) == \
+        _lib.OFV_ERR_UNSUPPORTED
+    assert lib.ofv_stream_reset(vhandle) == _lib.OFV_OK
+    assert lib.ofv_stream_reset(None) == _lib.OFV_ERR_INVALID_ARG
