@@ -91,7 +91,8 @@ def parse():
     ap.add_argument("--pmc-probe", action="store_true",
                     help="for hardware-counter runs: launch a 256 MiB elementwise negation and a 256 MiB copy 3 times each, then the full-resolution "
                          "Gauss-Newton kernel 5 times in each decomposition, and exit")
-    ap.add_argument("--suite", default=None, choices=["batch4mp", "live21mp", "adjoint512", "paper", "all"],
+    ap.add_argument("--suite", default=None,
+                    choices=["batch4mp", "live21mp", "stream21mp", "adjoint512", "paper", "all"],
                     help="run an additional measurement instead of the default workload (one JSON line each)")
     return ap.parse_args()
 
@@ -410,6 +411,88 @@ def suite_live21mp(args, dev):
             "data": "synthetic: 16 phases of a cylinder wake (potential flow + Lamb-Oseen street, max 10 px)"}
 
 
+def suite_stream21mp(args, dev):
+    """A time-resolved 5120x4096 sequence (16 frames of a cylinder wake, cycled): pair calls that normalise
+    and reduce both frames of every pair, against pushes that normalise and reduce each new frame once
+    and pair it with the retained pyramid of the previous one; both as hipGraph loops, the live
+    configuration's parameters (L 4, KR 10, IT 3, NR 2, FP32 storage)."""
+    import torch
+    import paper_2509_25924_amd as ofv
+    import synth
+    from synth.gpu_render import make_pair_device
+    W, H = 5120, 4096
+    nf = 16
+    seq = []
+    for ph in range(nf):
+        flow = synth.CylinderWake(H, W, t=200.0 * ph / nf, dmax=10.0)
+        a, _, _ = make_pair_device(H, W, flow, fwhm=2.5, ppp=0.1, seed=4000 + ph, bit_depth=12,
+                                   noise=0.01 * 4095, device=dev, max_disp=10.0, with_gt=False)
+        seq.append(a)
+    prm = {"num_levels": 4, "kernel_radius": 10, "iterations": 3, "norm_radius": 2}
+    h = ofv.Handle(W, H, 1)
+    out = torch.empty((2, H, W), dtype=torch.float32, device=dev)
+
+    def capture(fn):
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            fn()
+        torch.cuda.current_stream().wait_stream(s)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            fn()
+        h.bind_stream()
+        return g
+
+    steps = 200
+    # pair calls: step k computes (frame k-1, frame k)
+    graphs = [capture(lambda k=k: ofv.compute_flow(seq[(k - 1) % nf], seq[k], prm, bit_depth=12, out=out,
+                                                   handle=h)) for k in range(nf)]
+    kk = [1]
+
+    def pair_step():
+        graphs[kk[0] % nf].replay()
+        kk[0] += 1
+    sec_pair = _timed(pair_step, steps, 16)
+    torch.cuda.synchronize()
+    ref = out.clone()                                   # pair (frame k-1, frame k) of the last replay
+    last_k = (kk[0] - 1) % nf
+    del graphs
+    # pushes: frame k goes to slab k % 2 (nf is even, so the slab of a frame never changes)
+    h.stream_reset()
+    h.stream_push(seq[0], prm, bit_depth=12, out=out)
+    pushes = {}
+    for k in list(range(1, nf)) + [0]:
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            h.stream_push(seq[k], prm, bit_depth=12, out=out)
+        pushes[k] = g
+    h.bind_stream()
+    h.stream_reset()
+    h.stream_push(seq[0], prm, bit_depth=12, out=out)   # retained frame 0 in slab 0, as at capture
+    ks = [1]
+
+    def push_step():
+        pushes[ks[0] % nf].replay()
+        ks[0] += 1
+    # the replays must continue the sequence from frame 1: warm-up and timed steps run in order
+    sec_push = _timed(push_step, steps, 16)
+    torch.cuda.synchronize()
+    # the push loop ends on frame (ks - 1); recompute the pair check for the same frames
+    lk = (ks[0] - 1) % nf
+    chk = ofv.compute_flow(seq[(lk - 1) % nf], seq[lk], prm, bit_depth=12, handle=ofv.Handle(W, H, 1))
+    torch.cuda.synchronize()
+    if not torch.equal(chk, out):
+        raise RuntimeError("streamed field differs from the pair call on the same frames")
+    del pushes
+    return {"metric": "time-resolved 5120x4096 sequence: steps/s with each frame reduced once (stream push) vs "
+                      "pair calls", "value": round(1.0 / sec_push, 1), "unit": "steps/s", "steps": steps,
+            "pair_calls_steps_per_s": round(1.0 / sec_pair, 1), "speedup": round(sec_pair / sec_push, 3),
+            "ms_per_step_stream": round(sec_push * 1e3, 3), "ms_per_step_pairs": round(sec_pair * 1e3, 3),
+            "checked": f"streamed field of frames ({(lk - 1) % nf}, {lk}) equals the pair call bit for bit",
+            "params": prm, "data": "synthetic: 16 frames of a cylinder wake (potential flow + Lamb-Oseen street)"}
+
+
 def suite_adjoint512(args, dev):
     """Backward/forward cost: 16 float 512x512 pairs, loss sum |V - V_gt|^2."""
     import torch
@@ -485,9 +568,9 @@ def run_suite(args):
         _build.build()
     ofv.load()
     dev = torch.device("cuda:0")
-    names = ["batch4mp", "live21mp", "adjoint512", "paper"] if args.suite == "all" else [args.suite]
-    fns = {"batch4mp": suite_batch4mp, "live21mp": suite_live21mp, "adjoint512": suite_adjoint512,
-           "paper": suite_paper}
+    names = ["batch4mp", "live21mp", "stream21mp", "adjoint512", "paper"] if args.suite == "all" else [args.suite]
+    fns = {"batch4mp": suite_batch4mp, "live21mp": suite_live21mp, "stream21mp": suite_stream21mp,
+           "adjoint512": suite_adjoint512, "paper": suite_paper}
     for nm in names:
         print(f"# suite {nm} ...", file=sys.stderr, flush=True)
         r = fns[nm](args, dev)
