@@ -91,8 +91,10 @@ def parse():
     ap.add_argument("--pmc-probe", action="store_true",
                     help="for hardware-counter runs: launch a 256 MiB elementwise negation and a 256 MiB copy 3 times each, then the full-resolution "
                          "Gauss-Newton kernel 5 times in each decomposition, and exit")
+    ap.add_argument("--sweep-realisations", type=int, default=10,
+                    help="particle fields per image of the accuracy sweep (the paper uses 10)")
     ap.add_argument("--suite", default=None,
-                    choices=["batch4mp", "live21mp", "stream21mp", "adjoint512", "paper", "all"],
+                    choices=["batch4mp", "live21mp", "stream21mp", "sweep", "adjoint512", "paper", "all"],
                     help="run an additional measurement instead of the default workload (one JSON line each)")
     return ap.parse_args()
 
@@ -493,6 +495,94 @@ def suite_stream21mp(args, dev):
             "params": prm, "data": "synthetic: 16 frames of a cylinder wake (potential flow + Lamb-Oseen street)"}
 
 
+def suite_sweep(args, dev):
+    """The paper's accuracy study on synthetic Rankine vortices, on the batched estimator: every image of
+    its Rankine grid (maximum displacement 8-32 px x 5-15 particles per 16x16 window x core radius
+    12-150 px: 72 images of 1024^2, 8-bit, no noise) x every setting of its estimator grid (KR 2-7,
+    PSL 2-4, IT 1-4, NR 1-4: 288), for `--sweep-realisations` particle fields; scored by Psi and <Err>;
+    the setting with the lowest Psi per (core radius, displacement), compared with the paper's table."""
+    import itertools
+    import json as _json
+    import numpy as np
+    import torch
+    import paper_2509_25924_amd as ofv
+    import synth
+    from synth import metrics as M
+    from synth.gpu_render import make_pair_device
+    S = 1024
+    c = (S - 1) / 2.0
+    nreal = args.sweep_realisations
+    ig, og = M.rankine_grid(), M.ofv_grid()
+    imgs = list(itertools.product(ig["dmax"], ig["part_per_iw"], ig["radius"]))
+    settings = list(itertools.product(og["kernel_radius"], og["psl"], og["iterations"], og["norm_radius"]))
+    fwhm = 0.75 * synth.FWHM_PER_SIGMA          # particle image diameter 3 px taken as the e^-2 diameter (4 sigma)
+    vort = [synth.Rankine(c, c, float(R), float(D)) for D, _, R in imgs]
+    yy, xx = np.mgrid[0:S, 0:S].astype(np.float64)
+    gts = torch.stack([torch.as_tensor(np.stack(v(xx, yy)), dtype=torch.float32) for v in vort]).to(dev)
+    del yy, xx
+    radii = sorted(set(R for _, _, R in imgs))
+    unf = {R: M.Unfolding(c, c, M.default_r_max(R, S, S), dev) for R in radii}
+    groups = {R: [i for i, (_, _, r) in enumerate(imgs) if r == R] for R in radii}
+    theory = {R: torch.stack([unf[R].theory(vort[i], torch.float32) for i in groups[R]]) for R in radii}
+    n = len(imgs)
+    hd = ofv.Handle(S, S, n)
+    outs = [torch.empty((2, S, S), dtype=torch.float32, device=dev) for _ in range(n)]
+    psi_sum = np.zeros((n, len(settings)))
+    err_sum = np.zeros((n, len(settings)))
+    est_s, t_start = 0.0, time.perf_counter()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for rz in range(nreal):
+        f0, f1 = [], []
+        for i, (D, ppi, R) in enumerate(imgs):
+            a, b, _ = make_pair_device(S, S, vort[i], fwhm=fwhm, ppp=ppi / 256.0, seed=7000 + 1000 * rz + i,
+                                       bit_depth=8, noise=0.0, device=dev, max_disp=float(D))
+            f0.append(a)
+            f1.append(b)
+        for si, (kr, psl, it, nr) in enumerate(settings):
+            prm = {"num_levels": psl + 1, "kernel_radius": kr, "iterations": it, "norm_radius": nr}
+            e0.record()
+            ofv.compute_flow_batch(f0, f1, prm, bit_depth=8, outs=outs, handle=hd)
+            e1.record()
+            for R in radii:
+                idx = groups[R]
+                fl = torch.stack([outs[i] for i in idx])
+                psi_sum[idx, si] += unf[R].psi(fl, theory[R]).cpu().numpy()
+                err_sum[idx, si] += M.mean_endpoint_error(fl, gts[idx], 16).cpu().numpy()
+            est_s += e0.elapsed_time(e1) / 1e3
+        del f0, f1
+    total_s = time.perf_counter() - t_start
+    psi_m, err_m = psi_sum / nreal, err_sum / nreal
+    paper = _json.load(open(os.path.join(ROOT, "tests", "golden", "paper_numbers.json")))["rankine_best_settings"]
+    rows = []
+    for R, D, ppi_p, kr_p, nr_p, psl_p, it_p in paper["rows"]:
+        cand = [i for i, (d, _, r) in enumerate(imgs) if d == D and r == R]
+        i, si = min(((i, int(np.argmin(psi_m[i]))) for i in cand), key=lambda t: psi_m[t[0], t[1]])
+        kr, psl, it, nr = settings[si]
+        rows.append({"R": R, "D": D, "D_over_R": round(D / R, 3), "particles_per_iw": imgs[i][1], "KR": kr,
+                     "NR": nr, "PSL": psl, "IT": it, "psi": round(float(psi_m[i, si]), 4),
+                     "mean_err_px": round(float(err_m[i, si]), 4),
+                     "paper": {"particles_per_iw": ppi_p, "KR": kr_p, "NR": nr_p, "PSL": psl_p, "IT": it_p}})
+
+    def spearman(a, b):
+        rank = lambda x: np.argsort(np.argsort(np.asarray(x, float), kind="stable"), kind="stable").astype(float)
+        return float(np.corrcoef(rank(a), rank(b))[0, 1])
+    dr = [r["D_over_R"] for r in rows]
+    ours_kr = [r["KR"] for r in rows]
+    paper_kr = [r["paper"]["KR"] for r in rows]
+    flows = n * len(settings) * nreal
+    return {"metric": "accuracy sweep: Rankine image grid x estimator grid, fields/s of the batched estimator",
+            "value": round(flows / est_s, 1), "unit": "fields/s", "fields": flows, "realisations": nreal,
+            "estimator_seconds": round(est_s, 2), "wall_seconds": round(total_s, 1),
+            "spearman_DR_vs_best_KR": {"ours": round(spearman(dr, ours_kr), 3),
+                                        "paper": round(spearman(dr, paper_kr), 3)},
+            "best_KR_equal_to_paper": int(sum(a == b for a, b in zip(ours_kr, paper_kr))),
+            "best_KR_mean_abs_diff": round(float(np.mean(np.abs(np.subtract(ours_kr, paper_kr)))), 3),
+            "best_psi_median": round(float(np.median([r["psi"] for r in rows])), 4),
+            "best_settings": rows,
+            "data": "synthetic Rankine vortices at 1024^2 (Gaussian particles of 3 px e^-2 diameter, 8-bit, no "
+                    "noise, no out-of-plane loss) standing in for the paper's generator images"}
+
+
 def suite_adjoint512(args, dev):
     """Backward/forward cost: 16 float 512x512 pairs, loss sum |V - V_gt|^2."""
     import torch
@@ -568,8 +658,10 @@ def run_suite(args):
         _build.build()
     ofv.load()
     dev = torch.device("cuda:0")
-    names = ["batch4mp", "live21mp", "stream21mp", "adjoint512", "paper"] if args.suite == "all" else [args.suite]
+    names = (["batch4mp", "live21mp", "stream21mp", "sweep", "adjoint512", "paper"] if args.suite == "all"
+             else [args.suite])
     fns = {"batch4mp": suite_batch4mp, "live21mp": suite_live21mp, "stream21mp": suite_stream21mp,
+           "sweep": suite_sweep,
            "adjoint512": suite_adjoint512, "paper": suite_paper}
     for nm in names:
         print(f"# suite {nm} ...", file=sys.stderr, flush=True)
