@@ -37,6 +37,12 @@ restated where it is used):
  R8  Up-sampling is V_fine(X, Y) = 2 * bilinear(V_coarse, X / 2, Y / 2).
  R9  The same IT at every level; V = 0 at the coarsest level, or the
      optional initial field restricted by REDUCE / 2 per level.
+ R24 The forward-additive estimator the paper contrasts its symmetric
+     objective with (estimator="forward_additive"): the residual
+     I1(k + V) - I0(k) is linearised about V(k) with G the central-difference
+     gradient of the warped second image, so the step keeps the same normal
+     equations with S = W1 = P1(k + V), T = W1 - P0(k); V is then anchored
+     at the pixels of frame 0 instead of the midpoint.
 
 Besides the method itself, compute_flow can round every image plane (the
 normalised frames and each REDUCE output) to a storage type, leaving all
@@ -222,8 +228,17 @@ def warp_terms(p0: torch.Tensor, p1: torch.Tensor, u: torch.Tensor, v: torch.Ten
     return 0.5 * (w0 + w1), w1 - w0
 
 
+def warp_terms_forward(p0: torch.Tensor, p1: torch.Tensor, u: torch.Tensor, v: torch.Tensor):
+    """Forward-additive warps (R24): W1 = P1(k + V); S = W1 and T = W1 - P0(k)."""
+    h, w = p0.shape
+    yy, xx = torch.meshgrid(torch.arange(h, dtype=DT), torch.arange(w, dtype=DT), indexing="ij")
+    w1 = bilinear(p1, xx + u, yy + v)
+    return w1, w1 - p0
+
+
 def gn_iteration(p0: torch.Tensor, p1: torch.Tensor, u: torch.Tensor, v: torch.Tensor,
-                 kr: int, reg_rel: float, reg_abs: float, terms: Optional[list] = None):
+                 kr: int, reg_rel: float, reg_abs: float, terms: Optional[list] = None,
+                 estimator: str = "symmetric"):
     """One Jacobi Gauss-Newton update of the flow at every pixel (R5).
 
     At each pixel k the residual I0(k - V/2) - I1(k + V/2) of Eq. (of_symmetric)
@@ -233,8 +248,14 @@ def gn_iteration(p0: torch.Tensor, p1: torch.Tensor, u: torch.Tensor, v: torch.T
         A = sum_{k in N(m)} G G^T,   c = sum_{k in N(m)} G b,   b = G . V(k) - T.
     With damping lam = reg_rel (Sxx + Syy) + reg_abs towards the current V(m),
     (A + lam I) V'(m) = c + lam V(m) is solved by Cramer's rule.
+    estimator="forward_additive" takes the warps of R24 instead.
     """
-    s, t = warp_terms(p0, p1, u, v)
+    if estimator == "symmetric":
+        s, t = warp_terms(p0, p1, u, v)
+    elif estimator == "forward_additive":
+        s, t = warp_terms_forward(p0, p1, u, v)
+    else:
+        raise ValueError(f"unknown estimator {estimator!r}")
     gx, gy = central_gradient(s)
     b = gx * u + gy * v - t
     sxx = window_sum(gx * gx, kr)
@@ -292,7 +313,8 @@ def compute_flow(frame0, frame1, params: Dict, bit_depth0: int = 8, bit_depth1: 
     """Dense displacement field (u, v) in px/frame at full resolution.
 
     params: num_levels (PSL + 1), kernel_radius (KR), iterations (IT),
-    norm_radius (NR), and optionally norm_eps, reg_rel, reg_abs.
+    norm_radius (NR), and optionally norm_eps, reg_rel, reg_abs and
+    estimator ("symmetric", the paper's, or "forward_additive", R24).
     Returns a float64 tensor [2, H, W]; u along +x (columns), v along +y
     (rows), mapping frame0 to frame1, defined at the midpoint.
     plane_round ("f32", "f16", "bf16" or None) rounds every image plane to
@@ -332,7 +354,8 @@ def compute_flow(frame0, frame1, params: Dict, bit_depth0: int = 8, bit_depth1: 
         if trace is not None:
             trace.flow_in[lev] = (u, v)
         for k in range(it):
-            u, v = gn_iteration(pyr0[lev], pyr1[lev], u, v, kr, p["reg_rel"], p["reg_abs"])
+            u, v = gn_iteration(pyr0[lev], pyr1[lev], u, v, kr, p["reg_rel"], p["reg_abs"],
+                                estimator=p.get("estimator", "symmetric"))
             if trace is not None:
                 trace.iterates[(lev, k)] = (u, v)
     # step 6: full-resolution field

@@ -61,7 +61,7 @@ def bf_bilinear(p: np.ndarray, x: float, y: float) -> float:
 
 
 def bf_gn_iteration(p0: np.ndarray, p1: np.ndarray, u: np.ndarray, v: np.ndarray, kr: int,
-                    reg_rel: float, reg_abs: float):
+                    reg_rel: float, reg_abs: float, forward_additive: bool = False):
     """One Jacobi step: per-window least squares with Levenberg damping rows.
 
     For every m, the linear model of the residual at each k in the window is
@@ -74,9 +74,14 @@ def bf_gn_iteration(p0: np.ndarray, p1: np.ndarray, u: np.ndarray, v: np.ndarray
     t = np.zeros((h, w))
     for y in range(h):
         for x in range(w):
-            w0 = bf_bilinear(p0, x - u[y, x] / 2.0, y - v[y, x] / 2.0)
-            w1 = bf_bilinear(p1, x + u[y, x] / 2.0, y + v[y, x] / 2.0)
-            s[y, x] = (w0 + w1) / 2.0
+            if forward_additive:   # I1(k + V) - I0(k), gradient of the warped second image
+                w0 = p0[y, x]
+                w1 = bf_bilinear(p1, x + u[y, x], y + v[y, x])
+                s[y, x] = w1
+            else:
+                w0 = bf_bilinear(p0, x - u[y, x] / 2.0, y - v[y, x] / 2.0)
+                w1 = bf_bilinear(p1, x + u[y, x] / 2.0, y + v[y, x] / 2.0)
+                s[y, x] = (w0 + w1) / 2.0
             t[y, x] = w1 - w0
     g = np.zeros((h, w, 2))
     for y in range(h):
@@ -114,7 +119,7 @@ def bf_upsample(uc: np.ndarray, h: int, w: int) -> np.ndarray:
 
 def bf_compute_flow(i0: np.ndarray, i1: np.ndarray, levels: int, kr: int, it: int, nr: int,
                     eps: float, reg_rel: float, reg_abs: float,
-                    flow_init: Optional[np.ndarray] = None) -> np.ndarray:
+                    flow_init: Optional[np.ndarray] = None, forward_additive: bool = False) -> np.ndarray:
     """The whole pipeline on float intensity images (already scaled to [0, 1])."""
     n0 = bf_normalize(i0, nr, eps)
     n1 = bf_normalize(i1, nr, eps)
@@ -135,5 +140,5 @@ def bf_compute_flow(i0: np.ndarray, i1: np.ndarray, levels: int, kr: int, it: in
         if lev < levels - 1:
             u, v = bf_upsample(u, h, w), bf_upsample(v, h, w)
         for _ in range(it):
-            u, v = bf_gn_iteration(pyr0[lev], pyr1[lev], u, v, kr, reg_rel, reg_abs)
+            u, v = bf_gn_iteration(pyr0[lev], pyr1[lev], u, v, kr, reg_rel, reg_abs, forward_additive)
     return np.stack([u, v])

@@ -407,3 +407,68 @@ def test_float32_planes_stay_within_fp32_tolerance():
     ref = oracle.compute_flow(pair.frame0, pair.frame1, prm, bit_depth0=8)
     got = oracle.compute_flow(pair.frame0, pair.frame1, prm, bit_depth0=8, plane_round="f32")
     assert 0 < torch.max(torch.abs(got - ref)).item() < 1e-4
+
+
+# ---------------------------------------------------------------- forward-additive estimator (R24)
+
+@pytest.mark.parametrize("levels,kr,it", [(1, 1, 1), (1, 2, 3), (2, 1, 3), (2, 2, 2)])
+def test_forward_additive_matches_bruteforce_8x8(levels, kr, it):
+    rng = np.random.default_rng(300 + 10 * levels + kr + it)
+    i0 = rng.uniform(0, 1, (8, 8))
+    i1 = rng.uniform(0, 1, (8, 8))
+    v0 = rng.uniform(-1, 1, (2, 8, 8))
+    prm = {"num_levels": levels, "kernel_radius": kr, "iterations": it, "norm_radius": 1,
+           "estimator": "forward_additive"}
+    got = oracle.compute_flow(i0, i1, prm, bit_depth0=0, flow_init=v0).numpy()
+    ref = bf.bf_compute_flow(i0, i1, levels, kr, it, 1, 1e-4, 1e-3, 1e-9, flow_init=v0, forward_additive=True)
+    assert np.max(np.abs(got - ref)) < 1e-10
+    sym = oracle.compute_flow(i0, i1, dict(prm, estimator="symmetric"), bit_depth0=0, flow_init=v0).numpy()
+    assert np.max(np.abs(got - sym)) > 1e-3      # a different estimator
+
+
+def _check_fa_fixed_point():
+    tx, ty = 2, -1
+    f0, f1 = _shifted_pair(tx, ty)
+    n = f0.shape[0]
+    init = np.stack([np.full((n, n), float(tx)), np.full((n, n), float(ty))])
+    prm = {"num_levels": 1, "kernel_radius": 3, "iterations": 1, "norm_radius": 0, "estimator": "forward_additive"}
+    out = oracle.compute_flow(f0, f1, prm, bit_depth0=0, flow_init=init).numpy()
+    b = 3 + 2 + 2
+    return max(np.max(np.abs(out[0, b:-b, b:-b] - tx)), np.max(np.abs(out[1, b:-b, b:-b] - ty)))
+
+
+def test_forward_additive_integer_translation_is_an_exact_fixed_point():
+    # f1(k + t) = f0(k): the full-step warp of the second frame matches the first exactly
+    assert _check_fa_fixed_point() < 1e-12
+
+
+def test_textbook_forward_additive_lk_without_damping():
+    # reg = 0, V = 0: one step solves (sum G G^T) V = -sum G (I1 - I0), G the gradient of I1
+    p0, p1, _, _ = _tiny_levels(seed=6)
+    z = torch.zeros(8, 8, dtype=torch.float64)
+    un, vn = oracle.gn_iteration(T(p0), T(p1), z, z, 2, 0.0, 0.0, estimator="forward_additive")
+    gy, gx = np.gradient(p1, edge_order=1)
+    gx[:, 0] *= 0.5
+    gx[:, -1] *= 0.5
+    gy[0] *= 0.5
+    gy[-1] *= 0.5     # central differences with clamped indices halve the one-sided edge steps
+    t = p1 - p0
+    y, x = 4, 4
+    sl = (slice(2, 7), slice(2, 7))
+    A = np.array([[np.sum(gx[sl] ** 2), np.sum(gx[sl] * gy[sl])],
+                  [np.sum(gx[sl] * gy[sl]), np.sum(gy[sl] ** 2)]])
+    c = -np.array([np.sum(gx[sl] * t[sl]), np.sum(gy[sl] * t[sl])])
+    sol = np.linalg.solve(A, c)
+    assert abs(sol[0] - un[y, x].item()) < 1e-10 and abs(sol[1] - vn[y, x].item()) < 1e-10
+
+
+def test_planted_half_step_in_forward_additive_is_caught(monkeypatch):
+    from oracle import ofv_oracle as O
+
+    def mut(p0, p1, u, v):
+        h, w = p0.shape
+        yy, xx = torch.meshgrid(torch.arange(h, dtype=O.DT), torch.arange(w, dtype=O.DT), indexing="ij")
+        w1 = O.bilinear(p1, xx + 0.5 * u, yy + 0.5 * v)
+        return w1, w1 - p0
+    monkeypatch.setattr(O, "warp_terms_forward", mut)
+    assert _check_fa_fixed_point() > 1e-3
