@@ -85,8 +85,18 @@ typedef struct {
   float reg_rel;         /* >= 0, typical 1e-3: damping lambda = reg_rel * trace(A) + reg_abs */
   float reg_abs;         /* >= 0, typical 1e-9; reg_rel = reg_abs = 0 gives NaN on textureless windows */
   int32_t storage;       /* ofv_storage */
-  uint32_t flags;        /* reserved, must be 0 */
+  uint32_t flags;        /* 0 or OFV_FLAG_FORWARD_ADDITIVE */
 } ofv_params;
+
+/* params.flags: the forward-additive Lucas-Kanade estimator that the paper
+ * contrasts its symmetric objective with (section "Live-Optical Flow
+ * Velocimetry", after Eq. of_symmetric): minimise
+ * sum_k [I0(k) - I1(k + V)]^2 instead, linearised the same way about V(k)
+ * with the gradient of the warped second image; the field is then anchored
+ * at the pixels of frame 0.  Runs on 16 x 16 tiles (and the strip march for
+ * levels one pixel thin), ignores the decomposition choice, and has no
+ * adjoint (ofv_compute_flow_backward returns OFV_ERR_UNSUPPORTED). */
+#define OFV_FLAG_FORWARD_ADDITIVE 1u
 
 /* Fill *p with the defaults: 3 levels, KR 4, IT 3, NR 1, eps 1e-4,
  * reg_rel 1e-3, reg_abs 1e-9, F32 storage.  p == NULL is ignored. */

@@ -160,6 +160,11 @@ def params_struct(params: Dict) -> OfvParams:
             setattr(p, k, params[k])
     st = params.get("storage", "f32")
     p.storage = _lib.STORE[st] if isinstance(st, str) else int(st)
+    est = params.get("estimator", "symmetric")
+    if est not in ("symmetric", "forward_additive"):
+        raise ValueError(f"unknown estimator {est!r}")
+    if est == "forward_additive":
+        p.flags |= _lib.FLAG_FORWARD_ADDITIVE
     return p
 
 

@@ -3,8 +3,8 @@
 
 namespace ofv {
 
-hipError_t launch_gn_bf16_zero(const GnArgs& a, int kr, int nblocks, hipStream_t s) {
-  return launch_gn_typed<FLOW_ZERO, bf16_t>(a, kr, nblocks, s);
+hipError_t launch_gn_bf16_zero(const GnArgs& a, int kr, int nblocks, hipStream_t s, bool fa) {
+  return launch_gn_typed<FLOW_ZERO, bf16_t>(a, kr, nblocks, s, fa);
 }
 
 }  // namespace ofv

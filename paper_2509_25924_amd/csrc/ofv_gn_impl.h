@@ -138,20 +138,25 @@ __device__ __forceinline__ void tap4(const TS* p, int64_t pitch, int w, int h, f
   q11 = Px<TS>::ld(r0 + dy + dx);
 }
 
-template <typename TS>
+// Symmetric warps of Eq. (of_symmetric): P0 at k - V/2 and P1 at k + V/2,
+// S the mean of the two.  FA (the forward-additive estimator): P0 at k
+// itself (integer position: the interpolation weights are exactly 0) and
+// P1 at k + V, S the warped P1.
+template <bool FA, typename TS>
 __device__ __forceinline__ void warp_issue(const GnCtx<TS>& c, int x, int y, float u, float v, WarpReq& g) {
   const float fx = static_cast<float>(x);
   const float fy = static_cast<float>(y);
-  const float hu = 0.5f * u;
-  const float hv = 0.5f * v;
+  const float hu = FA ? 0.0f : 0.5f * u;
+  const float hv = FA ? 0.0f : 0.5f * v;
   tap4(c.p0, c.ip, c.w, c.h, fx - hu, fy - hv, g.a00, g.a01, g.a10, g.a11, g.ax0, g.ay0);
-  tap4(c.p1, c.ip, c.w, c.h, fx + hu, fy + hv, g.b00, g.b01, g.b10, g.b11, g.ax1, g.ay1);
+  tap4(c.p1, c.ip, c.w, c.h, fx + (FA ? u : hu), fy + (FA ? v : hv), g.b00, g.b01, g.b10, g.b11, g.ax1, g.ay1);
 }
 
+template <bool FA>
 __device__ __forceinline__ void warp_finish(const WarpReq& g, bool valid, float& s, float& t) {
   const float w0 = lerp4(g.a00, g.a01, g.a10, g.a11, g.ax0, g.ay0);
   const float w1 = lerp4(g.b00, g.b01, g.b10, g.b11, g.ax1, g.ay1);
-  s = valid ? 0.5f * (w0 + w1) : 0.0f;
+  s = valid ? (FA ? w1 : 0.5f * (w0 + w1)) : 0.0f;
   t = valid ? w1 - w0 : 0.0f;
 }
 
@@ -175,7 +180,7 @@ __device__ __forceinline__ float wave_prefix(float x) {
   return x;
 }
 
-template <int KR, int MODE, typename TS>
+template <int KR, int MODE, typename TS, bool FA = false>
 __global__ __launch_bounds__(kGnThreads) void gn_kernel(const GnArgs a) {
   constexpr int NWIN = 2 * KR + 1;
   constexpr int TX = kGnThreads - 2 * KR - 2;
@@ -237,13 +242,13 @@ __global__ __launch_bounds__(kGnThreads) void gn_kernel(const GnArgs a) {
     flow_finish<MODE>(fb, row_ok(r0 + 1), u_0, v_0);
     flow_finish<MODE>(fc, row_ok(r0 + 2), u_1, v_1);
     WarpReq ga, gb;
-    warp_issue(c, cc, rc(r0), ua, va, ga);
-    warp_issue(c, cc, rc(r0 + 1), u_0, v_0, gb);
-    warp_issue(c, cc, rc(r0 + 2), u_1, v_1, g1);
+    warp_issue<FA>(c, cc, rc(r0), ua, va, ga);
+    warp_issue<FA>(c, cc, rc(r0 + 1), u_0, v_0, gb);
+    warp_issue<FA>(c, cc, rc(r0 + 2), u_1, v_1, g1);
     flow_issue<MODE>(c, cc, rc(r0 + 4), f3);
     float tdummy;
-    warp_finish(ga, row_ok(r0), s_m, tdummy);
-    warp_finish(gb, row_ok(r0 + 1), s_0, t_0);
+    warp_finish<FA>(ga, row_ok(r0), s_m, tdummy);
+    warp_finish<FA>(gb, row_ok(r0 + 1), s_0, t_0);
   }
   s_row[0][tid] = s_0;
   __syncthreads();
@@ -271,9 +276,9 @@ __global__ __launch_bounds__(kGnThreads) void gn_kernel(const GnArgs a) {
         // pipeline: S/T of row pr+1 (gathers issued last step); gathers of
         // row pr+2 (flow requested two steps ago); flow of row pr+4.
         float s_p, t_p;
-        warp_finish(g1, row_ok(pr + 1), s_p, t_p);
+        warp_finish<FA>(g1, row_ok(pr + 1), s_p, t_p);
         flow_finish<MODE>(f2, row_ok(pr + 2), u_2, v_2);
-        warp_issue(c, cc, rc(pr + 2), u_2, v_2, g1);
+        warp_issue<FA>(c, cc, rc(pr + 2), u_2, v_2, g1);
         f2 = f3;
         flow_issue<MODE>(c, cc, rc(pr + 4), f3);
         // gradient of S at (col, pr), indices clamped to the level
@@ -336,12 +341,15 @@ __global__ __launch_bounds__(kGnThreads) void gn_kernel(const GnArgs a) {
 }
 
 template <int MODE, typename TS>
-hipError_t launch_gn_typed(const GnArgs& a, int kr, int nblocks, hipStream_t s) {
+hipError_t launch_gn_typed(const GnArgs& a, int kr, int nblocks, hipStream_t s, bool fa) {
   const dim3 grid(nblocks);
   const dim3 block(kGnThreads);
   switch (kr) {
-#define OFV_GN_CASE(R) \
-  case R: hipLaunchKernelGGL((gn_kernel<R, MODE, TS>), grid, block, 0, s, a); break;
+#define OFV_GN_CASE(R)                                                                   \
+  case R:                                                                                \
+    if (fa) hipLaunchKernelGGL((gn_kernel<R, MODE, TS, true>), grid, block, 0, s, a);     \
+    else hipLaunchKernelGGL((gn_kernel<R, MODE, TS, false>), grid, block, 0, s, a);       \
+    break;
     OFV_GN_CASE(1)
     OFV_GN_CASE(2)
     OFV_GN_CASE(3)

@@ -96,7 +96,9 @@ struct TileOcc {
   static constexpr int value = fit < 1 ? 1 : (fit > 4 ? 4 : fit);
 };
 
-template <int KR, int MODE, typename TS, int TX, int TY, int SL, int SLV, int NT>
+// FA: the forward-additive estimator instead of the symmetric objective
+// (P0 read at the pixel itself, P1 warped by the full V, S = the warped P1).
+template <int KR, int MODE, typename TS, int TX, int TY, int SL, int SLV, int NT, bool FA = false>
 __global__ __launch_bounds__(NT)
 __attribute__((amdgpu_waves_per_eu(TileOcc<KR, TX, TY, NT>::value, TileOcc<KR, TX, TY, NT>::value)))
 void gn_tile_kernel(const GnArgs a) {
@@ -220,10 +222,13 @@ void gn_tile_kernel(const GnArgs a) {
       float g0[CH][4], g1[CH][4], a0x[CH], a0y[CH], a1x[CH], a1y[CH];
 #pragma unroll
       for (int k = 0; k < CH; ++k) {
-        const float hu = 0.5f * uu[k];
-        const float hv = 0.5f * vv2[k];
+        // symmetric: P0 at k - V/2, P1 at k + V/2; forward-additive: P0 at k
+        // (through the same interpolation, so that equal planes give T = 0
+        // exactly), P1 at k + V
+        const float hu = FA ? 0.0f : 0.5f * uu[k];
+        const float hv = FA ? 0.0f : 0.5f * vv2[k];
         const BilTap t0 = bil_setup(fx[k] - hu, fy[k] - hv, wm1, hm1, wm2, hm2, uip);
-        const BilTap t1 = bil_setup(fx[k] + hu, fy[k] + hv, wm1, hm1, wm2, hm2, uip);
+        const BilTap t1 = bil_setup(fx[k] + (FA ? uu[k] : hu), fy[k] + (FA ? vv2[k] : hv), wm1, hm1, wm2, hm2, uip);
         a0x[k] = t0.ax;
         a0y[k] = t0.ay;
         a1x[k] = t1.ax;
@@ -243,7 +248,7 @@ void gn_tile_kernel(const GnArgs a) {
           kT[k0 + k] = w1 - w0;
           kU[k0 + k] = uu[k];
           kV[k0 + k] = vv2[k];
-          if (tid + NT * (k0 + k) < NE) sS[oo[k]] = 0.5f * (w0 + w1);
+          if (tid + NT * (k0 + k) < NE) sS[oo[k]] = FA ? w1 : 0.5f * (w0 + w1);
         }
       }
     }
@@ -386,10 +391,10 @@ void gn_tile_kernel(const GnArgs a) {
   }
 }
 
-template <int KR, int MODE, typename TS, int TX, int TY, int SL, int SLV, int NT>
+template <int KR, int MODE, typename TS, int TX, int TY, int SL, int SLV, int NT, bool FA = false>
 hipError_t launch_gn_tile_cfg(const GnArgs& a, int nblocks, hipStream_t s) {
   constexpr size_t lds = sizeof(float) * TileGeom<KR, TX, TY>::LDS_FLOATS;
-  auto kern = gn_tile_kernel<KR, MODE, TS, TX, TY, SL, SLV, NT>;
+  auto kern = gn_tile_kernel<KR, MODE, TS, TX, TY, SL, SLV, NT, FA>;
   // dynamic LDS above 64 KiB must be enabled once per kernel (thread-safe static init)
   static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                                      hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -411,10 +416,12 @@ hipError_t launch_gn_tile_cfg(const GnArgs& a, int nblocks, hipStream_t s) {
 // lanes, so that the warps of a tile are spread over more waves per SIMD.
 // The small tiles spread coarse levels over many compute units: there the
 // launch is bound by the instruction latency of few waves, not by traffic.
+// fa (forward-additive estimator): 16 x 16 tiles whatever the variant.
 template <int MODE, typename TS>
-hipError_t launch_gn_tile_typed(const GnArgs& a, int kr, int variant, int nblocks, hipStream_t s) {
+hipError_t launch_gn_tile_typed(const GnArgs& a, int kr, int variant, int nblocks, hipStream_t s, bool fa) {
 #define OFV_GNT_CASE(R)                                                                             \
   case R:                                                                                           \
+    if (fa) return launch_gn_tile_cfg<R, MODE, TS, 16, 16, 4, 1, 256, true>(a, nblocks, s);          \
     switch (variant) {                                                                              \
       case GN_TILE_64x32: return launch_gn_tile_cfg<R, MODE, TS, 64, 32, 8, 4, 512>(a, nblocks, s);  \
       case GN_TILE_64x16: return launch_gn_tile_cfg<R, MODE, TS, 64, 16, 8, 4, 256>(a, nblocks, s);  \

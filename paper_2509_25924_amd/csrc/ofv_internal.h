@@ -168,7 +168,9 @@ hipError_t launch_reduce_multi(const ReduceMArgs& a, int nlev, int nblocks, hipS
 hipError_t launch_upsample(const UpsampleArgs& a, hipStream_t s);
 hipError_t launch_derived(const DerivedArgs& a, int nblocks, hipStream_t s);
 // All jobs of one launch share the input-flow mode (a compile-time parameter of the kernel).
-hipError_t launch_gn(const GnArgs& a, int kr, int storage, int mode, int variant, int nblocks, hipStream_t s);
+// fa: the forward-additive estimator (16 x 16 tiles or the march) instead of the symmetric one.
+hipError_t launch_gn(const GnArgs& a, int kr, int storage, int mode, int variant, int nblocks, hipStream_t s,
+                     bool fa = false);
 
 // ---------------------------------------------------------------- adjoint (float32 storage)
 struct ImageIn {

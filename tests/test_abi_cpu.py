@@ -146,7 +146,7 @@ def test_valid_call_reaches_the_device_step(lib, vhandle):
     (lambda i0, i1, p: setattr(p, "reg_rel", -1.0), _lib.OFV_ERR_INVALID_ARG, b"reg_rel"),
     (lambda i0, i1, p: setattr(p, "reg_abs", float("inf")), _lib.OFV_ERR_INVALID_ARG, b"reg_abs"),
     (lambda i0, i1, p: setattr(p, "storage", 3), _lib.OFV_ERR_INVALID_ARG, b"storage"),
-    (lambda i0, i1, p: setattr(p, "flags", 1), _lib.OFV_ERR_INVALID_ARG, b"flags"),
+    (lambda i0, i1, p: setattr(p, "flags", 4), _lib.OFV_ERR_INVALID_ARG, b"flags"),
     (lambda i0, i1, p: (setattr(i0, "width", 257), setattr(i1, "width", 257), setattr(i0, "pitch", 257),
                         setattr(i1, "pitch", 257)), _lib.OFV_ERR_CAPACITY, b"exceeds"),
     (lambda i0, i1, p: (setattr(i0, "height", 129), setattr(i1, "height", 129)), _lib.OFV_ERR_CAPACITY, b"exceeds"),
@@ -289,3 +289,16 @@ def test_stream_validation(lib, vhandle):
         _lib.OFV_ERR_UNSUPPORTED
     assert lib.ofv_stream_reset(vhandle) == _lib.OFV_OK
     assert lib.ofv_stream_reset(None) == _lib.OFV_ERR_INVALID_ARG
+
+
+def test_estimator_flags(lib, vhandle):
+    img0, img1 = _img(), _img(0x200000)
+    p = _params(flags=_lib.FLAG_FORWARD_ADDITIVE)
+    assert lib.ofv_compute_flow(vhandle, byref(img0), byref(img1), byref(p), c_void_p(OUT)) == \
+        _lib.OFV_ERR_UNSUPPORTED                                        # valid, validation-only handle
+    bad = _params(flags=2)
+    assert lib.ofv_compute_flow(vhandle, byref(img0), byref(img1), byref(bad), c_void_p(OUT)) == \
+        _lib.OFV_ERR_INVALID_ARG
+    assert lib.ofv_compute_flow_backward(vhandle, byref(img0), byref(img1), byref(p), None, c_void_p(OUT),
+                                         c_void_p(OUT + (1 << 20)), None, None) == _lib.OFV_ERR_UNSUPPORTED
+    assert b"symmetric" in lib.ofv_last_error(vhandle)
