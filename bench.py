@@ -824,6 +824,18 @@ def main():
         del kgraph
     else:
         kern_s = eager_s
+    # practical HBM ceiling for context: a 256 MiB device-to-device copy (512 MiB moved), event-timed
+    csrc = torch.empty(64 << 20, dtype=torch.float32, device=dev)
+    cdst = torch.empty_like(csrc)
+    for _ in range(3):
+        cdst.copy_(csrc)
+    ev0.record()
+    for _ in range(10):
+        cdst.copy_(csrc)
+    ev1.record()
+    torch.cuda.synchronize()
+    copy_gbps = 10 * 2 * csrc.numel() * 4 / (ev0.elapsed_time(ev1) / 1e3) / 1e9
+    del csrc, cdst
     decomp = args.variant
     if args.variant == "tuned":
         decomp = "auto"
@@ -881,7 +893,8 @@ def main():
                      "launches_timed": args.kernel_launches,
                      "timed_as": "hipGraph replay of back-to-back launches" if graph is not None else "eager loop",
                      "us_eager_loop_per_launch": round(eager_s * 1e6, 3),
-                     "us_event_pair_per_launch": round(pair_s * 1e6, 3)},
+                     "us_event_pair_per_launch": round(pair_s * 1e6, 3),
+                     "stream_copy_GBps": round(copy_gbps, 1)},
     }
 
     if not args.no_cpu_baseline:

@@ -2,8 +2,8 @@
 // experiment of arXiv 2509.25924, section on live measurements): vorticity,
 // velocity probes and the recirculation area of Eq. (RA).
 // derived_kernel streams the field once (the neighbour taps of the central
-// differences hit the caches) with a bounded grid that strides over 64 x 16
-// tiles (one column of 4 consecutive rows per lane), writes the vorticity plane, interpolates the probes, and counts
+// differences hit the caches) with a bounded grid that strides over 64-column
+// tiles (one column of kDerivedRows consecutive rows per lane), writes the vorticity plane, interpolates the probes, and counts
 // the recirculating pixels with one ballot per wavefront and row; each
 // workgroup stores its count in its own slot (no atomics, so the count is
 // exact and the launch can be replayed in a graph).  derived_area_kernel,
@@ -31,7 +31,7 @@ __global__ __launch_bounds__(256) void derived_kernel(const DerivedArgs a) {
     // lane: one column, 4 consecutive rows of the tile; the u rows above and
     // below are carried from row to row
     const int x = (t % ntx) * kDerivedTW + (tid & 63);
-    const int y0 = (t / ntx) * kDerivedTH + 4 * (tid >> 6);
+    const int y0 = (t / ntx) * kDerivedTH + kDerivedRows * (tid >> 6);
     const bool xin = x < a.w;
     // neighbours of the x-derivative, clamped into the row: central inside,
     // one-sided at the edges, the same column (difference 0) for one column
@@ -41,7 +41,7 @@ __global__ __launch_bounds__(256) void derived_kernel(const DerivedArgs a) {
     float u_prev = xin && y0 >= 1 && y0 - 1 < a.h ? uc[static_cast<int64_t>(y0 - 1) * a.pitch] : 0.0f;
     float u_cur = xin && y0 < a.h ? uc[static_cast<int64_t>(y0) * a.pitch] : 0.0f;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < kDerivedRows; ++k) {
       const int y = y0 + k;
       const bool in = xin && y < a.h;
       const float u_next = in && y + 1 < a.h ? uc[static_cast<int64_t>(y + 1) * a.pitch] : 0.0f;

@@ -96,7 +96,8 @@ struct DerivedArgs {
   double* area;
   double dx, dz;
 };
-constexpr int kDerivedTW = 64, kDerivedTH = 16;   // a lane: one column, 4 consecutive rows
+constexpr int kDerivedTW = 64, kDerivedRows = 8;  // a lane: one column, kDerivedRows consecutive rows
+constexpr int kDerivedTH = 4 * kDerivedRows;       // 4 wavefronts per 256-lane workgroup stacked vertically
 constexpr int kDerivedMaxBlocks = 2048;   // grid bound of the derived-quantities kernel (slots of partial counts)
 
 // ---------------------------------------------------------------- up-sampling (stage entry point)
