@@ -117,3 +117,36 @@ def test_full_size_21mp_field(ofv):
     mask = (torch.rand((4096, 5120), generator=g) > 0.1).to(torch.uint8).numpy()
     pts = np.array([[0, 0], [5119, 4095], [2560.5, 2048.25], [1024, 2048]], np.float32)
     _check(ofv, flow, mask, 0.1, 0.1, 0.01, 1, pts)
+
+
+def test_padded_pitches_through_the_c_abi(ofv):
+    """Flow, mask and vorticity planes with row pitches above the width, called through the C ABI."""
+    from ctypes import byref, c_void_p
+    from paper_2509_25924_amd import _lib
+    say("derived with padded pitches")
+    h, w = 150, 203
+    fp, mp, vp = w + 13, w + 5, w + 7
+    rng = np.random.default_rng(44)
+    flow = rng.normal(0, 1.5, (2, h, w)).astype(np.float32)
+    mask = (rng.random((h, w)) > 0.3).astype(np.uint8)
+    dflow = torch.full((2, h, fp), float("nan"), device="cuda")
+    dflow[:, :, :w] = torch.from_numpy(flow).cuda()
+    dmask = torch.zeros((h, mp), dtype=torch.uint8, device="cuda")
+    dmask[:, :w] = torch.from_numpy(mask).cuda()
+    dvort = torch.full((h, vp), 7.0, device="cuda")
+    area = torch.zeros(1, dtype=torch.float64, device="cuda")
+    lib = ofv.load()
+    hd = ofv.Handle(16, 16, 1)
+    p = _lib.OfvDerivedParams(0.5, 2.0, 0.25, -1)
+    st = lib.ofv_derived(hd.ptr, c_void_p(dflow.data_ptr()), w, h, fp, c_void_p(dmask.data_ptr()), mp, byref(p),
+                         c_void_p(dvort.data_ptr()), vp, None, 0, None, c_void_p(area.data_ptr()))
+    assert st == 0, lib.ofv_last_error(hd.ptr)
+    torch.cuda.synchronize()
+    u, v = torch.as_tensor(flow[0]).double(), torch.as_tensor(flow[1]).double()
+    om = oracle.vorticity(u, v, 0.5, 2.0, 0.25, mask=mask)
+    got = dvort[:, :w].cpu().double()
+    assert torch.max(torch.abs(got - om)).item() <= 4e-7 * (2.0 / 0.5 + 0.5 / 2.0) / 0.25 * float(np.abs(flow).max())
+    assert torch.all(dvort[:, w:] == 7.0)                 # nothing written past the width
+    ref, _ = oracle.recirculation_area(u, 0.5, 2.0, mask=mask, sign=-1)
+    assert area.item() == ref
+    hd.close()
