@@ -93,19 +93,32 @@ __device__ __forceinline__ void stage_frame_tile_c(const NormJob& J, float* tile
   const PlaneView fv = plane_view(J.in, pitch * static_cast<uint32_t>(J.h) * static_cast<uint32_t>(sizeof(TI)));
   const float inv_max = 1.0f / static_cast<float>((1 << J.bits) - 1);
   float v[NLD];
+  if (x0 >= 0 && y0 >= 0 && x0 + TW <= J.w && y0 + TH <= J.h) {
+    // the whole tile lies inside the frame (block-uniform): no clamps or masks
+    const uint32_t base = __umul24(static_cast<uint32_t>(y0), pitch) + static_cast<uint32_t>(x0);
 #pragma unroll
-  for (int k = 0; k < NLD; ++k) {
-    const int i = min(static_cast<int>(threadIdx.x) + 256 * k, N - 1);
-    const int ty = i / TW;
-    const int gx = x0 + (i - ty * TW);
-    const int gy = y0 + ty;
-    const bool in = static_cast<unsigned>(gx) < static_cast<unsigned>(J.w) &&
-                    static_cast<unsigned>(gy) < static_cast<unsigned>(J.h);
-    const uint32_t o = __umul24(static_cast<uint32_t>(min(max(gy, 0), J.h - 1)), pitch) +
-                       static_cast<uint32_t>(min(max(gx, 0), J.w - 1));
-    float x = frame_ldv<TI>(fv, o);
-    if (!std::is_same<TI, float>::value) x *= inv_max;
-    v[k] = in ? x : 0.0f;
+    for (int k = 0; k < NLD; ++k) {
+      const int i = min(static_cast<int>(threadIdx.x) + 256 * k, N - 1);
+      const int ty = i / TW;
+      float x = frame_ldv<TI>(fv, base + __umul24(static_cast<uint32_t>(ty), pitch) + static_cast<uint32_t>(i - ty * TW));
+      if (!std::is_same<TI, float>::value) x *= inv_max;
+      v[k] = x;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) {
+      const int i = min(static_cast<int>(threadIdx.x) + 256 * k, N - 1);
+      const int ty = i / TW;
+      const int gx = x0 + (i - ty * TW);
+      const int gy = y0 + ty;
+      const bool in = static_cast<unsigned>(gx) < static_cast<unsigned>(J.w) &&
+                      static_cast<unsigned>(gy) < static_cast<unsigned>(J.h);
+      const uint32_t o = __umul24(static_cast<uint32_t>(min(max(gy, 0), J.h - 1)), pitch) +
+                         static_cast<uint32_t>(min(max(gx, 0), J.w - 1));
+      float x = frame_ldv<TI>(fv, o);
+      if (!std::is_same<TI, float>::value) x *= inv_max;
+      v[k] = in ? x : 0.0f;
+    }
   }
 #pragma unroll
   for (int k = 0; k < NLD; ++k)
