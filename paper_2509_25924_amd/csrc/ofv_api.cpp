@@ -324,7 +324,7 @@ ofv_status run_pipeline(ofv_ctx* h, int n, PairPlan* pp, const ofv_params* p, fl
       J.h = f->height;
       J.out = img_plane(h, q, fj[i].second, 0, ts);
       J.out_pitch = h->lpitch[0];
-      return ((J.w + 63) / 64) * ((J.h + 15) / 16);
+      return ((J.w + kNormTW - 1) / kNormTW) * ((J.h + kNormTH - 1) / kNormTH);
     };
     ofv_status r = run_chunked(h, nf, na, fill,
                                [&](const NormArgs& a, int b) { return launch_normalize(a, b, s); }, "normalize");
@@ -1301,7 +1301,7 @@ ofv_status ofv_stage_normalize(ofv_handle h, const ofv_image* frame, int norm_ra
   J.out = out;
   J.out_pitch = out_pitch;
   J.tile_start = 0;
-  hipError_t e = launch_normalize(na, ((J.w + 63) / 64) * ((J.h + 15) / 16), h->stream);
+  hipError_t e = launch_normalize(na, ((J.w + kNormTW - 1) / kNormTW) * ((J.h + kNormTH - 1) / kNormTH), h->stream);
   return e == hipSuccess ? OFV_OK : device_error(h, e, "normalize");
 }
 

@@ -27,6 +27,8 @@ struct NormJob {
   int tile_start;      // first block of this job
   int pad_;
 };
+// normalisation tile: kNormTW x kNormTH outputs per 256-lane workgroup, kNormPX per lane
+constexpr int kNormTW = 64, kNormPX = 4, kNormTH = 4 * kNormPX;
 struct NormArgs {
   int njobs;
   int nr;

@@ -11,13 +11,13 @@
 namespace ofv {
 
 // ---------------------------------------------------------------------------
-// Step 1: decode + local z-score.  Tile of 64 x 16 outputs per 256 lanes;
+// Step 1: decode + local z-score.  Tile of kNormTW x kNormTH outputs per 256 lanes;
 // integer frames are scaled by the float32 reciprocal of 2^B - 1 and the
 // z-score uses the hardware reciprocal square root (both within a few
 // float32 rounding errors of the exact quotients);
-// the (64 + 2 NR) x (16 + 2 NR) input tile is staged in LDS once (frame
-// pixels outside the frame stored as 0) and each lane evaluates 4
-// vertically adjacent outputs of one column.  Every normalisation kernel
+// the (kNormTW + 2 NR) x (kNormTH + 2 NR) input tile is staged in LDS once
+// (frame pixels outside the frame stored as 0) and each lane evaluates
+// kNormPX vertically adjacent outputs of one column.  Every normalisation kernel
 // evaluates one pixel by the same sequence of float32 operations over the
 // window truncated to the frame (n pixels), so that all of them agree bit
 // for bit:
@@ -26,12 +26,10 @@ namespace ofv {
 //   N = (I - mu) rsq(q rn + eps)        (second-pass variance)
 // Taps outside the frame are stored as 0 (exact in the sums) and masked by
 // a 0/1 weight in the q chain (fma(0, d, q) = q).
-// For NR <= 3 the lane's (4 + 2 NR) x (2 NR + 1) patch is read into
-// registers once and row sums are shared between the 4 outputs.  Larger
+// For NR <= 3 the lane's (kNormPX + 2 NR) x (2 NR + 1) patch is read into
+// registers once and row sums are shared between its outputs.  Larger
 // radii take the generic path that walks the window in LDS.
 // ---------------------------------------------------------------------------
-constexpr int kNormTW = 64;
-constexpr int kNormTH = 16;
 
 template <typename TI>
 __device__ __forceinline__ float frame_value(const void* base, int64_t o, float inv_max) {
@@ -150,7 +148,7 @@ __global__ __launch_bounds__(256) void normalize_kernel(const NormArgs a) {
   }
   __syncthreads();
   const int lx = threadIdx.x & 63;
-  const int ly0 = 4 * (threadIdx.x >> 6);
+  const int ly0 = kNormPX * (threadIdx.x >> 6);
   const int gx = x0 + lx;
   const int gy0 = y0 + ly0;
   if (gx >= J.w || gy0 >= J.h) return;
@@ -158,7 +156,7 @@ __global__ __launch_bounds__(256) void normalize_kernel(const NormArgs a) {
   if (NRC > 0) {
     constexpr int R = NRC;
     constexpr int NC = 2 * R + 1;
-    constexpr int NRW = 4 + 2 * R;
+    constexpr int NRW = kNormPX + 2 * R;
     float pv[NRW][NC];
     float vy[NRW], vx[NC];
 #pragma unroll
@@ -185,7 +183,7 @@ __global__ __launch_bounds__(256) void normalize_kernel(const NormArgs a) {
     if (x0 >= R && y0 >= R && x0 + kNormTW + R <= J.w && y0 + kNormTH + R <= J.h) {
       constexpr float rn = 1.0f / static_cast<float>(NC * NC);
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
+      for (int k = 0; k < kNormPX; ++k) {
         float sm = 0.0f;
 #pragma unroll
         for (int r = 0; r < NC; ++r) sm += hs[k + r];
@@ -204,7 +202,7 @@ __global__ __launch_bounds__(256) void normalize_kernel(const NormArgs a) {
       return;
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < kNormPX; ++k) {
       if (gy0 + k < J.h) {
         float sm = 0.0f, nrow = 0.0f;
 #pragma unroll
@@ -230,7 +228,7 @@ __global__ __launch_bounds__(256) void normalize_kernel(const NormArgs a) {
   }
   const int xa = max(-nr, -gx);
   const int xb = min(nr, J.w - 1 - gx);
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < kNormPX; ++k) {
     const int ly = ly0 + k;
     const int gy = gy0 + k;
     if (gy >= J.h) break;
