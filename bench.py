@@ -94,7 +94,8 @@ def parse():
     ap.add_argument("--sweep-realisations", type=int, default=10,
                     help="particle fields per image of the accuracy sweep (the paper uses 10)")
     ap.add_argument("--suite", default=None,
-                    choices=["batch4mp", "live21mp", "stream21mp", "sweep", "adjoint512", "paper", "all"],
+                    choices=["batch4mp", "live21mp", "stream21mp", "sweep", "adjoint512", "paper", "oracle",
+                             "all"],
                     help="run an additional measurement instead of the default workload (one JSON line each)")
     return ap.parse_args()
 
@@ -583,6 +584,52 @@ def suite_sweep(args, dev):
                     "noise, no out-of-plane loss) standing in for the paper's generator images"}
 
 
+def suite_oracle(args, dev):
+    """The FP64 CPU oracle's own throughput on the host of the GPU: the 256^2 Rankine and 1024^2 shear
+    configurations with every thread and with one, one 2048^2 turbulence pair and a 2048^2 crop of a
+    5120x4096 cylinder-wake pair (live parameters) with every thread (a reported baseline, not a target)."""
+    import numpy as np
+    import torch
+    import oracle
+    import synth
+    from synth.gpu_render import make_pair_device
+    nthreads = torch.get_num_threads()
+    rows = []
+
+    def timed(name, f0, f1, prm, bits, threads, budget=20.0, max_runs=5):
+        torch.set_num_threads(threads)
+        runs, t = 0, 0.0
+        while runs < 1 or (t < budget and runs < max_runs):
+            t0 = time.perf_counter()
+            oracle.compute_flow(f0, f1, prm, bit_depth0=bits)
+            t += time.perf_counter() - t0
+            runs += 1
+        h, w = f0.shape
+        rows.append({"config": name, "size": f"{w}x{h}", "threads": threads, "runs": runs,
+                     "seconds_per_field": round(t / runs, 3), "mvectors_per_s": round(w * h * runs / t / 1e6, 4)})
+        print(f"#   oracle {name} threads={threads}: {t / runs:.2f} s per field", file=sys.stderr, flush=True)
+
+    pair, prm = synth.config_rankine_256()
+    for th in (nthreads, 1):
+        timed("rankine_256", pair.frame0, pair.frame1, prm, 8, th)
+    pair, prm = synth.config_shear_1mp()
+    for th in (nthreads, 1):
+        timed("shear_1mp", pair.frame0, pair.frame1, prm, 12, th, budget=30.0, max_runs=3)
+    pair, prm = synth.config_turbulence_4mp(0)
+    timed("turbulence_4mp", pair.frame0, pair.frame1, dict(prm, storage="f32"), 12, nthreads, max_runs=1)
+    W, H = 5120, 4096
+    a, b, _ = make_pair_device(H, W, synth.CylinderWake(H, W, t=0.0, dmax=10.0), fwhm=2.5, ppp=0.1, seed=4000,
+                               bit_depth=12, noise=0.01 * 4095, device=dev, max_disp=10.0)
+    # a 2048^2 crop of the 5120x4096 frame with the live parameters (the whole frame takes minutes)
+    crop = (slice(1024, 3072), slice(1536, 3584))
+    timed("cylinder_21mp_crop2048", a[crop].cpu().numpy().astype(np.uint16), b[crop].cpu().numpy().astype(np.uint16),
+          {"num_levels": 4, "kernel_radius": 10, "iterations": 3, "norm_radius": 2}, 12, nthreads, max_runs=1)
+    torch.set_num_threads(nthreads)
+    return {"metric": "FP64 CPU oracle throughput on the GPU host", "value": rows[2]["mvectors_per_s"],
+            "unit": "Mvectors/s (1024^2 shear, every thread)", "rows": rows, "host": host_cpu(),
+            "note": "plain float64 torch CPU operations, not tuned; a baseline, not a target"}
+
+
 def suite_adjoint512(args, dev):
     """Backward/forward cost: 16 float 512x512 pairs, loss sum |V - V_gt|^2."""
     import torch
@@ -661,7 +708,7 @@ def run_suite(args):
     names = (["batch4mp", "live21mp", "stream21mp", "sweep", "adjoint512", "paper"] if args.suite == "all"
              else [args.suite])
     fns = {"batch4mp": suite_batch4mp, "live21mp": suite_live21mp, "stream21mp": suite_stream21mp,
-           "sweep": suite_sweep,
+           "sweep": suite_sweep, "oracle": suite_oracle,
            "adjoint512": suite_adjoint512, "paper": suite_paper}
     for nm in names:
         print(f"# suite {nm} ...", file=sys.stderr, flush=True)
