@@ -753,7 +753,7 @@ def main():
             with open(args.tuning_table) as fh:
                 handle.load_tuning_table(fh.read())
         elif not args.pmc_probe:
-            handle.autotune(f0, f1, prm, bit_depth=bits, repeats=3)
+            handle.autotune(f0, f1, prm, bit_depth=bits, repeats=7)
         if args.save_tuning:
             with open(args.save_tuning, "w") as fh:
                 fh.write(handle.tuning_table())

@@ -191,12 +191,13 @@ ofv_status ofv_compute_flow_backward(ofv_handle h, const ofv_image* frame0, cons
  * 4..1024. */
 ofv_status ofv_set_gn_variant(ofv_handle h, int variant, int tile_h);
 
-/* Autotuner: runs the estimator on this pair once per candidate
+/* Autotuner: runs the estimator on this pair with every candidate
  * decomposition (16x16, 32x16, 64x16, 64x32 and 64x64 tiles with 256 to 1024
- * lanes, strips of 16/32/64 rows), `repeats` timed runs each, times every
- * Gauss-Newton launch with HIP events, and records the fastest candidate per
- * (window radius, storage, flow mode, level size, batch size) in the handle;
- * later calls with matching geometry use it.
+ * lanes, strips of 16/32/64 rows): one untimed run each, then `repeats`
+ * rounds in which the candidates take turns, every Gauss-Newton launch timed
+ * with HIP events; per (window radius, storage, flow mode, level size, batch
+ * size) it records the candidate with the lowest median launch time in the
+ * handle, and later calls with matching geometry use it.
  * flow_out receives the flow (as ofv_compute_flow).  Unlike the compute
  * calls this synchronises the stream and may create HIP events; call it at
  * set-up, not inside graph capture.  1 <= repeats <= 1000. */

@@ -1190,33 +1190,46 @@ ofv_status ofv_autotune(ofv_handle h, const ofv_image* frame0, const ofv_image* 
   const Cand cands[] = {{GN_TILE_16x16, 16},  {GN_TILE_16x16W, 16}, {GN_TILE_32x16, 16}, {GN_TILE_32x16W, 16},
                         {GN_TILE_64x16, 16},  {GN_TILE_64x32, 32},  {GN_TILE_64x16W, 16}, {GN_TILE_64x32W, 32},
                         {GN_TILE_64x64, 64},  {GN_MARCH, 16},       {GN_MARCH, 32},       {GN_MARCH, 64}};
-  std::map<ofv_ctx::TuneKey, std::pair<float, ofv_ctx::Choice>> best;
+  constexpr int nc = static_cast<int>(sizeof(cands) / sizeof(cands[0]));
+  // launch times per (level key, candidate); the candidates take turns within every
+  // repeat, so that slow drifts of the clock affect them alike
+  std::map<ofv_ctx::TuneKey, std::vector<std::vector<float>>> samples;
   const int saved_v = h->forced_variant, saved_t = h->forced_tile_h;
-  for (const Cand& c : cands) {
-    h->forced_variant = c.variant;
-    h->forced_tile_h = c.tile_h;
-    r = compute_common(h, 1, frame0, frame1, params, nullptr, &flow_out);  // warm-up
-    if (r != OFV_OK) break;
-    h->capture = true;
-    h->events_used = 0;
-    h->recs.clear();
-    for (int k = 0; k < repeats && r == OFV_OK; ++k) r = compute_common(h, 1, frame0, frame1, params, nullptr, &flow_out);
-    h->capture = false;
-    if (r != OFV_OK) break;
-    if (hipStreamSynchronize(h->stream) != hipSuccess) {
-      r = fail(h, OFV_ERR_DEVICE, "synchronisation failed while tuning");
-      break;
+  for (int k = -1; k < repeats && r == OFV_OK; ++k) {  // k = -1: warm-up of every candidate
+    for (int ci = 0; ci < nc && r == OFV_OK; ++ci) {
+      h->forced_variant = cands[ci].variant;
+      h->forced_tile_h = cands[ci].tile_h;
+      h->capture = k >= 0;
+      h->events_used = 0;
+      h->recs.clear();
+      r = compute_common(h, 1, frame0, frame1, params, nullptr, &flow_out);
+      h->capture = false;
+      if (r != OFV_OK) break;
+      if (k < 0) continue;
+      if (hipStreamSynchronize(h->stream) != hipSuccess) {
+        r = fail(h, OFV_ERR_DEVICE, "synchronisation failed while tuning");
+        break;
+      }
+      for (const auto& rec : h->recs) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, rec.a, rec.b) != hipSuccess) ms = 1e30f;
+        auto& v = samples[rec.key];
+        if (v.empty()) v.resize(nc);
+        v[ci].push_back(ms);
+      }
     }
-    std::map<ofv_ctx::TuneKey, float> tot;
-    for (const auto& rec : h->recs) {
-      float ms = 0.0f;
-      if (hipEventElapsedTime(&ms, rec.a, rec.b) != hipSuccess) ms = 1e30f;
-      tot[rec.key] += ms;
-    }
-    for (const auto& kv : tot) {
+  }
+  // per level key: the candidate with the lowest median launch time
+  std::map<ofv_ctx::TuneKey, std::pair<float, ofv_ctx::Choice>> best;
+  for (auto& kv : samples) {
+    for (int ci = 0; ci < nc; ++ci) {
+      std::vector<float>& v = kv.second[ci];
+      if (v.empty()) continue;
+      std::sort(v.begin(), v.end());
+      const float med = v[v.size() / 2];
       auto it = best.find(kv.first);
-      if (it == best.end() || kv.second < it->second.first)
-        best[kv.first] = {kv.second, ofv_ctx::Choice{c.variant, c.tile_h}};
+      if (it == best.end() || med < it->second.first)
+        best[kv.first] = {med, ofv_ctx::Choice{cands[ci].variant, cands[ci].tile_h}};
     }
   }
   h->forced_variant = saved_v;
