@@ -19,10 +19,11 @@
 //      GxGy, Gy^2, Gx b, Gy b (0 outside the level) -> five LDS planes;
 //  B.  per (product row, segment of SL output columns): horizontal window
 //      sums by running sums over the product planes, kept in registers ...
-//  B'. ... and written back over the product planes once every lane has
-//      read its inputs;
+//  B'. ... and written back, transposed (column-major, one plane per
+//      product), over the product planes once every lane has read its inputs;
 //  C.  per (output column, segment of SLV output rows): running vertical
-//      window sums, damped 2x2 solve, coalesced store of u' and v'.
+//      window sums along the contiguous columns of B', damped 2x2 solve,
+//      coalesced store of u' and v'.
 // Every product is formed once; only the window sums repeat work at the
 // segment ends.
 #pragma once
@@ -40,6 +41,11 @@ struct TileGeom {
   static constexpr int PY = TY + 2 * KR;      // product rows
   static constexpr int NE = EX * EY;
   static constexpr int PLANE = LP * EY;       // one ext-sized LDS plane
+  // B' output: per product, TX columns of PY horizontal sums, odd column
+  // pitch (column-strided lanes of C hit distinct banks)
+  static constexpr int CP = PY | 1;
+  static constexpr int HPL = TX * CP;
+  static_assert(HPL <= PLANE, "transposed sums fit in the product planes");
   // the S plane and five product planes, all indexed by ext coordinates
   static constexpr int LDS_FLOATS = 6 * PLANE;
 };
@@ -74,6 +80,16 @@ __device__ __forceinline__ float bil_combine(float p00, float p01, float p10, fl
   return fmaf(ay, bot - top, top);
 }
 
+// An LDS element offset that the compiler treats as unknown.  Accesses at
+// constant distances from it then keep small immediate offsets from one
+// register, instead of being folded into offsets from a shared base that
+// overflow the 16-bit (8-bit for paired accesses) offset fields and cost an
+// address add each.  Emits no instruction.
+__device__ __forceinline__ int lds_reg(int i) {
+  asm volatile("" : "+v"(i));
+  return i;
+}
+
 // Workgroups are handed to the 8 XCDs of the chip in turn (workgroup i to
 // XCD i mod 8), and each XCD has its own L2.  Tile l of a job of n tiles is
 // renumbered so that the workgroups of one XCD take a contiguous run of
@@ -104,6 +120,7 @@ __attribute__((amdgpu_waves_per_eu(TileOcc<KR, TX, TY, NT>::value, TileOcc<KR, T
 void gn_tile_kernel(const GnArgs a) {
   using G = TileGeom<KR, TX, TY>;
   constexpr int NWIN = G::NWIN, EX = G::EX, EY = G::EY, LP = G::LP, PY = G::PY, PL = G::PLANE, NE = G::NE;
+  constexpr int CP = G::CP, HPL = G::HPL;
   constexpr int NSEG = TX / SL;
   static_assert(TX % SL == 0 && TY % SLV == 0, "segments must tile the output");
   static_assert(TX * (TY / SLV) <= NT, "phase C items");
@@ -267,11 +284,13 @@ void gn_tile_kernel(const GnArgs a) {
 #pragma unroll
       for (int k = 0; k < C2; ++k) {
         if (k0 + k < NA) {
+          // the four neighbours at non-negative offsets from the one above
           const int o = (kF & (1u << (2 * (k0 + k)))) ? kO[k0 + k] : LP + 1;
-          sxp[k] = sS[o + 1];
-          sxm[k] = sS[o - 1];
-          syp[k] = sS[o + LP];
-          sym[k] = sS[o - LP];
+          const float* n = sS + (o - LP);
+          sym[k] = n[0];
+          sxm[k] = n[LP - 1];
+          sxp[k] = n[LP + 1];
+          syp[k] = n[2 * LP];
         }
       }
 #pragma unroll
@@ -302,33 +321,37 @@ void gn_tile_kernel(const GnArgs a) {
     const int item = tid + NT * it;
     if (item < NSEG * PY) {
       // ext column of the first product of the first window: product column c is ext column c + 1
-      const float* row = sP + (item % PY + 1) * LP + 1 + (item / PY) * SL;
+      const int rb = (item % PY + 1) * LP + 1 + (item / PY) * SL;
 #pragma unroll
       for (int q = 0; q < 5; ++q) {
+        const float* row = lds + lds_reg((q + 1) * PL + rb);
         float ring[NWIN];
         float acc = 0.0f;
 #pragma unroll
         for (int k = 0; k < SL + 2 * KR; ++k) {
-          const float pq = row[q * PL + k];
+          const float pq = row[k];
           if (k >= NWIN) acc -= ring[k % NWIN];
           ring[k % NWIN] = pq;
-          acc += pq;
+          acc = k == 0 ? pq : acc + pq;
           if (k >= 2 * KR) hsum[it][q][k - 2 * KR] = acc;
         }
       }
     }
   }
   __syncthreads();
-  // ---- B': the sums of output column j of product row r go to ext column j + 1 of ext row r + 1
+  // ---- B': the sum of output column j of product row r goes to element
+  // j CP + r of the product's transposed plane (planes HPL apart)
 #pragma unroll
   for (int it = 0; it < NIT; ++it) {
     const int item = tid + NT * it;
     if (item < NSEG * PY) {
-      float* row = sP + (item % PY + 1) * LP + 1 + (item / PY) * SL;
+      const int cb = (item / PY) * SL * CP + item % PY;
 #pragma unroll
-      for (int q = 0; q < 5; ++q)
+      for (int q = 0; q < 5; ++q) {
+        float* col = lds + lds_reg(PL + q * HPL + cb);
 #pragma unroll
-        for (int jj = 0; jj < SL; ++jj) row[q * PL + jj] = hsum[it][q][jj];
+        for (int jj = 0; jj < SL; ++jj) col[jj * CP] = hsum[it][q][jj];
+      }
     }
   }
   __syncthreads();
@@ -340,6 +363,9 @@ void gn_tile_kernel(const GnArgs a) {
     const int sg = tid / TX;
     const int gx = x0 + j;
     if (sg < NSEGV && gx < W) {
+      const uint32_t obytes = static_cast<uint32_t>(J.out_pitch) * static_cast<uint32_t>(H) * 4u;
+      const PlaneView wu = plane_view(J.out_u, obytes);
+      const PlaneView wv = plane_view(J.out_v, obytes);
       const int rs = sg * SLV;  // first product row of the first output's window
       // flow at the outputs (the damping anchor V(m)), loaded ahead of the sums
       float um[SLV], vm[SLV];
@@ -362,17 +388,19 @@ void gn_tile_kernel(const GnArgs a) {
           vm[k] = 0.0f;
         }
       }
+      const float* col[5];
+#pragma unroll
+      for (int q = 0; q < 5; ++q) col[q] = lds + lds_reg(PL + q * HPL + j * CP + rs);
       float ring[5][NWIN];
-      float acc[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+      float acc[5];
 #pragma unroll
       for (int k = 0; k < SLV + 2 * KR; ++k) {
-        const int r = rs + k;
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
-          const float hq = sP[q * PL + (r + 1) * LP + j + 1];
+          const float hq = col[q][k];
           if (k >= NWIN) acc[q] -= ring[q][k % NWIN];
           ring[q][k % NWIN] = hq;
-          acc[q] += hq;
+          acc[q] = k == 0 ? hq : acc[q] + hq;
         }
         if (k >= 2 * KR) {
           const int oy = rs + k - 2 * KR;  // output row within the tile
@@ -381,9 +409,10 @@ void gn_tile_kernel(const GnArgs a) {
             float un, vn;
             solve2x2(acc[0], acc[1], acc[2], acc[3], acc[4], um[k - 2 * KR], vm[k - 2 * KR], a.reg_rel, a.reg_abs,
                      un, vn);
-            const int64_t oo = static_cast<int64_t>(gy) * J.out_pitch + gx;
-            J.out_u[oo] = un;
-            J.out_v[oo] = vn;
+            const uint32_t oo =
+                (__umul24(static_cast<uint32_t>(gy), static_cast<uint32_t>(J.out_pitch)) + static_cast<uint32_t>(gx)) * 4u;
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(un), wu, static_cast<int>(oo), 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(vn), wv, static_cast<int>(oo), 0, 0);
           }
         }
       }
