@@ -176,10 +176,10 @@ ofv_status ofv_compute_flow_backward(ofv_handle h, const ofv_image* frame0, cons
 #define OFV_GN_AUTO (-1)      /* tuned table entry if any, else the march for launches of >= 3 Mi pixels,
                                  OFV_GN_TILE_64x16 below */
 #define OFV_GN_MARCH 0        /* 256-column strips marching down tile_h rows */
-#define OFV_GN_TILE_64x32 1   /* 64 x 32 output tiles, three LDS phases */
-#define OFV_GN_TILE_64x16 2   /* 64 x 16 output tiles, three LDS phases */
-#define OFV_GN_TILE_32x16 3   /* 32 x 16 output tiles (coarse levels) */
-#define OFV_GN_TILE_16x16 4   /* 16 x 16 output tiles (coarse levels) */
+#define OFV_GN_TILE_64x32 1   /* 64 x 32 output tiles, 512 lanes per workgroup */
+#define OFV_GN_TILE_64x16 2   /* 64 x 16 output tiles, 256 lanes per workgroup */
+#define OFV_GN_TILE_32x16 3   /* 32 x 16 output tiles, 256 lanes (coarse levels) */
+#define OFV_GN_TILE_16x16 4   /* 16 x 16 output tiles, 256 lanes (coarse levels) */
 #define OFV_GN_TILE_64x32W 5  /* 64 x 32 output tiles, 1024 lanes per workgroup */
 #define OFV_GN_TILE_64x16W 6  /* 64 x 16 output tiles, 512 lanes per workgroup */
 #define OFV_GN_TILE_64x64 7   /* 64 x 64 output tiles, 1024 lanes per workgroup */
@@ -188,7 +188,10 @@ ofv_status ofv_compute_flow_backward(ofv_handle h, const ofv_image* frame0, cons
 
 /* Force a decomposition for later calls on h (OFV_GN_AUTO restores the
  * default); tile_h (rows per strip for OFV_GN_MARCH) is 0 for automatic or
- * 4..1024. */
+ * 4..1024.  The environment variable OFV_GN_VARIANT (march, tile32, tile16,
+ * tile32x16, tile16x16, tile64x64, tile64x32w, tile64x16w, tile16x16w or
+ * tile32x16w), read at every launch, overrides both this choice and the
+ * tuned table; levels one pixel wide or high always take the march. */
 ofv_status ofv_set_gn_variant(ofv_handle h, int variant, int tile_h);
 
 /* Autotuner: runs the estimator on this pair with every candidate

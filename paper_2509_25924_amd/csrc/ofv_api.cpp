@@ -242,6 +242,8 @@ void pick_gn(const ofv_ctx* h, const ofv_ctx::TuneKey& key, int64_t strips, int6
     if (!std::strcmp(e, "tile32x16")) { variant = GN_TILE_32x16; return; }
     if (!std::strcmp(e, "tile16x16")) { variant = GN_TILE_16x16; return; }
     if (!std::strcmp(e, "tile64x64")) { variant = GN_TILE_64x64; return; }
+    if (!std::strcmp(e, "tile64x32w")) { variant = GN_TILE_64x32W; return; }
+    if (!std::strcmp(e, "tile64x16w")) { variant = GN_TILE_64x16W; return; }
     if (!std::strcmp(e, "tile16x16w")) { variant = GN_TILE_16x16W; return; }
     if (!std::strcmp(e, "tile32x16w")) { variant = GN_TILE_32x16W; return; }
   }
