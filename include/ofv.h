@@ -188,9 +188,10 @@ ofv_status ofv_compute_flow_backward(ofv_handle h, const ofv_image* frame0, cons
 
 /* Force a decomposition for later calls on h (OFV_GN_AUTO restores the
  * default); tile_h (rows per strip for OFV_GN_MARCH) is 0 for automatic or
- * 4..1024.  The environment variable OFV_GN_VARIANT (march, tile32, tile16,
- * tile32x16, tile16x16, tile64x64, tile64x32w, tile64x16w, tile16x16w or
- * tile32x16w), read at every launch, overrides both this choice and the
+ * 4..1024.  The environment variable OFV_GN_VARIANT (march, tile64x32,
+ * tile64x16, tile32x16, tile16x16, tile64x32w, tile64x16w, tile64x64,
+ * tile16x16w or tile32x16w; tile32 and tile16 are accepted for tile64x32
+ * and tile64x16), read at every launch, overrides both this choice and the
  * tuned table; levels one pixel wide or high always take the march. */
 ofv_status ofv_set_gn_variant(ofv_handle h, int variant, int tile_h);
 

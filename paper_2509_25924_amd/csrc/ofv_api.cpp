@@ -237,8 +237,8 @@ void pick_gn(const ofv_ctx* h, const ofv_ctx::TuneKey& key, int64_t strips, int6
   }
   if (const char* e = std::getenv("OFV_GN_VARIANT")) {
     if (!std::strcmp(e, "march")) { variant = GN_MARCH; return; }
-    if (!std::strcmp(e, "tile32")) { variant = GN_TILE_64x32; return; }
-    if (!std::strcmp(e, "tile16")) { variant = GN_TILE_64x16; return; }
+    if (!std::strcmp(e, "tile64x32") || !std::strcmp(e, "tile32")) { variant = GN_TILE_64x32; return; }
+    if (!std::strcmp(e, "tile64x16") || !std::strcmp(e, "tile16")) { variant = GN_TILE_64x16; return; }
     if (!std::strcmp(e, "tile32x16")) { variant = GN_TILE_32x16; return; }
     if (!std::strcmp(e, "tile16x16")) { variant = GN_TILE_16x16; return; }
     if (!std::strcmp(e, "tile64x64")) { variant = GN_TILE_64x64; return; }

@@ -454,6 +454,27 @@ def test_every_decomposition_matches_oracle(ofv, variant, tile_h):
     h.close()
 
 
+def test_variant_environment_override(ofv, monkeypatch):
+    """OFV_GN_VARIANT selects the same kernels as ofv_set_gn_variant: equal fields bit for bit."""
+    from paper_2509_25924_amd import _lib
+    say("variant environment override")
+    pair, prm = synth.config_shear_1mp(size=300)
+    f0, f1 = dev_tensor(pair.frame0), dev_tensor(pair.frame1)
+    h = ofv.Handle(300, 300, 1)
+    aliases = {"tile32": "tile64x32", "tile16": "tile64x16"}
+    for name in [n for n in _lib.GN_VARIANTS if n != "auto"] + list(aliases):
+        h.set_gn_variant(aliases.get(name, name), 0)
+        want = ofv.compute_flow(f0, f1, prm, bit_depth=12, handle=h)
+        h.set_gn_variant("auto", 0)
+        monkeypatch.setenv("OFV_GN_VARIANT", name)
+        got = ofv.compute_flow(f0, f1, prm, bit_depth=12, handle=h)
+        monkeypatch.delenv("OFV_GN_VARIANT")
+        torch.cuda.synchronize()
+        say("  ", name, "equal" if torch.equal(got, want) else "DIFFERENT")
+        assert torch.equal(got, want), name
+    h.close()
+
+
 def test_autotune_table_roundtrip(ofv):
     say("autotune")
     pair, prm = synth.config_rankine_256()
