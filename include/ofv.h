@@ -185,23 +185,25 @@ ofv_status ofv_compute_flow_backward(ofv_handle h, const ofv_image* frame0, cons
 #define OFV_GN_TILE_64x64 7   /* 64 x 64 output tiles, 1024 lanes per workgroup */
 #define OFV_GN_TILE_16x16W 8  /* 16 x 16 output tiles, 1024 lanes per workgroup (coarse levels) */
 #define OFV_GN_TILE_32x16W 9  /* 32 x 16 output tiles, 512 lanes per workgroup (coarse levels) */
+#define OFV_GN_TILE_32x32W 10 /* 32 x 32 output tiles, 1024 lanes per workgroup */
 
 /* Force a decomposition for later calls on h (OFV_GN_AUTO restores the
  * default); tile_h (rows per strip for OFV_GN_MARCH) is 0 for automatic or
  * 4..1024.  The environment variable OFV_GN_VARIANT (march, tile64x32,
  * tile64x16, tile32x16, tile16x16, tile64x32w, tile64x16w, tile64x64,
- * tile16x16w or tile32x16w; tile32 and tile16 are accepted for tile64x32
- * and tile64x16), read at every launch, overrides both this choice and the
- * tuned table; levels one pixel wide or high always take the march. */
+ * tile16x16w, tile32x16w or tile32x32w; tile32 and tile16 are accepted for
+ * tile64x32 and tile64x16), read at every launch, overrides both this
+ * choice and the tuned table; levels one pixel wide or high always take the
+ * march. */
 ofv_status ofv_set_gn_variant(ofv_handle h, int variant, int tile_h);
 
 /* Autotuner: runs the estimator on this pair with every candidate
- * decomposition (16x16, 32x16, 64x16, 64x32 and 64x64 tiles with 256 to 1024
- * lanes, strips of 16/32/64 rows): one untimed run each, then `repeats`
- * rounds in which the candidates take turns, every Gauss-Newton launch timed
- * with HIP events; per (window radius, storage, flow mode, level size, batch
- * size) it records the candidate with the lowest median launch time in the
- * handle, and later calls with matching geometry use it.
+ * decomposition (16x16, 32x16, 32x32, 64x16, 64x32 and 64x64 tiles with
+ * 256 to 1024 lanes, strips of 16/32/64 rows): one untimed run each, then
+ * `repeats` rounds in which the candidates take turns, every Gauss-Newton
+ * launch timed with HIP events; per (window radius, storage, flow mode,
+ * level size, batch size) it records the candidate with the lowest median
+ * launch time in the handle, and later calls with matching geometry use it.
  * flow_out receives the flow (as ofv_compute_flow).  Unlike the compute
  * calls this synchronises the stream and may create HIP events; call it at
  * set-up, not inside graph capture.  1 <= repeats <= 1000. */

@@ -58,7 +58,7 @@ class Handle:
 
     def set_gn_variant(self, variant: str = "auto", tile_h: int = 0) -> None:
         """Force a work decomposition of the Gauss-Newton kernel ('auto', 'march', 'tile64x32', 'tile64x16',
-        'tile32x16', 'tile16x16', 'tile64x32w', 'tile64x16w', 'tile64x64', 'tile16x16w', 'tile32x16w')."""
+        'tile32x16', 'tile16x16', 'tile64x32w', 'tile64x16w', 'tile64x64', 'tile16x16w', 'tile32x16w', 'tile32x32w')."""
         check(load().ofv_set_gn_variant(self.ptr, _lib.GN_VARIANTS[variant], int(tile_h)), self.ptr)
 
     def autotune(self, frame0: torch.Tensor, frame1: torch.Tensor, params: Dict, bit_depth: Optional[int] = None,

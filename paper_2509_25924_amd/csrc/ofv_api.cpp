@@ -246,6 +246,7 @@ void pick_gn(const ofv_ctx* h, const ofv_ctx::TuneKey& key, int64_t strips, int6
     if (!std::strcmp(e, "tile64x16w")) { variant = GN_TILE_64x16W; return; }
     if (!std::strcmp(e, "tile16x16w")) { variant = GN_TILE_16x16W; return; }
     if (!std::strcmp(e, "tile32x16w")) { variant = GN_TILE_32x16W; return; }
+    if (!std::strcmp(e, "tile32x32w")) { variant = GN_TILE_32x32W; return; }
   }
   if (h->forced_variant >= 0) {
     variant = h->forced_variant;
@@ -1191,7 +1192,8 @@ ofv_status ofv_autotune(ofv_handle h, const ofv_image* frame0, const ofv_image* 
   // tile variants ignore tile_h (their tile height is fixed); it is recorded as their height
   const Cand cands[] = {{GN_TILE_16x16, 16},  {GN_TILE_16x16W, 16}, {GN_TILE_32x16, 16}, {GN_TILE_32x16W, 16},
                         {GN_TILE_64x16, 16},  {GN_TILE_64x32, 32},  {GN_TILE_64x16W, 16}, {GN_TILE_64x32W, 32},
-                        {GN_TILE_64x64, 64},  {GN_MARCH, 16},       {GN_MARCH, 32},       {GN_MARCH, 64}};
+                        {GN_TILE_32x32W, 32}, {GN_TILE_64x64, 64},  {GN_MARCH, 16},       {GN_MARCH, 32},
+                        {GN_MARCH, 64}};
   constexpr int nc = static_cast<int>(sizeof(cands) / sizeof(cands[0]));
   // launch times per (level key, candidate); the candidates take turns within every
   // repeat, so that slow drifts of the clock affect them alike

@@ -442,7 +442,9 @@ hipError_t launch_gn_tile_cfg(const GnArgs& a, int nblocks, hipStream_t s) {
 // variant GN_TILE_64x64: 64 x 64 outputs, 1024 lanes (segments 8 columns / 4
 // rows), the smallest halo, one workgroup per compute unit;
 // variants GN_TILE_16x16W / 32x16W: the coarse-level tiles with 1024 / 512
-// lanes, so that the warps of a tile are spread over more waves per SIMD.
+// lanes, so that the warps of a tile are spread over more waves per SIMD;
+// variant GN_TILE_32x32W: 32 x 32 outputs, 1024 lanes (segments 4 columns /
+// 2 rows), two pixels per lane in A1 for mid-size levels.
 // The small tiles spread coarse levels over many compute units: there the
 // launch is bound by the instruction latency of few waves, not by traffic.
 // fa (forward-additive estimator): 16 x 16 tiles whatever the variant.
@@ -460,6 +462,7 @@ hipError_t launch_gn_tile_typed(const GnArgs& a, int kr, int variant, int nblock
       case GN_TILE_64x64: return launch_gn_tile_cfg<R, MODE, TS, 64, 64, 8, 4, 1024>(a, nblocks, s);  \
       case GN_TILE_16x16W: return launch_gn_tile_cfg<R, MODE, TS, 16, 16, 4, 1, 1024>(a, nblocks, s); \
       case GN_TILE_32x16W: return launch_gn_tile_cfg<R, MODE, TS, 32, 16, 4, 2, 512>(a, nblocks, s);  \
+      case GN_TILE_32x32W: return launch_gn_tile_cfg<R, MODE, TS, 32, 32, 4, 2, 1024>(a, nblocks, s); \
       default: return launch_gn_tile_cfg<R, MODE, TS, 16, 16, 4, 1, 256>(a, nblocks, s);            \
     }
   switch (kr) {

@@ -139,9 +139,10 @@ enum GnVariant {
   GN_TILE_64x16W = 6,
   GN_TILE_64x64 = 7,
   GN_TILE_16x16W = 8,
-  GN_TILE_32x16W = 9
+  GN_TILE_32x16W = 9,
+  GN_TILE_32x32W = 10
 };
-constexpr int kGnVariants = 10;
+constexpr int kGnVariants = 11;
 
 // Columns of output produced by one 256-lane strip for window radius kr.
 inline int gn_tile_w(int kr) { return kGnThreads - 2 * kr - 2; }
@@ -161,6 +162,7 @@ inline void gn_tile_dims(int variant, int kr, int tile_h, int& tw, int& th) {
   else if (variant == GN_TILE_64x32W) { tw = 64; th = 32; }
   else if (variant == GN_TILE_64x64) { tw = 64; th = 64; }
   else if (variant == GN_TILE_32x16 || variant == GN_TILE_32x16W) { tw = 32; th = 16; }
+  else if (variant == GN_TILE_32x32W) { tw = 32; th = 32; }
   else if (variant == GN_TILE_16x16 || variant == GN_TILE_16x16W) { tw = 16; th = 16; }
   else { tw = gn_tile_w(kr); th = tile_h; }
 }
