@@ -3,10 +3,12 @@
 // velocity probes and the recirculation area of Eq. (RA).
 // derived_kernel streams the field once (the neighbour taps of the central
 // differences hit the caches) with a bounded grid that strides over 64-column
-// tiles (one column of kDerivedRows consecutive rows per lane), writes the vorticity plane, interpolates the probes, and counts
-// the recirculating pixels with one ballot per wavefront and row; each
-// workgroup stores its count in its own slot (no atomics, so the count is
-// exact and the launch can be replayed in a graph).  derived_area_kernel,
+// tiles (one column of kDerivedRows consecutive rows per lane), writes the
+// vorticity plane, interpolates the probes, and counts the recirculating
+// pixels with one ballot per wavefront and row; the wavefronts of a
+// workgroup add their counts in LDS and the workgroup stores the total in its
+// own slot (no global atomics, so the count is exact and deterministic and
+// the launch can be replayed in a graph).  derived_area_kernel,
 // one workgroup, sums the slots and writes the area.
 #include <stdint.h>
 
@@ -28,8 +30,8 @@ __global__ __launch_bounds__(256) void derived_kernel(const DerivedArgs a) {
   unsigned int cnt = 0;  // recirculating pixels seen by this lane's wavefront (the same in every lane)
   const int ntx = (a.w + kDerivedTW - 1) / kDerivedTW;
   for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
-    // lane: one column, 4 consecutive rows of the tile; the u rows above and
-    // below are carried from row to row
+    // lane: one column, kDerivedRows consecutive rows of the tile; the u rows
+    // above and below are carried from row to row
     const int x = (t % ntx) * kDerivedTW + (tid & 63);
     const int y0 = (t / ntx) * kDerivedTH + kDerivedRows * (tid >> 6);
     const bool xin = x < a.w;
