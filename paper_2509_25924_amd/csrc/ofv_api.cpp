@@ -356,8 +356,11 @@ ofv_status run_pipeline(ofv_ctx* h, int n, PairPlan* pp, const ofv_params* p, fl
     } else {
       ReduceMArgs ra{};
       ra.storage = st;
+      int64_t px = 0;  // input pixels of the launches
+      for (const auto& f : fj) px += static_cast<int64_t>(pp[f.first].lw[l - 1]) * pp[f.first].lh[l - 1];
+      const bool small = reduce_multi_small(nlev, px);
       int tw = 0, th = 0;
-      reduce_multi_tile(nlev, tw, th);
+      reduce_multi_tile(nlev, small, tw, th);
       auto fill = [&](int i, ReduceMJob& J) {
         const PairPlan& q = pp[fj[i].first];
         J.in = img_plane(h, q, fj[i].second, l - 1, ts);
@@ -372,7 +375,8 @@ ofv_status run_pipeline(ofv_ctx* h, int n, PairPlan* pp, const ofv_params* p, fl
         return ((q.lw[d] + tw - 1) / tw) * ((q.lh[d] + th - 1) / th);
       };
       r = run_chunked(h, nf, ra, fill,
-                      [&](const ReduceMArgs& a, int b) { return launch_reduce_multi(a, nlev, b, s); }, "reduce");
+                      [&](const ReduceMArgs& a, int b) { return launch_reduce_multi(a, nlev, small, b, s); },
+                      "reduce");
     }
     if (r != OFV_OK) return r;
     l += nlev;
@@ -1391,9 +1395,11 @@ ofv_status ofv_stage_pyramid(ofv_handle h, int storage, const void* in, int widt
   J.w = width;
   J.h = height;
   J.tile_start = 0;
+  const bool small = reduce_multi_small(levels, static_cast<int64_t>(width) * height);
   int tw = 0, th = 0;
-  reduce_multi_tile(levels, tw, th);
-  const hipError_t e = launch_reduce_multi(ra, levels, ((w + tw - 1) / tw) * ((hh + th - 1) / th), h->stream);
+  reduce_multi_tile(levels, small, tw, th);
+  const hipError_t e =
+      launch_reduce_multi(ra, levels, small, ((w + tw - 1) / tw) * ((hh + th - 1) / th), h->stream);
   return e == hipSuccess ? OFV_OK : device_error(h, e, "pyramid");
 }
 

@@ -71,10 +71,20 @@ struct ReduceMArgs {
   int pad_[2];
   ReduceMJob job[kMaxJobs];
 };
-// output tile of the deepest level per workgroup for nlev levels
-inline void reduce_multi_tile(int nlev, int& tw, int& th) {
-  tw = nlev == 3 ? 16 : 32;
-  th = 8;
+// Output tile of the deepest level and lanes per workgroup for nlev
+// levels.  Three levels: launches over at least kReduceMSmallPixels input
+// pixels take 8 x 8 tiles with 512 lanes (51 KB of LDS at FP32, several
+// workgroups per compute unit, so that the loads of one overlap the passes
+// of another), smaller launches 16 x 8 tiles with 1024 lanes (the smallest
+// halo; 90 KB, one workgroup per compute unit).
+constexpr int64_t kReduceMSmallPixels = int64_t{4} << 20;
+inline bool reduce_multi_small(int nlev, int64_t pixels) { return nlev == 3 && pixels >= kReduceMSmallPixels; }
+constexpr int reduce_multi_tw(int nlev, bool small) { return nlev == 3 ? (small ? 8 : 16) : 32; }
+constexpr int reduce_multi_th(int, bool) { return 8; }
+constexpr int reduce_multi_nt(int nlev, bool small) { return nlev == 3 ? (small ? 512 : 1024) : 256; }
+inline void reduce_multi_tile(int nlev, bool small, int& tw, int& th) {
+  tw = reduce_multi_tw(nlev, small);
+  th = reduce_multi_th(nlev, small);
 }
 
 // ---------------------------------------------------------------- live derived quantities
@@ -169,7 +179,7 @@ inline void gn_tile_dims(int variant, int kr, int tile_h, int& tw, int& th) {
 
 hipError_t launch_normalize(const NormArgs& a, int nblocks, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, int nblocks, hipStream_t s);
-hipError_t launch_reduce_multi(const ReduceMArgs& a, int nlev, int nblocks, hipStream_t s);
+hipError_t launch_reduce_multi(const ReduceMArgs& a, int nlev, bool small, int nblocks, hipStream_t s);
 hipError_t launch_upsample(const UpsampleArgs& a, hipStream_t s);
 hipError_t launch_derived(const DerivedArgs& a, int nblocks, hipStream_t s);
 // All jobs of one launch share the input-flow mode (a compile-time parameter of the kernel).

@@ -501,10 +501,10 @@ __global__ __launch_bounds__(NT) void reduce_multi_kernel(const ReduceMArgs a) {
   chain_levels<TS, NLEV, TW, TH, NT>(lds, ox, oy, lw, lh, J.out, J.out_pitch);
 }
 
-template <typename TS, int NLEV>
+template <typename TS, int NLEV, bool SMALL>
 hipError_t launch_reduce_multi_typed(const ReduceMArgs& a, int nblocks, hipStream_t s) {
-  constexpr int TW = NLEV == 3 ? 16 : 32, TH = 8;
-  constexpr int NT = NLEV == 3 ? 1024 : 256;
+  constexpr int TW = reduce_multi_tw(NLEV, SMALL), TH = reduce_multi_th(NLEV, SMALL);
+  constexpr int NT = reduce_multi_nt(NLEV, SMALL);
   constexpr size_t lds = sizeof(float) * RChain<NLEV, TW, TH>::LDS_FLOATS;
   auto kern = reduce_multi_kernel<TS, NLEV, TW, TH, NT>;
   static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
@@ -516,17 +516,19 @@ hipError_t launch_reduce_multi_typed(const ReduceMArgs& a, int nblocks, hipStrea
 }
 
 template <typename TS>
-hipError_t launch_reduce_multi_st(const ReduceMArgs& a, int nlev, int nblocks, hipStream_t s) {
-  if (nlev == 2) return launch_reduce_multi_typed<TS, 2>(a, nblocks, s);
-  if (nlev == 3) return launch_reduce_multi_typed<TS, 3>(a, nblocks, s);
+hipError_t launch_reduce_multi_st(const ReduceMArgs& a, int nlev, bool small, int nblocks, hipStream_t s) {
+  if (nlev == 2) return launch_reduce_multi_typed<TS, 2, false>(a, nblocks, s);
+  if (nlev == 3)
+    return small ? launch_reduce_multi_typed<TS, 3, true>(a, nblocks, s)
+                 : launch_reduce_multi_typed<TS, 3, false>(a, nblocks, s);
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_reduce_multi(const ReduceMArgs& a, int nlev, int nblocks, hipStream_t s) {
+hipError_t launch_reduce_multi(const ReduceMArgs& a, int nlev, bool small, int nblocks, hipStream_t s) {
   switch (a.storage) {
-    case ST_F32: return launch_reduce_multi_st<float>(a, nlev, nblocks, s);
-    case ST_F16: return launch_reduce_multi_st<_Float16>(a, nlev, nblocks, s);
-    default: return launch_reduce_multi_st<bf16_t>(a, nlev, nblocks, s);
+    case ST_F32: return launch_reduce_multi_st<float>(a, nlev, small, nblocks, s);
+    case ST_F16: return launch_reduce_multi_st<_Float16>(a, nlev, small, nblocks, s);
+    default: return launch_reduce_multi_st<bf16_t>(a, nlev, small, nblocks, s);
   }
 }
 

@@ -45,10 +45,20 @@ struct Px<float> {
   static __device__ __forceinline__ void st(float* p, float v) { *p = v; }
 };
 
+// float32 -> float16, round to nearest even, from a value the compiler treats
+// as opaque: the conversion always takes the float32-rounded result, never
+// a multiply-add fused with it into one rounding (v_fma_mix), which the
+// compiler would otherwise do at some call sites and not at others, so that
+// kernels computing the same sums could store different halves.
+__device__ __forceinline__ _Float16 to_half(float v) {
+  asm volatile("" : "+v"(v));
+  return static_cast<_Float16>(v);
+}
+
 template <>
 struct Px<_Float16> {
   static __device__ __forceinline__ float ld(const _Float16* p) { return static_cast<float>(*p); }
-  static __device__ __forceinline__ float round(float v) { return static_cast<float>(static_cast<_Float16>(v)); }
+  static __device__ __forceinline__ float round(float v) { return static_cast<float>(to_half(v)); }
   static __device__ __forceinline__ float ldv(PlaneView v, uint32_t i) { return ldvs(v, i, 0); }
   static __device__ __forceinline__ float ldvs(PlaneView v, uint32_t i, uint32_t jb) {
     const uint16_t b = __builtin_amdgcn_raw_buffer_load_b16(v, static_cast<int>(i * 2u), static_cast<int>(jb), 0);
@@ -62,7 +72,7 @@ struct Px<_Float16> {
     a = static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(w & 0xffffu)));
     b = static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(w >> 16)));
   }
-  static __device__ __forceinline__ void st(_Float16* p, float v) { *p = static_cast<_Float16>(v); }
+  static __device__ __forceinline__ void st(_Float16* p, float v) { *p = to_half(v); }
 };
 
 // bfloat16 = the upper half of an IEEE binary32; conversion from float rounds

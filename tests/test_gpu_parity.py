@@ -85,7 +85,10 @@ def test_reduce_stage(ofv, shape):
 
 
 @pytest.mark.parametrize("storage,dt", [("f32", torch.float32), ("f16", torch.float16), ("bf16", torch.bfloat16)])
-@pytest.mark.parametrize("shape", [(1, 1), (3, 5), (9, 1), (65, 130), (257, 255), (1024, 1024), (1000, 1366)])
+# 2048 x 2048 and 2100 x 2003 reach the launch size that takes the small
+# three-level tiles
+@pytest.mark.parametrize("shape", [(1, 1), (3, 5), (9, 1), (65, 130), (257, 255), (1024, 1024), (1000, 1366),
+                                   (2048, 2048), (2100, 2003)])
 def test_pyramid_stage_equals_chained_reduce(ofv, storage, dt, shape):
     """Several REDUCE levels in one launch give the chained single-level
     result bit for bit (each level rounded to the storage type before the
