@@ -20,7 +20,9 @@
 //  B.  per (product row, segment of SL output columns): horizontal window
 //      sums by running sums over the product planes, kept in registers ...
 //  B'. ... and written back, transposed (column-major, one plane per
-//      product), over the product planes once every lane has read its inputs;
+//      product), over the product planes once every lane has read its inputs
+//      (1024-lane tiles with LDS to spare: into a region of their own, with
+//      no barrier between B and B');
 //  C.  per (output column, segment of SLV output rows): running vertical
 //      window sums along the contiguous columns of B', damped 2x2 solve,
 //      coalesced store of u' and v'.
@@ -48,6 +50,18 @@ struct TileGeom {
   static_assert(HPL <= PLANE, "transposed sums fit in the product planes");
   // the S plane and five product planes, all indexed by ext coordinates
   static constexpr int LDS_FLOATS = 6 * PLANE;
+};
+
+// 1024-lane workgroups (at most two per compute unit) whose product planes
+// leave room within 80 KiB put the transposed horizontal sums in an LDS
+// region of their own: B then stores them as it forms them, without the
+// barrier and the register round trip of writing back over the products.
+template <int KR, int TX, int TY, int NT>
+struct TileLds {
+  using G = TileGeom<KR, TX, TY>;
+  static constexpr bool HSEP = NT == 1024 && 4 * (G::LDS_FLOATS + 5 * G::HPL) <= 81920;
+  static constexpr int HOFF = HSEP ? G::LDS_FLOATS : G::PLANE;  // first float of the sums
+  static constexpr int FLOATS = HSEP ? G::LDS_FLOATS + 5 * G::HPL : G::LDS_FLOATS;
 };
 
 // Bilinear sample at (x, y) clamped into a w x h plane, split into the
@@ -105,7 +119,7 @@ __device__ __forceinline__ int xcd_tile(int l, int n) {
 // the register budget of the kernel is sized for that occupancy.
 template <int KR, int TX, int TY, int NT>
 struct TileOcc {
-  static constexpr int lds = 4 * TileGeom<KR, TX, TY>::LDS_FLOATS;
+  static constexpr int lds = 4 * TileLds<KR, TX, TY, NT>::FLOATS;
   static constexpr int fit = (163840 / lds) * (NT / 256);
   // at most 4 waves per SIMD: 128 registers per lane keep the gathers of a
   // chunk in flight without spilling
@@ -121,6 +135,8 @@ void gn_tile_kernel(const GnArgs a) {
   using G = TileGeom<KR, TX, TY>;
   constexpr int NWIN = G::NWIN, EX = G::EX, EY = G::EY, LP = G::LP, PY = G::PY, PL = G::PLANE, NE = G::NE;
   constexpr int CP = G::CP, HPL = G::HPL;
+  constexpr bool HSEP = TileLds<KR, TX, TY, NT>::HSEP;
+  constexpr int HOFF = TileLds<KR, TX, TY, NT>::HOFF;
   constexpr int NSEG = TX / SL;
   static_assert(TX % SL == 0 && TY % SLV == 0, "segments must tile the output");
   static_assert(TX * (TY / SLV) <= NT, "phase C items");
@@ -338,9 +354,11 @@ void gn_tile_kernel(const GnArgs a) {
       }
     }
   }
-  __syncthreads();
   // ---- B': the sum of output column j of product row r goes to element
-  // j CP + r of the product's transposed plane (planes HPL apart)
+  // j CP + r of the product's transposed plane (planes HPL apart from
+  // HOFF): over the product planes once every lane has read them, or at
+  // once into a region of their own
+  if (!HSEP) __syncthreads();
 #pragma unroll
   for (int it = 0; it < NIT; ++it) {
     const int item = tid + NT * it;
@@ -348,7 +366,7 @@ void gn_tile_kernel(const GnArgs a) {
       const int cb = (item / PY) * SL * CP + item % PY;
 #pragma unroll
       for (int q = 0; q < 5; ++q) {
-        float* col = lds + lds_reg(PL + q * HPL + cb);
+        float* col = lds + lds_reg(HOFF + q * HPL + cb);
 #pragma unroll
         for (int jj = 0; jj < SL; ++jj) col[jj * CP] = hsum[it][q][jj];
       }
@@ -390,7 +408,7 @@ void gn_tile_kernel(const GnArgs a) {
       }
       const float* col[5];
 #pragma unroll
-      for (int q = 0; q < 5; ++q) col[q] = lds + lds_reg(PL + q * HPL + j * CP + rs);
+      for (int q = 0; q < 5; ++q) col[q] = lds + lds_reg(HOFF + q * HPL + j * CP + rs);
       float ring[5][NWIN];
       float acc[5];
 #pragma unroll
@@ -422,7 +440,7 @@ void gn_tile_kernel(const GnArgs a) {
 
 template <int KR, int MODE, typename TS, int TX, int TY, int SL, int SLV, int NT, bool FA = false>
 hipError_t launch_gn_tile_cfg(const GnArgs& a, int nblocks, hipStream_t s) {
-  constexpr size_t lds = sizeof(float) * TileGeom<KR, TX, TY>::LDS_FLOATS;
+  constexpr size_t lds = sizeof(float) * TileLds<KR, TX, TY, NT>::FLOATS;
   auto kern = gn_tile_kernel<KR, MODE, TS, TX, TY, SL, SLV, NT, FA>;
   // dynamic LDS above 64 KiB must be enabled once per kernel (thread-safe static init)
   static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
