@@ -95,7 +95,7 @@ def parse():
                     help="particle fields per image of the accuracy sweep (the paper uses 10)")
     ap.add_argument("--suite", default=None,
                     choices=["batch4mp", "live21mp", "stream21mp", "sweep", "adjoint512", "paper", "oracle",
-                             "all"],
+                             "preprocess", "all"],
                     help="run an additional measurement instead of the default workload (one JSON line each)")
     return ap.parse_args()
 
@@ -697,6 +697,32 @@ def suite_paper(args, dev):
             "data": "synthetic 8-bit particle pairs (translation + shear), pre-loaded in device memory"}
 
 
+def suite_preprocess(args, dev):
+    """Normalisation (NR 1, 12-bit input, FP32 planes) and the three-level pyramid of one frame at 1, 4 and
+    21 Mp through the stage entry points.  Host-timed averages over back-to-back calls: at 1 Mp the Python
+    call rate bounds them, so the kernel durations come from a kernel trace of this suite."""
+    import torch
+    import paper_2509_25924_amd as ofv
+    rows = []
+    g = torch.Generator(device=dev).manual_seed(7)
+    for (w, h) in ((1024, 1024), (2048, 2048), (5120, 4096)):
+        frame = torch.randint(0, 4096, (h, w), dtype=torch.int32, device=dev, generator=g).to(torch.uint16)
+        hd = ofv.Handle(w, h, 1)
+        plane = ofv.stage_normalize(frame, 1, 1e-4, "f32", bit_depth=12, handle=hd)
+        n = 200 if w * h <= 4 << 20 else 50
+        t_norm = _timed(lambda: ofv.stage_normalize(frame, 1, 1e-4, "f32", bit_depth=12, handle=hd), n, 5)
+        t_pyr = _timed(lambda: ofv.stage_pyramid(plane, 3, handle=hd), n, 5)
+        px = w * h
+        norm_bytes = px * (2 + 4)
+        pyr_bytes = px * 4 + sum(((w + (1 << k) - 1) >> k) * ((h + (1 << k) - 1) >> k) * 4 for k in (1, 2, 3))
+        rows.append({"size": f"{w}x{h}", "normalize_us": round(t_norm * 1e6, 2),
+                     "normalize_GBps": round(norm_bytes / t_norm / 1e9, 1),
+                     "pyramid3_us": round(t_pyr * 1e6, 2), "pyramid3_GBps": round(pyr_bytes / t_pyr / 1e9, 1)})
+        hd.close()
+    return {"metric": "normalisation and three-level pyramid of one frame (host-timed, per call)", "rows": rows,
+            "data": "uniform random 12-bit frames"}
+
+
 def run_suite(args):
     import torch
     import paper_2509_25924_amd as ofv
@@ -709,7 +735,7 @@ def run_suite(args):
              else [args.suite])
     fns = {"batch4mp": suite_batch4mp, "live21mp": suite_live21mp, "stream21mp": suite_stream21mp,
            "sweep": suite_sweep, "oracle": suite_oracle,
-           "adjoint512": suite_adjoint512, "paper": suite_paper}
+           "adjoint512": suite_adjoint512, "paper": suite_paper, "preprocess": suite_preprocess}
     for nm in names:
         print(f"# suite {nm} ...", file=sys.stderr, flush=True)
         r = fns[nm](args, dev)
