@@ -184,6 +184,9 @@ void gn_tile_kernel(const GnArgs a) {
   // then are any combined, so up to 8 CH gathers are in flight per lane.
   float kT[NA], kU[NA], kV[NA];
   int kO[NA];      // LDS offset of each pixel of the lane
+  // up-sampling iterations: the up-sampled flow of the tile's output rows
+  // goes from A1 to C through LDS where the free space allows
+  constexpr bool STAGE_UV = MODE == FLOW_UPSAMPLE && !HSEP && PL + 5 * HPL + TY * LP <= 6 * PL;
   uint32_t kF = 0; // bit 2k: pixel k is in the product region; bit 2k+1: it lies inside the level
   {
     constexpr int DY = NT / EX, DX = NT % EX;
@@ -372,6 +375,23 @@ void gn_tile_kernel(const GnArgs a) {
       }
     }
   }
+  // The up-sampled flow of the ext pixels on the tile's output rows, as A1
+  // computed it, for the damping anchor of C (instead of eight more gathers
+  // per output there), at their ext offsets less KR + 1 rows: U over the S
+  // plane (free after A2), V past the transposed sums (free after B).
+  // Slots past the ext region lie below the output rows.
+  float* const sUm = lds;
+  float* const sVm = lds + PL + 5 * HPL;
+  if (STAGE_UV) {
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+      const int d = kO[k] - (KR + 1) * LP;
+      if (static_cast<unsigned>(d) < static_cast<unsigned>(TY * LP)) {
+        sUm[d] = kU[k];
+        sVm[d] = kV[k];
+      }
+    }
+  }
   __syncthreads();
 
   // ---- C: vertical window sums, solve, store; item = (output column, segment)
@@ -394,6 +414,9 @@ void gn_tile_kernel(const GnArgs a) {
           const uint32_t o = __umul24(static_cast<uint32_t>(gy), fpitch) + static_cast<uint32_t>(gx);
           um[k] = ld_f32(vu, o);
           vm[k] = ld_f32(vv, o);
+        } else if (STAGE_UV) {
+          um[k] = sUm[(rs + k) * LP + KR + 1 + j];
+          vm[k] = sVm[(rs + k) * LP + KR + 1 + j];
         } else if (MODE == FLOW_UPSAMPLE) {
           const BilTap tp = bil_setup(0.5f * static_cast<float>(gx), 0.5f * static_cast<float>(gy), cwm1, chm1,
                                       cwm2, chm2, fpitch);
