@@ -858,9 +858,9 @@ def main():
     for _ in range(10):
         ofv.stage_gn_iteration(p0, p1, fin, "direct", kr, prm["reg_rel"], prm["reg_abs"], handle=handle)
     # The roofline's launch duration: the launches captured back to back in a
-    # hipGraph (as inside the pipeline), one replay bracketed by a pair of
-    # events on the launch stream, so that host-side call overhead cannot
-    # open gaps between them.  Two eager figures are reported beside it: an
+    # hipGraph (as inside the pipeline), each of five replays bracketed by a
+    # pair of events on the launch stream, so that host-side call overhead
+    # cannot open gaps between them; the median replay is reported.  Two eager figures are reported beside it: an
     # event pair around each launch (one queue barrier per event) and a pair
     # around an eager loop of back-to-back calls (host-bound when a call
     # takes longer to issue than the kernel runs).
@@ -889,11 +889,14 @@ def main():
         handle.bind_stream()
         kgraph.replay()
         torch.cuda.synchronize()
-        ev0.record()
-        kgraph.replay()
-        ev1.record()
-        torch.cuda.synchronize()
-        kern_s = ev0.elapsed_time(ev1) / 1e3 / args.kernel_launches
+        reps = []
+        for _ in range(5):
+            ev0.record()
+            kgraph.replay()
+            ev1.record()
+            torch.cuda.synchronize()
+            reps.append(ev0.elapsed_time(ev1))
+        kern_s = sorted(reps)[len(reps) // 2] / 1e3 / args.kernel_launches
         del kgraph
     else:
         kern_s = eager_s
@@ -964,7 +967,7 @@ def main():
                      "kernel": f"Gauss-Newton iteration, {decomp}, KR {kr}, {args.storage}, full resolution {w}x{h}",
                      "bytes_per_launch": algo_bytes, "us_per_launch": round(kern_s * 1e6, 3),
                      "launches_timed": args.kernel_launches,
-                     "timed_as": "hipGraph replay of back-to-back launches" if graph is not None else "eager loop",
+                     "timed_as": "median of 5 hipGraph replays of back-to-back launches" if graph is not None else "eager loop",
                      "us_eager_loop_per_launch": round(eager_s * 1e6, 3),
                      "us_event_pair_per_launch": round(pair_s * 1e6, 3),
                      "stream_copy_GBps": round(copy_gbps, 1)},
