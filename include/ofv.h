@@ -144,6 +144,25 @@ ofv_status ofv_compute_flow_batch(ofv_handle h, int n, const ofv_image* frame0, 
                                   const ofv_params* params, const float* const* flow_init,
                                   float* const* flow_out);
 
+/* For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * estimator of ofv_compute_flow without a handle.  Its workspace (both
+ * frames' pyramids and the flow ping-pong buffers, 8/3 * 4 * 2 + 16 bytes
+ * per pixel with rows padded to 64 elements) lives in a static 48 MiB device
+ * array of the library, one per device, held until the process ends; pairs
+ * needing more (above about 1.5 Mi pixels, e.g. 1280 x 1024 fits, 1536 x
+ * 1024 does not) give OFV_ERR_CAPACITY before anything is enqueued.  Work
+ * runs on the current device, enqueued on `stream` (a hipStream_t, NULL =
+ * the default stream); the call allocates nothing and does not synchronise.
+ * The array is shared by every call on the device and keeps the last
+ * call's contents (nothing in it needs to start at zero): calls that
+ * overlap on one device, e.g. on two streams, race and give undefined
+ * results.  The work decomposition is the default one (tuned tables live in
+ * handles).  Arguments, errors and results as ofv_compute_flow;
+ * ofv_last_error(NULL) holds the message of a failing call on this thread. */
+ofv_status ofv_compute_flow_static(const ofv_image* frame0, const ofv_image* frame1, const ofv_params* params,
+                                   float* flow_out, void* stream);
+
 /* Reserve device memory for ofv_compute_flow_backward on pairs up to the
  * handle's max size with up to max_levels levels and max_iterations
  * iterations per level: the output field of every iteration (8 bytes per

@@ -191,6 +191,24 @@ def compute_flow(frame0: torch.Tensor, frame1: torch.Tensor, params: Dict, flow_
     return out
 
 
+def compute_flow_static(frame0: torch.Tensor, frame1: torch.Tensor, params: Dict, bit_depth: Optional[int] = None,
+                        out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Dense flow of one pair through ofv_compute_flow_static: no handle and no device allocation by the
+    library (its workspace is a static device array of 48 MiB, about 1.5 Mi pixels per pair); enqueued on the
+    current torch stream.  Concurrent calls on one device race (they share that array)."""
+    h, w = frame0.shape
+    if out is None:
+        out = torch.empty((2, h, w), dtype=torch.float32, device=frame0.device)
+    _check_flow(out, h, w, "out")
+    i0, i1 = image_desc(frame0, bit_depth), image_desc(frame1, bit_depth)
+    p = params_struct(params)
+    with torch.cuda.device(frame0.device):
+        st = load().ofv_compute_flow_static(byref(i0), byref(i1), byref(p), c_void_p(out.data_ptr()),
+                                            c_void_p(_stream_ptr(frame0.device.index)))
+    check(st, None)
+    return out
+
+
 def compute_flow_batch(frames0: Sequence[torch.Tensor], frames1: Sequence[torch.Tensor], params: Dict,
                        flow_init: Optional[Sequence[Optional[torch.Tensor]]] = None, bit_depth: Optional[int] = None,
                        outs: Optional[Sequence[torch.Tensor]] = None, handle: Optional[Handle] = None

@@ -12,6 +12,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <tuple>
@@ -622,6 +623,25 @@ ofv_status compute_common(ofv_ctx* h, int n, const ofv_image* f0, const ofv_imag
   return run_pipeline(h, n, pp.data(), p);
 }
 
+// Workspace layout of a handle for pairs up to w x hgt: level sizes and
+// pitches, each level's offset in a frame's pyramid slab (sized for float32
+// planes), and the bytes of one pair's slot (two slabs, two flow buffers).
+void set_geometry(ofv_ctx* h, int w, int hgt, int batch) {
+  h->max_w = w;
+  h->max_h = hgt;
+  h->max_batch = batch;
+  level_dims(w, hgt, OFV_MAX_LEVELS, h->lw, h->lh);
+  int64_t off = 0;
+  for (int l = 0; l < OFV_MAX_LEVELS; ++l) {
+    h->lpitch[l] = round_up(h->lw[l], kPitchAlign);
+    h->img_off[l] = off;
+    off += h->lpitch[l] * h->lh[l];
+  }
+  h->frame_bytes = round_up(off * 4, kSlabAlign);
+  h->flow_bytes = round_up(2 * h->lpitch[0] * h->lh[0] * 4, kSlabAlign);
+  h->slot_bytes = 2 * h->frame_bytes + 2 * h->flow_bytes;
+}
+
 }  // namespace
 
 // ====================================================================== C ABI
@@ -670,19 +690,7 @@ ofv_status ofv_create(ofv_handle* out, int device, int max_width, int max_height
   if (!h) return fail(nullptr, OFV_ERR_OUT_OF_MEMORY, "host allocation failed");
   h->device = device;
   h->stream = static_cast<hipStream_t>(stream);
-  h->max_w = max_width;
-  h->max_h = max_height;
-  h->max_batch = max_batch;
-  level_dims(max_width, max_height, OFV_MAX_LEVELS, h->lw, h->lh);
-  int64_t off = 0;
-  for (int l = 0; l < OFV_MAX_LEVELS; ++l) {
-    h->lpitch[l] = round_up(h->lw[l], kPitchAlign);
-    h->img_off[l] = off;
-    off += h->lpitch[l] * h->lh[l];
-  }
-  h->frame_bytes = round_up(off * 4, kSlabAlign);
-  h->flow_bytes = round_up(2 * h->lpitch[0] * h->lh[0] * 4, kSlabAlign);
-  h->slot_bytes = 2 * h->frame_bytes + 2 * h->flow_bytes;
+  set_geometry(h, max_width, max_height, max_batch);
   h->ws_bytes = h->slot_bytes * static_cast<size_t>(max_batch) + kDerivedMaxBlocks * sizeof(unsigned int);
   if (device >= 0) {
     if (fault_injected("alloc")) {
@@ -737,6 +745,81 @@ ofv_status ofv_compute_flow_batch(ofv_handle h, int n, const ofv_image* frame0, 
                                   const ofv_params* params, const float* const* flow_init,
                                   float* const* flow_out) {
   return compute_common(h, n, frame0, frame1, params, flow_init, flow_out);
+}
+
+// ------------------------------------------------------------------ no-allocation entry point
+
+// Device scratch of ofv_compute_flow_static: the two pyramid slabs and the
+// two flow ping-pong buffers of one pair.  Each device the library runs on
+// holds its own copy until the process ends.  In host code `scratch` is
+// only a stand-in for the symbol: its device address comes from
+// hipGetSymbolAddress, once per device.
+static constexpr size_t kStaticScratchBytes = size_t{48} << 20;
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
+namespace {
+
+constexpr int kMaxStaticDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxStaticDevices] = {};
+
+// Device address of `scratch` on the current device `dev`.
+hipError_t static_scratch(int dev, char** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<char*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+ofv_status static_fail(ofv_ctx* c, ofv_status s) {
+  g_create_error = c->err;
+  return s;
+}
+
+}  // namespace
+
+ofv_status ofv_compute_flow_static(const ofv_image* frame0, const ofv_image* frame1, const ofv_params* params,
+                                   float* flow_out, void* stream) {
+  g_create_error.clear();
+  ofv_ctx c;  // host-side plan of the call: it owns no device memory
+  ofv_status r = check_params(&c, params);
+  if (r != OFV_OK) return static_fail(&c, r);
+  r = check_image(&c, frame0, "frame0");
+  if (r != OFV_OK) return static_fail(&c, r);
+  r = check_image(&c, frame1, "frame1");
+  if (r != OFV_OK) return static_fail(&c, r);
+  set_geometry(&c, frame0->width, frame0->height, 1);
+  if (c.slot_bytes > kStaticScratchBytes)
+    return static_fail(&c, fail(&c, OFV_ERR_CAPACITY,
+                                "%dx%d needs %zu bytes of scratch; the static scratch holds %zu (about 1.5 Mi pixels)",
+                                frame0->width, frame0->height, c.slot_bytes, kStaticScratchBytes));
+  r = validate_pair(&c, frame0, frame1, nullptr, flow_out, 0);
+  if (r != OFV_OK) return static_fail(&c, r);
+  if (fault_injected("launch")) return static_fail(&c, fail(&c, OFV_ERR_DEVICE, "injected launch failure"));
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return static_fail(&c, device_error(&c, e, "hipGetDevice"));
+  if (dev < 0 || dev >= kMaxStaticDevices)
+    return static_fail(&c, fail(&c, OFV_ERR_UNSUPPORTED, "device %d: at most %d devices", dev, kMaxStaticDevices));
+  e = static_scratch(dev, &c.ws);
+  if (e != hipSuccess) return static_fail(&c, device_error(&c, e, "hipGetSymbolAddress(scratch)"));
+  c.device = dev;
+  c.stream = static_cast<hipStream_t>(stream);
+  c.ws_bytes = kStaticScratchBytes;
+  PairPlan pp{};
+  pp.f[0] = frame0;
+  pp.f[1] = frame1;
+  pp.init = nullptr;
+  pp.out = flow_out;
+  pp.slot = c.ws;
+  level_dims(frame0->width, frame0->height, params->num_levels, pp.lw, pp.lh);
+  r = run_pipeline(&c, 1, &pp, params);
+  return r == OFV_OK ? OFV_OK : static_fail(&c, r);
 }
 
 // ------------------------------------------------------------------ adjoint

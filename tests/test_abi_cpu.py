@@ -302,3 +302,28 @@ def test_estimator_flags(lib, vhandle):
     assert lib.ofv_compute_flow_backward(vhandle, byref(img0), byref(img1), byref(p), None, c_void_p(OUT),
                                          c_void_p(OUT + (1 << 20)), None, None) == _lib.OFV_ERR_UNSUPPORTED
     assert b"symmetric" in lib.ofv_last_error(vhandle)
+
+
+def test_static_entry_point_validation(lib, monkeypatch):
+    """ofv_compute_flow_static checks everything on the host before touching a device: bad
+    arguments, and pairs whose workspace exceeds the static scratch array (OFV_ERR_CAPACITY)."""
+    def call(i0, i1, p, out=OUT):
+        return lib.ofv_compute_flow_static(byref(i0), byref(i1), byref(p), c_void_p(out), None)
+
+    assert lib.ofv_compute_flow_static(None, byref(_img()), byref(_params()), c_void_p(OUT), None) == \
+        _lib.OFV_ERR_INVALID_ARG
+    assert b"frame0 is NULL" in lib.ofv_last_error(None)
+    assert call(_img(), _img(0x200000), _params(kernel_radius=0)) == _lib.OFV_ERR_INVALID_ARG
+    assert b"kernel_radius" in lib.ofv_last_error(None)
+    assert call(_img(), _img(0x200000, w=65), _params()) == _lib.OFV_ERR_INVALID_ARG
+    assert b"sizes differ" in lib.ofv_last_error(None)
+    assert call(_img(), _img(0x200000), _params(), out=0) == _lib.OFV_ERR_INVALID_ARG
+    big0 = _img(0x100000, w=2048, h=1024)
+    big1 = _img(0x40000000, w=2048, h=1024)
+    assert call(big0, big1, _params(), out=0x80000000) == _lib.OFV_ERR_CAPACITY
+    assert b"static scratch" in lib.ofv_last_error(None)
+    fit0 = _img(0x100000, w=1280, h=1024)
+    fit1 = _img(0x40000000, w=1280, h=1024)
+    monkeypatch.setenv("OFV_FAULT_INJECT", "launch")
+    assert call(fit0, fit1, _params(), out=0x80000000) == _lib.OFV_ERR_DEVICE
+    assert b"injected" in lib.ofv_last_error(None)
