@@ -85,7 +85,8 @@ typedef struct {
   float reg_rel;         /* >= 0, typical 1e-3: damping lambda = reg_rel * trace(A) + reg_abs */
   float reg_abs;         /* >= 0, typical 1e-9; reg_rel = reg_abs = 0 gives NaN on textureless windows */
   int32_t storage;       /* ofv_storage */
-  uint32_t flags;        /* 0 or OFV_FLAG_FORWARD_ADDITIVE */
+  uint32_t flags;        /* 0 or an OR of OFV_FLAG_FORWARD_ADDITIVE, OFV_FLAG_INCREMENT_UPDATE,
+                            OFV_FLAG_NO_FP64_FALLBACK */
 } ofv_params;
 
 /* params.flags: the forward-additive Lucas-Kanade estimator that the paper
@@ -97,6 +98,25 @@ typedef struct {
  * levels one pixel thin), ignores the decomposition choice, and has no
  * adjoint (ofv_compute_flow_backward returns OFV_ERR_UNSUPPORTED). */
 #define OFV_FLAG_FORWARD_ADDITIVE 1u
+
+/* params.flags: the increment form of the Gauss-Newton update, the
+ * alternative to the consistent form of our reading of Eq. of_symmetric: the
+ * residual of every pixel k of the window N(m) is linearised about the
+ * window's own V(m) rather than about the V(k) its warps used, which gives
+ *   (A + lam I) dV = sum_{k in N(m)} G(k) (-T(k)),   V'(m) = V(m) + dV
+ * (A, lam and the warps as without the flag).  Both forms agree where the
+ * field is uniform over the window and at V = 0.  Combined with
+ * OFV_FLAG_FORWARD_ADDITIVE it is the textbook forward-additive
+ * Lucas-Kanade step on every window.  Runs on the same kernels as
+ * OFV_FLAG_FORWARD_ADDITIVE (16 x 16 tiles, the strip march for levels one
+ * pixel thin) and has no adjoint. */
+#define OFV_FLAG_INCREMENT_UPDATE 2u
+
+/* params.flags: switch off the float64 fallback of the 2x2 solve (by
+ * default, windows whose damped normal matrix has q = 4 det / trace^2 below
+ * 1e-2 have the determinant and the solution recomputed in float64 from the
+ * float32 sums).  For A/B comparisons of the fallback's effect. */
+#define OFV_FLAG_NO_FP64_FALLBACK 4u
 
 /* Fill *p with the defaults: 3 levels, KR 4, IT 3, NR 1, eps 1e-4,
  * reg_rel 1e-3, reg_abs 1e-9, F32 storage.  p == NULL is ignored. */

@@ -43,12 +43,22 @@ restated where it is used):
      gradient of the warped second image, so the step keeps the same normal
      equations with S = W1 = P1(k + V), T = W1 - P0(k); V is then anchored
      at the pixels of frame 0 instead of the midpoint.
+ R25 The increment form of the update (update="increment"), the alternative
+     to R5: every residual of the window N(m) is linearised about the
+     window's own V(m), so G(k) . dV = -T(k) with dV = V - V(m), and
+     (A + lam I) dV = sum G (-T), V'(m) = V(m) + dV.  It coincides with R5
+     where V is uniform over the window and at V = 0; with the warps of R24
+     it is the classic forward-additive Lucas-Kanade step per window.
 
 Besides the method itself, compute_flow can round every image plane (the
 normalised frames and each REDUCE output) to a storage type, leaving all
 arithmetic in float64.  That is not part of the paper: it gives the error
 that storing the planes in float32 / float16 / bfloat16 causes by itself,
-the floor against which a reduced-precision implementation is judged.
+the floor against which a reduced-precision implementation is judged.  For
+the same purpose it can run every step in float32 arithmetic instead
+(arith="f32"): on inputs where the iteration amplifies rounding (windows
+whose normal matrix is nearly singular) that is the floor of any float32
+implementation.  Both options are diagnostics; the reference is float64.
 """
 from __future__ import annotations
 
@@ -156,10 +166,10 @@ _PLANE_TYPES = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat
 
 
 def round_plane(p: torch.Tensor, plane_round: Optional[str]) -> torch.Tensor:
-    """p rounded to nearest in the storage type (ties to even), back in float64."""
+    """p rounded to nearest in the storage type (ties to even), back in p's own type."""
     if plane_round is None:
         return p
-    return p.to(_PLANE_TYPES[plane_round]).to(DT)
+    return p.to(_PLANE_TYPES[plane_round]).to(p.dtype)
 
 
 def pyramid(p0: torch.Tensor, levels: int, plane_round: Optional[str] = None) -> List[torch.Tensor]:
@@ -222,7 +232,7 @@ def warp_terms(p0: torch.Tensor, p1: torch.Tensor, u: torch.Tensor, v: torch.Ten
     Returns S = (W0 + W1) / 2 and T = W1 - W0 at every pixel k (R6, R7).
     """
     h, w = p0.shape
-    yy, xx = torch.meshgrid(torch.arange(h, dtype=DT), torch.arange(w, dtype=DT), indexing="ij")
+    yy, xx = torch.meshgrid(torch.arange(h, dtype=p0.dtype), torch.arange(w, dtype=p0.dtype), indexing="ij")
     w0 = bilinear(p0, xx - 0.5 * u, yy - 0.5 * v)
     w1 = bilinear(p1, xx + 0.5 * u, yy + 0.5 * v)
     return 0.5 * (w0 + w1), w1 - w0
@@ -231,14 +241,20 @@ def warp_terms(p0: torch.Tensor, p1: torch.Tensor, u: torch.Tensor, v: torch.Ten
 def warp_terms_forward(p0: torch.Tensor, p1: torch.Tensor, u: torch.Tensor, v: torch.Tensor):
     """Forward-additive warps (R24): W1 = P1(k + V); S = W1 and T = W1 - P0(k)."""
     h, w = p0.shape
-    yy, xx = torch.meshgrid(torch.arange(h, dtype=DT), torch.arange(w, dtype=DT), indexing="ij")
+    yy, xx = torch.meshgrid(torch.arange(h, dtype=p0.dtype), torch.arange(w, dtype=p0.dtype), indexing="ij")
     w1 = bilinear(p1, xx + u, yy + v)
     return w1, w1 - p0
 
 
+def increment_step(a, d, sxy, det, sxb, syb, u, v):
+    """R25: the damped step dV = (A + lam I)^-1 c by Cramer's rule (a, d the damped diagonal,
+    det its determinant, c = (sxb, syb) the sums of G (-T)), added to the current V(m)."""
+    return u + (d * sxb - sxy * syb) / det, v + (a * syb - sxy * sxb) / det
+
+
 def gn_iteration(p0: torch.Tensor, p1: torch.Tensor, u: torch.Tensor, v: torch.Tensor,
                  kr: int, reg_rel: float, reg_abs: float, terms: Optional[list] = None,
-                 estimator: str = "symmetric"):
+                 estimator: str = "symmetric", update: str = "consistent"):
     """One Jacobi Gauss-Newton update of the flow at every pixel (R5).
 
     At each pixel k the residual I0(k - V/2) - I1(k + V/2) of Eq. (of_symmetric)
@@ -249,6 +265,7 @@ def gn_iteration(p0: torch.Tensor, p1: torch.Tensor, u: torch.Tensor, v: torch.T
     With damping lam = reg_rel (Sxx + Syy) + reg_abs towards the current V(m),
     (A + lam I) V'(m) = c + lam V(m) is solved by Cramer's rule.
     estimator="forward_additive" takes the warps of R24 instead.
+    update="increment" (R25): b = -T, (A + lam I) dV = c, V'(m) = V(m) + dV.
     """
     if estimator == "symmetric":
         s, t = warp_terms(p0, p1, u, v)
@@ -257,7 +274,12 @@ def gn_iteration(p0: torch.Tensor, p1: torch.Tensor, u: torch.Tensor, v: torch.T
     else:
         raise ValueError(f"unknown estimator {estimator!r}")
     gx, gy = central_gradient(s)
-    b = gx * u + gy * v - t
+    if update == "consistent":
+        b = gx * u + gy * v - t
+    elif update == "increment":
+        b = -t
+    else:
+        raise ValueError(f"unknown update {update!r}")
     sxx = window_sum(gx * gx, kr)
     sxy = window_sum(gx * gy, kr)
     syy = window_sum(gy * gy, kr)
@@ -267,10 +289,13 @@ def gn_iteration(p0: torch.Tensor, p1: torch.Tensor, u: torch.Tensor, v: torch.T
     a = sxx + lam
     d = syy + lam
     det = a * d - sxy * sxy
-    r1 = sxb + lam * u
-    r2 = syb + lam * v
-    un = (d * r1 - sxy * r2) / det
-    vn = (a * r2 - sxy * r1) / det
+    if update == "consistent":
+        r1 = sxb + lam * u
+        r2 = syb + lam * v
+        un = (d * r1 - sxy * r2) / det
+        vn = (a * r2 - sxy * r1) / det
+    else:
+        un, vn = increment_step(a, d, sxy, det, sxb, syb, u, v)
     if terms is not None:
         terms.append(IterationTerms(s, t, gx, gy, b, {"sxx": sxx, "sxy": sxy, "syy": syy,
                                                        "sxb": sxb, "syb": syb}))
@@ -283,7 +308,7 @@ def gn_iteration(p0: torch.Tensor, p1: torch.Tensor, u: torch.Tensor, v: torch.T
 
 def upsample(uc: torch.Tensor, vc: torch.Tensor, h: int, w: int):
     """V_fine(X, Y) = 2 * bilinear(V_coarse, X / 2, Y / 2) on an h x w grid (R8)."""
-    yy, xx = torch.meshgrid(torch.arange(h, dtype=DT), torch.arange(w, dtype=DT), indexing="ij")
+    yy, xx = torch.meshgrid(torch.arange(h, dtype=uc.dtype), torch.arange(w, dtype=uc.dtype), indexing="ij")
     return 2.0 * bilinear(uc, 0.5 * xx, 0.5 * yy), 2.0 * bilinear(vc, 0.5 * xx, 0.5 * yy)
 
 
@@ -309,16 +334,19 @@ class Trace:
 
 
 def compute_flow(frame0, frame1, params: Dict, bit_depth0: int = 8, bit_depth1: Optional[int] = None,
-                 flow_init=None, trace: Optional[Trace] = None, plane_round: Optional[str] = None):
+                 flow_init=None, trace: Optional[Trace] = None, plane_round: Optional[str] = None,
+                 arith: Optional[str] = None):
     """Dense displacement field (u, v) in px/frame at full resolution.
 
     params: num_levels (PSL + 1), kernel_radius (KR), iterations (IT),
-    norm_radius (NR), and optionally norm_eps, reg_rel, reg_abs and
-    estimator ("symmetric", the paper's, or "forward_additive", R24).
+    norm_radius (NR), and optionally norm_eps, reg_rel, reg_abs,
+    estimator ("symmetric", the paper's, or "forward_additive", R24) and
+    update ("consistent", R5, or "increment", R25).
     Returns a float64 tensor [2, H, W]; u along +x (columns), v along +y
     (rows), mapping frame0 to frame1, defined at the midpoint.
     plane_round ("f32", "f16", "bf16" or None) rounds every image plane to
-    that storage type (not part of the method; see the module docstring).
+    that storage type; arith="f32" runs every step in float32 (both not part
+    of the method; see the module docstring).
     """
     if bit_depth1 is None:
         bit_depth1 = bit_depth0
@@ -329,8 +357,9 @@ def compute_flow(frame0, frame1, params: Dict, bit_depth0: int = 8, bit_depth1: 
     it = int(p["iterations"])
     nr = int(p["norm_radius"])
     # step 1: normalisation of each frame, independently
-    n0 = normalize(intensity(frame0, bit_depth0), nr, p["norm_eps"])
-    n1 = normalize(intensity(frame1, bit_depth1), nr, p["norm_eps"])
+    dt = torch.float32 if arith == "f32" else DT
+    n0 = normalize(intensity(frame0, bit_depth0).to(dt), nr, p["norm_eps"])
+    n1 = normalize(intensity(frame1, bit_depth1).to(dt), nr, p["norm_eps"])
     # step 2: pyramids
     pyr0 = pyramid(n0, levels, plane_round)
     pyr1 = pyramid(n1, levels, plane_round)
@@ -339,10 +368,10 @@ def compute_flow(frame0, frame1, params: Dict, bit_depth0: int = 8, bit_depth1: 
     # initial flow at the coarsest level
     hc, wc = pyr0[-1].shape
     if flow_init is None:
-        u = torch.zeros((hc, wc), dtype=DT)
-        v = torch.zeros((hc, wc), dtype=DT)
+        u = torch.zeros((hc, wc), dtype=dt)
+        v = torch.zeros((hc, wc), dtype=dt)
     else:
-        fi = _t(flow_init)
+        fi = _t(flow_init).to(dt)
         u, v = fi[0], fi[1]
         for _ in range(levels - 1):
             u, v = restrict_flow(u, v)
@@ -355,11 +384,11 @@ def compute_flow(frame0, frame1, params: Dict, bit_depth0: int = 8, bit_depth1: 
             trace.flow_in[lev] = (u, v)
         for k in range(it):
             u, v = gn_iteration(pyr0[lev], pyr1[lev], u, v, kr, p["reg_rel"], p["reg_abs"],
-                                estimator=p.get("estimator", "symmetric"))
+                                estimator=p.get("estimator", "symmetric"), update=p.get("update", "consistent"))
             if trace is not None:
                 trace.iterates[(lev, k)] = (u, v)
     # step 6: full-resolution field
-    return torch.stack([u, v])
+    return torch.stack([u, v]).to(DT)
 
 
 def endpoint_error(flow, gt) -> torch.Tensor:

@@ -20,6 +20,8 @@ STORE = {"f32": 0, "f16": 1, "bf16": 2}
 FLOW_IN_ZERO, FLOW_IN_DIRECT, FLOW_IN_UPSAMPLE = 0, 1, 2
 MAX_LEVELS = 16
 FLAG_FORWARD_ADDITIVE = 1
+FLAG_INCREMENT_UPDATE = 2
+FLAG_NO_FP64_FALLBACK = 4
 MAX_KERNEL_RADIUS = 12
 MAX_NORM_RADIUS = 16
 GN_VARIANTS = {"auto": -1, "march": 0, "tile64x32": 1, "tile64x16": 2, "tile32x16": 3, "tile16x16": 4,

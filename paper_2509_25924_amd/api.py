@@ -165,6 +165,13 @@ def params_struct(params: Dict) -> OfvParams:
         raise ValueError(f"unknown estimator {est!r}")
     if est == "forward_additive":
         p.flags |= _lib.FLAG_FORWARD_ADDITIVE
+    upd = params.get("update", "consistent")
+    if upd not in ("consistent", "increment"):
+        raise ValueError(f"unknown update {upd!r}")
+    if upd == "increment":
+        p.flags |= _lib.FLAG_INCREMENT_UPDATE
+    if not params.get("fp64_fallback", True):
+        p.flags |= _lib.FLAG_NO_FP64_FALLBACK
     return p
 
 

@@ -168,7 +168,8 @@ ofv_status check_params(ofv_ctx* h, const ofv_params* p) {
     return fail(h, OFV_ERR_INVALID_ARG, "reg_rel and reg_abs must be finite and >= 0");
   if (p->storage < OFV_STORE_F32 || p->storage > OFV_STORE_BF16)
     return fail(h, OFV_ERR_INVALID_ARG, "unknown storage %d", p->storage);
-  if (p->flags & ~OFV_FLAG_FORWARD_ADDITIVE) return fail(h, OFV_ERR_INVALID_ARG, "unknown flags 0x%x", p->flags);
+  if (p->flags & ~(OFV_FLAG_FORWARD_ADDITIVE | OFV_FLAG_INCREMENT_UPDATE | OFV_FLAG_NO_FP64_FALLBACK))
+    return fail(h, OFV_ERR_INVALID_ARG, "unknown flags 0x%x", p->flags);
   return OFV_OK;
 }
 
@@ -298,7 +299,12 @@ ofv_status run_pipeline(ofv_ctx* h, int n, PairPlan* pp, const ofv_params* p, fl
   // any run rewrites the slabs of the slots it uses: a retained streaming frame is gone
   h->stream_valid = false;
   const int L = p->num_levels;
-  const bool fa = (p->flags & OFV_FLAG_FORWARD_ADDITIVE) != 0;
+  // estimator variants other than the symmetric estimator's consistent update
+  // run on the generic kernels, which read them at run time
+  const bool generic = (p->flags & (OFV_FLAG_FORWARD_ADDITIVE | OFV_FLAG_INCREMENT_UPDATE)) != 0;
+  const uint32_t est = ((p->flags & OFV_FLAG_FORWARD_ADDITIVE) ? EST_FORWARD_ADDITIVE : 0u) |
+                       ((p->flags & OFV_FLAG_INCREMENT_UPDATE) ? EST_INCREMENT : 0u) |
+                       ((p->flags & OFV_FLAG_NO_FP64_FALLBACK) ? EST_NO_FP64 : 0u);
   const int kr = p->kernel_radius;
   const int it = p->iterations;
   const int st = p->storage;
@@ -447,6 +453,7 @@ ofv_status run_pipeline(ofv_ctx* h, int n, PairPlan* pp, const ofv_params* p, fl
       GnArgs ga{};
       ga.reg_rel = p->reg_rel;
       ga.reg_abs = p->reg_abs;
+      ga.est = est;
       std::vector<int> next(n);
       // the input-flow mode is a compile-time property of the kernel: group pairs by it
       auto mode_of = [&](int j) {
@@ -471,7 +478,7 @@ ofv_status run_pipeline(ofv_ctx* h, int n, PairPlan* pp, const ofv_params* p, fl
         int64_t pixels = 0;
         for (int j : group) pixels += static_cast<int64_t>(pp[j].lw[l]) * pp[j].lh[l];
         pick_gn(h, key, strips, rows_max, pixels, thin, variant, tile_h);
-        if (fa && variant != GN_MARCH) variant = GN_TILE_16x16;   // the forward-additive tiles
+        if (generic && variant != GN_MARCH) variant = GN_TILE_16x16;   // the generic estimator's tiles
         gn_tile_dims(variant, kr, tile_h, tw, th);
         ga.tile_h = tile_h;
         auto fill = [&](int gi, GnJob& J) {
@@ -536,7 +543,7 @@ ofv_status run_pipeline(ofv_ctx* h, int n, PairPlan* pp, const ofv_params* p, fl
           (void)hipEventRecord(ev0, s);
         }
         ofv_status r = run_chunked(h, static_cast<int>(group.size()), ga, fill,
-                                   [&](const GnArgs& a, int b) { return launch_gn(a, kr, st, mode, variant, b, s, fa); },
+                                   [&](const GnArgs& a, int b) { return launch_gn(a, kr, st, mode, variant, b, s, generic); },
                                    "gauss-newton iteration");
         if (r != OFV_OK) return r;
         if (h->capture) {
@@ -873,8 +880,8 @@ ofv_status ofv_compute_flow_backward(ofv_handle h, const ofv_image* frame0, cons
   if (check_handle(h) != OFV_OK) return OFV_ERR_INVALID_ARG;
   ofv_status r = check_params(h, params);
   if (r != OFV_OK) return r;
-  if (params->flags & OFV_FLAG_FORWARD_ADDITIVE)
-    return fail(h, OFV_ERR_UNSUPPORTED, "the adjoint covers the symmetric estimator only");
+  if (params->flags & (OFV_FLAG_FORWARD_ADDITIVE | OFV_FLAG_INCREMENT_UPDATE))
+    return fail(h, OFV_ERR_UNSUPPORTED, "the adjoint covers the symmetric estimator's consistent update only");
   r = check_image(h, frame0, "frame0");
   if (r != OFV_OK) return r;
   r = check_image(h, frame1, "frame1");
@@ -1267,7 +1274,7 @@ ofv_status ofv_autotune(ofv_handle h, const ofv_image* frame0, const ofv_image* 
                         float* flow_out, int repeats) {
   if (check_handle(h) != OFV_OK) return OFV_ERR_INVALID_ARG;
   if (repeats < 1 || repeats > 1000) return fail(h, OFV_ERR_INVALID_ARG, "repeats %d outside 1..1000", repeats);
-  if (params && (params->flags & OFV_FLAG_FORWARD_ADDITIVE))
+  if (params && (params->flags & (OFV_FLAG_FORWARD_ADDITIVE | OFV_FLAG_INCREMENT_UPDATE)))
     return fail(h, OFV_ERR_UNSUPPORTED, "the autotuner times the symmetric estimator's decompositions");
   // validate exactly like a compute call (the validation-only handle stops there)
   ofv_status r = compute_common(h, 1, frame0, frame1, params, nullptr, &flow_out);

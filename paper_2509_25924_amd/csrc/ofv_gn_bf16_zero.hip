@@ -3,8 +3,8 @@
 
 namespace ofv {
 
-hipError_t launch_gn_bf16_zero(const GnArgs& a, int kr, int nblocks, hipStream_t s, bool fa) {
-  return launch_gn_typed<FLOW_ZERO, bf16_t>(a, kr, nblocks, s, fa);
+hipError_t launch_gn_bf16_zero(const GnArgs& a, int kr, int nblocks, hipStream_t s, bool generic) {
+  return launch_gn_typed<FLOW_ZERO, bf16_t>(a, kr, nblocks, s, generic);
 }
 
 }  // namespace ofv

@@ -3,8 +3,8 @@
 
 namespace ofv {
 
-hipError_t launch_gn_f16_upsample(const GnArgs& a, int kr, int nblocks, hipStream_t s, bool fa) {
-  return launch_gn_typed<FLOW_UPSAMPLE, _Float16>(a, kr, nblocks, s, fa);
+hipError_t launch_gn_f16_upsample(const GnArgs& a, int kr, int nblocks, hipStream_t s, bool generic) {
+  return launch_gn_typed<FLOW_UPSAMPLE, _Float16>(a, kr, nblocks, s, generic);
 }
 
 }  // namespace ofv

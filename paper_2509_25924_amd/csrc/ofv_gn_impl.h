@@ -139,24 +139,23 @@ __device__ __forceinline__ void tap4(const TS* p, int64_t pitch, int w, int h, f
 }
 
 // Symmetric warps of Eq. (of_symmetric): P0 at k - V/2 and P1 at k + V/2,
-// S the mean of the two.  FA (the forward-additive estimator): P0 at k
+// S the mean of the two.  fa (the forward-additive estimator): P0 at k
 // itself (integer position: the interpolation weights are exactly 0) and
 // P1 at k + V, S the warped P1.
-template <bool FA, typename TS>
-__device__ __forceinline__ void warp_issue(const GnCtx<TS>& c, int x, int y, float u, float v, WarpReq& g) {
+template <typename TS>
+__device__ __forceinline__ void warp_issue(const GnCtx<TS>& c, int x, int y, float u, float v, WarpReq& g, bool fa) {
   const float fx = static_cast<float>(x);
   const float fy = static_cast<float>(y);
-  const float hu = FA ? 0.0f : 0.5f * u;
-  const float hv = FA ? 0.0f : 0.5f * v;
+  const float hu = fa ? 0.0f : 0.5f * u;
+  const float hv = fa ? 0.0f : 0.5f * v;
   tap4(c.p0, c.ip, c.w, c.h, fx - hu, fy - hv, g.a00, g.a01, g.a10, g.a11, g.ax0, g.ay0);
-  tap4(c.p1, c.ip, c.w, c.h, fx + (FA ? u : hu), fy + (FA ? v : hv), g.b00, g.b01, g.b10, g.b11, g.ax1, g.ay1);
+  tap4(c.p1, c.ip, c.w, c.h, fx + (fa ? u : hu), fy + (fa ? v : hv), g.b00, g.b01, g.b10, g.b11, g.ax1, g.ay1);
 }
 
-template <bool FA>
-__device__ __forceinline__ void warp_finish(const WarpReq& g, bool valid, float& s, float& t) {
+__device__ __forceinline__ void warp_finish(const WarpReq& g, bool valid, float& s, float& t, bool fa) {
   const float w0 = lerp4(g.a00, g.a01, g.a10, g.a11, g.ax0, g.ay0);
   const float w1 = lerp4(g.b00, g.b01, g.b10, g.b11, g.ax1, g.ay1);
-  s = valid ? (FA ? w1 : 0.5f * (w0 + w1)) : 0.0f;
+  s = valid ? (fa ? w1 : 0.5f * (w0 + w1)) : 0.0f;
   t = valid ? w1 - w0 : 0.0f;
 }
 
@@ -180,13 +179,19 @@ __device__ __forceinline__ float wave_prefix(float x) {
   return x;
 }
 
-template <int KR, int MODE, typename TS, bool FA = false>
+// GEN: the estimator variant is read from a.est at run time (forward-additive
+// warps, increment-form update); otherwise the symmetric estimator's
+// consistent update is compiled in.
+template <int KR, int MODE, typename TS, bool GEN = false>
 __global__ __launch_bounds__(kGnThreads) void gn_kernel(const GnArgs a) {
   constexpr int NWIN = 2 * KR + 1;
   constexpr int TX = kGnThreads - 2 * KR - 2;
   __shared__ float s_row[2][kGnThreads];
   __shared__ float p_row[2][5][kGnThreads];
 
+  const bool fwd = GEN && (a.est & EST_FORWARD_ADDITIVE) != 0;
+  const bool inc = GEN && (a.est & EST_INCREMENT) != 0;
+  const bool no_fp64 = (a.est & EST_NO_FP64) != 0;
   const int jb = find_job(a, blockIdx.x);
   const GnJob& J = a.job[jb];
   GnCtx<TS> c;
@@ -242,13 +247,13 @@ __global__ __launch_bounds__(kGnThreads) void gn_kernel(const GnArgs a) {
     flow_finish<MODE>(fb, row_ok(r0 + 1), u_0, v_0);
     flow_finish<MODE>(fc, row_ok(r0 + 2), u_1, v_1);
     WarpReq ga, gb;
-    warp_issue<FA>(c, cc, rc(r0), ua, va, ga);
-    warp_issue<FA>(c, cc, rc(r0 + 1), u_0, v_0, gb);
-    warp_issue<FA>(c, cc, rc(r0 + 2), u_1, v_1, g1);
+    warp_issue(c, cc, rc(r0), ua, va, ga, fwd);
+    warp_issue(c, cc, rc(r0 + 1), u_0, v_0, gb, fwd);
+    warp_issue(c, cc, rc(r0 + 2), u_1, v_1, g1, fwd);
     flow_issue<MODE>(c, cc, rc(r0 + 4), f3);
     float tdummy;
-    warp_finish<FA>(ga, row_ok(r0), s_m, tdummy);
-    warp_finish<FA>(gb, row_ok(r0 + 1), s_0, t_0);
+    warp_finish(ga, row_ok(r0), s_m, tdummy, fwd);
+    warp_finish(gb, row_ok(r0 + 1), s_0, t_0, fwd);
   }
   s_row[0][tid] = s_0;
   __syncthreads();
@@ -276,9 +281,9 @@ __global__ __launch_bounds__(kGnThreads) void gn_kernel(const GnArgs a) {
         // pipeline: S/T of row pr+1 (gathers issued last step); gathers of
         // row pr+2 (flow requested two steps ago); flow of row pr+4.
         float s_p, t_p;
-        warp_finish<FA>(g1, row_ok(pr + 1), s_p, t_p);
+        warp_finish(g1, row_ok(pr + 1), s_p, t_p, fwd);
         flow_finish<MODE>(f2, row_ok(pr + 2), u_2, v_2);
-        warp_issue<FA>(c, cc, rc(pr + 2), u_2, v_2, g1);
+        warp_issue(c, cc, rc(pr + 2), u_2, v_2, g1, fwd);
         f2 = f3;
         flow_issue<MODE>(c, cc, rc(pr + 4), f3);
         // gradient of S at (col, pr), indices clamped to the level
@@ -288,7 +293,7 @@ __global__ __launch_bounds__(kGnThreads) void gn_kernel(const GnArgs a) {
         const float sd = pr + 1 < H ? s_p : s_0;
         const float gx = 0.5f * (sr - sl);
         const float gy = 0.5f * (sd - su);
-        const float b = fmaf(gx, u_0, fmaf(gy, v_0, -t_0));
+        const float b = inc ? -t_0 : fmaf(gx, u_0, fmaf(gy, v_0, -t_0));
         const bool valid = prod_lane && row_ok(pr);
         float pq[5];
         pq[0] = valid ? gx * gx : 0.0f;
@@ -319,7 +324,7 @@ __global__ __launch_bounds__(kGnThreads) void gn_kernel(const GnArgs a) {
             const float um = ru[(k + KR + 1) % NWIN];
             const float vm = rv[(k + KR + 1) % NWIN];
             float un, vn;
-            solve2x2(acc[0], acc[1], acc[2], acc[3], acc[4], um, vm, a.reg_rel, a.reg_abs, un, vn);
+            solve2x2(acc[0], acc[1], acc[2], acc[3], acc[4], um, vm, a.reg_rel, a.reg_abs, un, vn, inc, no_fp64);
             const int64_t o = static_cast<int64_t>(orow) * J.out_pitch + col;
             J.out_u[o] = un;
             J.out_v[o] = vn;
@@ -341,13 +346,13 @@ __global__ __launch_bounds__(kGnThreads) void gn_kernel(const GnArgs a) {
 }
 
 template <int MODE, typename TS>
-hipError_t launch_gn_typed(const GnArgs& a, int kr, int nblocks, hipStream_t s, bool fa) {
+hipError_t launch_gn_typed(const GnArgs& a, int kr, int nblocks, hipStream_t s, bool generic) {
   const dim3 grid(nblocks);
   const dim3 block(kGnThreads);
   switch (kr) {
 #define OFV_GN_CASE(R)                                                                   \
   case R:                                                                                \
-    if (fa) hipLaunchKernelGGL((gn_kernel<R, MODE, TS, true>), grid, block, 0, s, a);     \
+    if (generic) hipLaunchKernelGGL((gn_kernel<R, MODE, TS, true>), grid, block, 0, s, a); \
     else hipLaunchKernelGGL((gn_kernel<R, MODE, TS, false>), grid, block, 0, s, a);       \
     break;
     OFV_GN_CASE(1)

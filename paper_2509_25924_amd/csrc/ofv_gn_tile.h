@@ -126,9 +126,11 @@ struct TileOcc {
   static constexpr int value = fit < 1 ? 1 : (fit > 4 ? 4 : fit);
 };
 
-// FA: the forward-additive estimator instead of the symmetric objective
-// (P0 read at the pixel itself, P1 warped by the full V, S = the warped P1).
-template <int KR, int MODE, typename TS, int TX, int TY, int SL, int SLV, int NT, bool FA = false>
+// GEN: the estimator variant is read from a.est at run time (forward-additive
+// warps: P0 read at the pixel itself, P1 warped by the full V, S = the warped
+// P1; increment-form update: b = -T and V' = V(m) + dV); otherwise the
+// symmetric estimator's consistent update is compiled in.
+template <int KR, int MODE, typename TS, int TX, int TY, int SL, int SLV, int NT, bool GEN = false>
 __global__ __launch_bounds__(NT)
 __attribute__((amdgpu_waves_per_eu(TileOcc<KR, TX, TY, NT>::value, TileOcc<KR, TX, TY, NT>::value)))
 void gn_tile_kernel(const GnArgs a) {
@@ -150,6 +152,9 @@ void gn_tile_kernel(const GnArgs a) {
   constexpr int CHF = (REGS - 48 - 3 * NA) / PER;
   constexpr int CH = CHF < 1 ? 1 : (CHF > NA ? NA : CHF);
   extern __shared__ float lds[];
+  const bool fa = GEN && (a.est & EST_FORWARD_ADDITIVE) != 0;
+  const bool inc = GEN && (a.est & EST_INCREMENT) != 0;
+  const bool no_fp64 = (a.est & EST_NO_FP64) != 0;
   float* sS = lds;           // EY x LP
   float* sP = lds + PL;      // 5 planes: products, then horizontal sums (ext coordinates)
 
@@ -261,10 +266,10 @@ void gn_tile_kernel(const GnArgs a) {
         // symmetric: P0 at k - V/2, P1 at k + V/2; forward-additive: P0 at k
         // (through the same interpolation, so that equal planes give T = 0
         // exactly), P1 at k + V
-        const float hu = FA ? 0.0f : 0.5f * uu[k];
-        const float hv = FA ? 0.0f : 0.5f * vv2[k];
+        const float hu = fa ? 0.0f : 0.5f * uu[k];
+        const float hv = fa ? 0.0f : 0.5f * vv2[k];
         const BilTap t0 = bil_setup(fx[k] - hu, fy[k] - hv, wm1, hm1, wm2, hm2, uip);
-        const BilTap t1 = bil_setup(fx[k] + (FA ? uu[k] : hu), fy[k] + (FA ? vv2[k] : hv), wm1, hm1, wm2, hm2, uip);
+        const BilTap t1 = bil_setup(fx[k] + (fa ? uu[k] : hu), fy[k] + (fa ? vv2[k] : hv), wm1, hm1, wm2, hm2, uip);
         a0x[k] = t0.ax;
         a0y[k] = t0.ay;
         a1x[k] = t1.ax;
@@ -284,7 +289,7 @@ void gn_tile_kernel(const GnArgs a) {
           kT[k0 + k] = w1 - w0;
           kU[k0 + k] = uu[k];
           kV[k0 + k] = vv2[k];
-          if (tid + NT * (k0 + k) < NE) sS[oo[k]] = FA ? w1 : 0.5f * (w0 + w1);
+          if (tid + NT * (k0 + k) < NE) sS[oo[k]] = fa ? w1 : 0.5f * (w0 + w1);
         }
       }
     }
@@ -318,7 +323,7 @@ void gn_tile_kernel(const GnArgs a) {
           const bool valid = kF & (2u << (2 * (k0 + k)));
           const float gx = valid ? 0.5f * (sxp[k] - sxm[k]) : 0.0f;
           const float gy = valid ? 0.5f * (syp[k] - sym[k]) : 0.0f;
-          const float b = fmaf(gx, kU[k0 + k], fmaf(gy, kV[k0 + k], -kT[k0 + k]));
+          const float b = inc ? -kT[k0 + k] : fmaf(gx, kU[k0 + k], fmaf(gy, kV[k0 + k], -kT[k0 + k]));
           if (kF & (1u << (2 * (k0 + k)))) {
             const int o = kO[k0 + k];
             sP[o] = gx * gx;
@@ -449,7 +454,7 @@ void gn_tile_kernel(const GnArgs a) {
           if (gy < H) {
             float un, vn;
             solve2x2(acc[0], acc[1], acc[2], acc[3], acc[4], um[k - 2 * KR], vm[k - 2 * KR], a.reg_rel, a.reg_abs,
-                     un, vn);
+                     un, vn, inc, no_fp64);
             const uint32_t oo =
                 (__umul24(static_cast<uint32_t>(gy), static_cast<uint32_t>(J.out_pitch)) + static_cast<uint32_t>(gx)) * 4u;
             __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(un), wu, static_cast<int>(oo), 0, 0);
@@ -461,10 +466,10 @@ void gn_tile_kernel(const GnArgs a) {
   }
 }
 
-template <int KR, int MODE, typename TS, int TX, int TY, int SL, int SLV, int NT, bool FA = false>
+template <int KR, int MODE, typename TS, int TX, int TY, int SL, int SLV, int NT, bool GEN = false>
 hipError_t launch_gn_tile_cfg(const GnArgs& a, int nblocks, hipStream_t s) {
   constexpr size_t lds = sizeof(float) * TileLds<KR, TX, TY, NT>::FLOATS;
-  auto kern = gn_tile_kernel<KR, MODE, TS, TX, TY, SL, SLV, NT, FA>;
+  auto kern = gn_tile_kernel<KR, MODE, TS, TX, TY, SL, SLV, NT, GEN>;
   // dynamic LDS above 64 KiB must be enabled once per kernel (thread-safe static init)
   static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                                      hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -488,12 +493,12 @@ hipError_t launch_gn_tile_cfg(const GnArgs& a, int nblocks, hipStream_t s) {
 // 2 rows), two pixels per lane in A1 for mid-size levels.
 // The small tiles spread coarse levels over many compute units: there the
 // launch is bound by the instruction latency of few waves, not by traffic.
-// fa (forward-additive estimator): 16 x 16 tiles whatever the variant.
+// generic (estimator variants read from a.est): 16 x 16 tiles whatever the variant.
 template <int MODE, typename TS>
-hipError_t launch_gn_tile_typed(const GnArgs& a, int kr, int variant, int nblocks, hipStream_t s, bool fa) {
+hipError_t launch_gn_tile_typed(const GnArgs& a, int kr, int variant, int nblocks, hipStream_t s, bool generic) {
 #define OFV_GNT_CASE(R)                                                                             \
   case R:                                                                                           \
-    if (fa) return launch_gn_tile_cfg<R, MODE, TS, 16, 16, 4, 1, 256, true>(a, nblocks, s);          \
+    if (generic) return launch_gn_tile_cfg<R, MODE, TS, 16, 16, 4, 1, 256, true>(a, nblocks, s);     \
     switch (variant) {                                                                              \
       case GN_TILE_64x32: return launch_gn_tile_cfg<R, MODE, TS, 64, 32, 8, 4, 512>(a, nblocks, s);  \
       case GN_TILE_64x16: return launch_gn_tile_cfg<R, MODE, TS, 64, 16, 8, 4, 256>(a, nblocks, s);  \

@@ -3,8 +3,8 @@
 
 namespace ofv {
 
-hipError_t launch_gnt_bf16_upsample(const GnArgs& a, int kr, int variant, int nblocks, hipStream_t s, bool fa) {
-  return launch_gn_tile_typed<FLOW_UPSAMPLE, bf16_t>(a, kr, variant, nblocks, s, fa);
+hipError_t launch_gnt_bf16_upsample(const GnArgs& a, int kr, int variant, int nblocks, hipStream_t s, bool generic) {
+  return launch_gn_tile_typed<FLOW_UPSAMPLE, bf16_t>(a, kr, variant, nblocks, s, generic);
 }
 
 }  // namespace ofv

@@ -131,10 +131,16 @@ struct GnJob {
   int mode;            // FlowIn (equal for all jobs of a launch)
   int tile_start;
 };
+// GnArgs::est: estimator variants, read at run time by the generic kernels
+// (forward-additive warps, increment-form update), and the switch of the
+// solve's float64 fallback, read by every kernel.
+enum GnEst : uint32_t { EST_FORWARD_ADDITIVE = 1u, EST_INCREMENT = 2u, EST_NO_FP64 = 4u };
 struct GnArgs {
   int njobs;
   int tile_h;          // output rows per workgroup
   float reg_rel, reg_abs;
+  uint32_t est;        // GnEst bits
+  int pad_;
   GnJob job[kMaxJobs];
 };
 
@@ -183,9 +189,10 @@ hipError_t launch_reduce_multi(const ReduceMArgs& a, int nlev, bool small, int n
 hipError_t launch_upsample(const UpsampleArgs& a, hipStream_t s);
 hipError_t launch_derived(const DerivedArgs& a, int nblocks, hipStream_t s);
 // All jobs of one launch share the input-flow mode (a compile-time parameter of the kernel).
-// fa: the forward-additive estimator (16 x 16 tiles or the march) instead of the symmetric one.
+// generic: the kernels that read the estimator variant from a.est (16 x 16 tiles or the march)
+// instead of the symmetric estimator's consistent update compiled in.
 hipError_t launch_gn(const GnArgs& a, int kr, int storage, int mode, int variant, int nblocks, hipStream_t s,
-                     bool fa = false);
+                     bool generic = false);
 
 // ---------------------------------------------------------------- adjoint (float32 storage)
 struct ImageIn {

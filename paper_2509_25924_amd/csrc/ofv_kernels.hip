@@ -559,7 +559,7 @@ hipError_t launch_upsample(const UpsampleArgs& a, hipStream_t s) {
 namespace ofv {
 
 #define OFV_DECL(ST, MD) \
-  hipError_t launch_gn_##ST##_##MD(const GnArgs& a, int kr, int nblocks, hipStream_t s, bool fa);
+  hipError_t launch_gn_##ST##_##MD(const GnArgs& a, int kr, int nblocks, hipStream_t s, bool generic);
 OFV_DECL(f32, zero)
 OFV_DECL(f32, direct)
 OFV_DECL(f32, upsample)
@@ -571,7 +571,7 @@ OFV_DECL(bf16, direct)
 OFV_DECL(bf16, upsample)
 #undef OFV_DECL
 #define OFV_DECLT(ST, MD) \
-  hipError_t launch_gnt_##ST##_##MD(const GnArgs& a, int kr, int variant, int nblocks, hipStream_t s, bool fa);
+  hipError_t launch_gnt_##ST##_##MD(const GnArgs& a, int kr, int variant, int nblocks, hipStream_t s, bool generic);
 OFV_DECLT(f32, zero)
 OFV_DECLT(f32, direct)
 OFV_DECLT(f32, upsample)
@@ -584,22 +584,22 @@ OFV_DECLT(bf16, upsample)
 #undef OFV_DECLT
 
 hipError_t launch_gn(const GnArgs& a, int kr, int storage, int mode, int variant, int nblocks, hipStream_t s,
-                     bool fa) {
+                     bool generic) {
   variant = gn_variant_for(variant, kr);
   if (variant != GN_MARCH) {
 #define OFV_PICKT(ST)                                                                     \
-  if (mode == FLOW_ZERO) return launch_gnt_##ST##_zero(a, kr, variant, nblocks, s, fa);     \
-  if (mode == FLOW_DIRECT) return launch_gnt_##ST##_direct(a, kr, variant, nblocks, s, fa); \
-  return launch_gnt_##ST##_upsample(a, kr, variant, nblocks, s, fa);
+  if (mode == FLOW_ZERO) return launch_gnt_##ST##_zero(a, kr, variant, nblocks, s, generic);     \
+  if (mode == FLOW_DIRECT) return launch_gnt_##ST##_direct(a, kr, variant, nblocks, s, generic); \
+  return launch_gnt_##ST##_upsample(a, kr, variant, nblocks, s, generic);
     if (storage == ST_F32) { OFV_PICKT(f32) }
     if (storage == ST_F16) { OFV_PICKT(f16) }
     OFV_PICKT(bf16)
 #undef OFV_PICKT
   }
 #define OFV_PICK(ST)                                                    \
-  if (mode == FLOW_ZERO) return launch_gn_##ST##_zero(a, kr, nblocks, s, fa);     \
-  if (mode == FLOW_DIRECT) return launch_gn_##ST##_direct(a, kr, nblocks, s, fa); \
-  return launch_gn_##ST##_upsample(a, kr, nblocks, s, fa);
+  if (mode == FLOW_ZERO) return launch_gn_##ST##_zero(a, kr, nblocks, s, generic);     \
+  if (mode == FLOW_DIRECT) return launch_gn_##ST##_direct(a, kr, nblocks, s, generic); \
+  return launch_gn_##ST##_upsample(a, kr, nblocks, s, generic);
   if (storage == ST_F32) { OFV_PICK(f32) }
   if (storage == ST_F16) { OFV_PICK(f16) }
   OFV_PICK(bf16)

@@ -144,17 +144,21 @@ __device__ __forceinline__ float bilinear(const T* __restrict__ p, int64_t pitch
 // (q = 4 det / trace^2 < 1e-2) the float32 determinant has lost leading
 // digits to cancellation; there the determinant and the solution are
 // recomputed in float64 from the same float32 sums (products of two floats
-// are exact in double, so det is then exact up to one rounding).
+// are exact in double, so det is then exact up to one rounding), unless
+// `no_fp64` switches that fallback off.
+// inc (the increment form of the update): (A + lam I) dV = c with c the sums
+// of G (-T), and V' = V(m) + dV.
 __device__ __forceinline__ void solve2x2(float sxx, float sxy, float syy, float sxb, float syb, float um, float vm,
-                                         float reg_rel, float reg_abs, float& u, float& v) {
+                                         float reg_rel, float reg_abs, float& u, float& v, bool inc = false,
+                                         bool no_fp64 = false) {
   const float lam = reg_rel * (sxx + syy) + reg_abs;
   const float aa = sxx + lam;
   const float dd = syy + lam;
-  const float r1 = sxb + lam * um;
-  const float r2 = syb + lam * vm;
+  const float r1 = inc ? sxb : sxb + lam * um;
+  const float r2 = inc ? syb : syb + lam * vm;
   const float det = aa * dd - sxy * sxy;
   const float tr = aa + dd;
-  if (det >= 2.5e-3f * tr * tr) {
+  if (det >= 2.5e-3f * tr * tr || no_fp64) {
     // hardware reciprocal (1 ulp) refined by one Newton step
     float inv = __builtin_amdgcn_rcpf(det);
     inv = fmaf(inv, fmaf(-det, inv, 1.0f), inv);
@@ -165,6 +169,10 @@ __device__ __forceinline__ void solve2x2(float sxx, float sxy, float syy, float 
     const double dt = a * d - b * b;
     u = static_cast<float>((d * x1 - b * x2) / dt);
     v = static_cast<float>((a * x2 - b * x1) / dt);
+  }
+  if (inc) {
+    u += um;
+    v += vm;
   }
 }
 

@@ -149,3 +149,30 @@ def make_texture(h: int, w: int, *, fwhm: float, ppp: float, seed: int,
     py = rng.uniform(-0.5, hh - 0.5, size=n)
     amps = rng.uniform(0.5, 1.0, size=n)
     return render_particles(hh, ww, px, py, amps, sigma)
+
+
+def make_stripes_pair(h: int, w: int, tx: float, ty: float, *, seed: int, noise: float = 0.5,
+                      fwhm: float = 2.5, density: float = 0.35) -> ParticlePair:
+    """An aperture-problem pair: a one-dimensional particle texture along s = x + y (oblique
+    stripes of Gaussian line profiles, FWHM ``fwhm`` across the stripe, ``density`` lines per unit
+    of s), translated by (tx, ty) between the frames, 8-bit with Gaussian noise of ``noise`` DN.
+    Only the component of the motion along (1, 1) is visible in such images; the window normal
+    matrices are then nearly singular at most pixels.  The ground truth is the translation."""
+    rng = np.random.default_rng(seed)
+    smin, smax = -40.0, float(h + w) + 40.0
+    n = int(density * (smax - smin))
+    s0 = rng.uniform(smin, smax, n)
+    amps = rng.uniform(0.5, 1.0, n)
+    # FWHM measured across the stripes (along (1, 1) / sqrt(2)) is fwhm; in units of s it is sqrt(2) fwhm
+    sig = fwhm / FWHM_PER_SIGMA * math.sqrt(2.0)
+    yy, xx = np.mgrid[0:h, 0:w].astype(np.float64)
+    frames = []
+    for sgn in (-0.5, 0.5):
+        s = xx + yy - sgn * (tx + ty)
+        img = np.zeros((h, w))
+        for c, a in zip(s0, amps):
+            img += a * np.exp(-0.5 * ((s - c) / sig) ** 2)
+        img = 255.0 * img / 1.2 + noise * rng.normal(size=(h, w))
+        frames.append(np.clip(np.round(img), 0, 255).astype(np.uint8))
+    gt = np.stack([np.full((h, w), float(tx)), np.full((h, w), float(ty))])
+    return ParticlePair(frames[0], frames[1], gt, 8, n)

@@ -61,13 +61,15 @@ def bf_bilinear(p: np.ndarray, x: float, y: float) -> float:
 
 
 def bf_gn_iteration(p0: np.ndarray, p1: np.ndarray, u: np.ndarray, v: np.ndarray, kr: int,
-                    reg_rel: float, reg_abs: float, forward_additive: bool = False):
+                    reg_rel: float, reg_abs: float, forward_additive: bool = False, increment: bool = False):
     """One Jacobi step: per-window least squares with Levenberg damping rows.
 
     For every m, the linear model of the residual at each k in the window is
     G(k) . V ~= G(k) . V(k) - T(k); damping adds sqrt(lam) * (V - V(m)) = 0
     rows.  The normal equations of that stacked system are solved with
-    numpy.linalg.solve.
+    numpy.linalg.solve.  increment: the unknown is the step D = V - V(m) and
+    the model at every k of the window is G(k) . D ~= -T(k), damping rows
+    sqrt(lam) * D = 0; the result is V(m) + D.
     """
     h, w = p0.shape
     s = np.zeros((h, w))
@@ -98,10 +100,19 @@ def bf_gn_iteration(p0: np.ndarray, p1: np.ndarray, u: np.ndarray, v: np.ndarray
                 for xx in range(max(0, x - kr), min(w, x + kr + 1)):
                     gk = g[yy, xx]
                     rows.append(gk)
-                    rhs.append(float(gk[0] * u[yy, xx] + gk[1] * v[yy, xx] - t[yy, xx]))
+                    if increment:
+                        rhs.append(float(-t[yy, xx]))
+                    else:
+                        rhs.append(float(gk[0] * u[yy, xx] + gk[1] * v[yy, xx] - t[yy, xx]))
             a = np.array(rows)
             bvec = np.array(rhs)
             lam = reg_rel * float(np.sum(a * a)) + reg_abs
+            if increment:
+                stacked = np.vstack([a, math.sqrt(lam) * np.eye(2)])
+                target = np.concatenate([bvec, np.zeros(2)])
+                step = np.linalg.solve(stacked.T @ stacked, stacked.T @ target)
+                un[y, x], vn[y, x] = u[y, x] + step[0], v[y, x] + step[1]
+                continue
             normal = a.T @ a + lam * np.eye(2)
             rhs_n = a.T @ bvec + lam * np.array([u[y, x], v[y, x]])
             sol = np.linalg.solve(normal, rhs_n)
@@ -119,7 +130,8 @@ def bf_upsample(uc: np.ndarray, h: int, w: int) -> np.ndarray:
 
 def bf_compute_flow(i0: np.ndarray, i1: np.ndarray, levels: int, kr: int, it: int, nr: int,
                     eps: float, reg_rel: float, reg_abs: float,
-                    flow_init: Optional[np.ndarray] = None, forward_additive: bool = False) -> np.ndarray:
+                    flow_init: Optional[np.ndarray] = None, forward_additive: bool = False,
+                    increment: bool = False) -> np.ndarray:
     """The whole pipeline on float intensity images (already scaled to [0, 1])."""
     n0 = bf_normalize(i0, nr, eps)
     n1 = bf_normalize(i1, nr, eps)
@@ -140,5 +152,5 @@ def bf_compute_flow(i0: np.ndarray, i1: np.ndarray, levels: int, kr: int, it: in
         if lev < levels - 1:
             u, v = bf_upsample(u, h, w), bf_upsample(v, h, w)
         for _ in range(it):
-            u, v = bf_gn_iteration(pyr0[lev], pyr1[lev], u, v, kr, reg_rel, reg_abs, forward_additive)
+            u, v = bf_gn_iteration(pyr0[lev], pyr1[lev], u, v, kr, reg_rel, reg_abs, forward_additive, increment)
     return np.stack([u, v])

@@ -146,7 +146,7 @@ def test_valid_call_reaches_the_device_step(lib, vhandle):
     (lambda i0, i1, p: setattr(p, "reg_rel", -1.0), _lib.OFV_ERR_INVALID_ARG, b"reg_rel"),
     (lambda i0, i1, p: setattr(p, "reg_abs", float("inf")), _lib.OFV_ERR_INVALID_ARG, b"reg_abs"),
     (lambda i0, i1, p: setattr(p, "storage", 3), _lib.OFV_ERR_INVALID_ARG, b"storage"),
-    (lambda i0, i1, p: setattr(p, "flags", 4), _lib.OFV_ERR_INVALID_ARG, b"flags"),
+    (lambda i0, i1, p: setattr(p, "flags", 8), _lib.OFV_ERR_INVALID_ARG, b"flags"),
     (lambda i0, i1, p: (setattr(i0, "width", 257), setattr(i1, "width", 257), setattr(i0, "pitch", 257),
                         setattr(i1, "pitch", 257)), _lib.OFV_ERR_CAPACITY, b"exceeds"),
     (lambda i0, i1, p: (setattr(i0, "height", 129), setattr(i1, "height", 129)), _lib.OFV_ERR_CAPACITY, b"exceeds"),
@@ -296,12 +296,19 @@ def test_estimator_flags(lib, vhandle):
     p = _params(flags=_lib.FLAG_FORWARD_ADDITIVE)
     assert lib.ofv_compute_flow(vhandle, byref(img0), byref(img1), byref(p), c_void_p(OUT)) == \
         _lib.OFV_ERR_UNSUPPORTED                                        # valid, validation-only handle
-    bad = _params(flags=2)
+    for ok in (_lib.FLAG_INCREMENT_UPDATE, _lib.FLAG_NO_FP64_FALLBACK,
+               _lib.FLAG_FORWARD_ADDITIVE | _lib.FLAG_INCREMENT_UPDATE | _lib.FLAG_NO_FP64_FALLBACK):
+        q = _params(flags=ok)
+        assert lib.ofv_compute_flow(vhandle, byref(img0), byref(img1), byref(q), c_void_p(OUT)) == \
+            _lib.OFV_ERR_UNSUPPORTED
+    bad = _params(flags=8)
     assert lib.ofv_compute_flow(vhandle, byref(img0), byref(img1), byref(bad), c_void_p(OUT)) == \
         _lib.OFV_ERR_INVALID_ARG
-    assert lib.ofv_compute_flow_backward(vhandle, byref(img0), byref(img1), byref(p), None, c_void_p(OUT),
-                                         c_void_p(OUT + (1 << 20)), None, None) == _lib.OFV_ERR_UNSUPPORTED
-    assert b"symmetric" in lib.ofv_last_error(vhandle)
+    for est in (_lib.FLAG_FORWARD_ADDITIVE, _lib.FLAG_INCREMENT_UPDATE):
+        q = _params(flags=est)
+        assert lib.ofv_compute_flow_backward(vhandle, byref(img0), byref(img1), byref(q), None, c_void_p(OUT),
+                                             c_void_p(OUT + (1 << 20)), None, None) == _lib.OFV_ERR_UNSUPPORTED
+        assert b"symmetric" in lib.ofv_last_error(vhandle)
 
 
 def test_static_entry_point_validation(lib, monkeypatch):

@@ -129,3 +129,24 @@ def test_backward_argument_errors(ofv):
                                        c_void_p(g.data_ptr()), None, None)
     assert st == _lib.OFV_ERR_INVALID_ARG   # output overlaps grad_flow
     h.close()
+
+
+def test_adjoint_matches_oracle_autograd_512(ofv):
+    """The differentiation workload's shape: one 512 x 512 float pair (Rankine vortex, noise
+    2/255), 3 levels, KR 4, IT 3, NR 1, loss sum |V - V_gt|^2, gradients for both frames and the
+    initial field against autograd of the FP64 oracle."""
+    say("adjoint 512x512")
+    pair, prm = synth.config_adjoint_512(0)
+    init = (pair.gt + np.random.default_rng(6).normal(0, 0.2, pair.gt.shape)).astype(np.float32)
+    v_or = oracle.compute_flow(pair.frame0, pair.frame1, prm, bit_depth0=0, flow_init=init)
+    g_up = 2.0 * (v_or - torch.as_tensor(pair.gt))
+    r0, r1, ri = _oracle_grads(pair.frame0, pair.frame1, init, prm, g_up, 0)
+    f0 = torch.from_numpy(pair.frame0).cuda()
+    f1 = torch.from_numpy(pair.frame1).cuda()
+    g0, g1, gi = ofv.compute_flow_backward(f0, f1, prm, g_up.float().cuda().contiguous(),
+                                           flow_init=torch.from_numpy(init).cuda())
+    torch.cuda.synchronize()
+    for name, got, ref in (("frame0", g0, r0), ("frame1", g1, r1), ("flow_init", gi, ri)):
+        rel, cos = _metrics(got, ref)
+        say(f"  {name}: rel-L2 {rel:.2e} cosine {cos:.7f}")
+        assert rel <= 1e-3 and cos >= 0.9999

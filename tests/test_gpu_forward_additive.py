@@ -1,5 +1,7 @@
-"""The forward-additive estimator (params estimator="forward_additive") on
-the GPU against the FP64 oracle's forward-additive estimator."""
+"""The estimator variants on the GPU against the FP64 oracle's: the
+forward-additive warps (params estimator="forward_additive") and the
+increment form of the update (params update="increment"), alone and
+together."""
 import sys
 
 import numpy as np
@@ -83,3 +85,37 @@ def test_forward_additive_identical_frames_and_batch(ofv):
     with pytest.raises(ofv.OfvError):
         h.autotune(f0[0], f1[0], prm, bit_depth=8)
     h.close()
+
+
+# ---------------------------------------------------------------- increment-form update
+
+@pytest.mark.parametrize("estimator", ["symmetric", "forward_additive"])
+@pytest.mark.parametrize("case", ["shear300", "rankine256", "march"])
+def test_increment_update_matches_oracle(ofv, estimator, case):
+    """update="increment" (OFV_FLAG_INCREMENT_UPDATE) on the GPU against the FP64 oracle's increment
+    update, with the symmetric warps and with the forward-additive ones (classic LK per window)."""
+    say("increment update", estimator, case)
+    h = None
+    if case in ("shear300", "march"):
+        pair, prm = synth.config_shear_1mp(size=300)
+        bits = 12
+        if case == "march":
+            h = ofv.Handle(300, 300, 1)
+            h.set_gn_variant("march")
+    else:
+        pair, prm = synth.config_rankine_256()
+        bits = 8
+    prm = dict(prm, estimator=estimator, update="increment")
+    f0 = torch.from_numpy(pair.frame0).cuda()
+    f1 = torch.from_numpy(pair.frame1).cuda()
+    got = ofv.compute_flow(f0, f1, prm, bit_depth=bits, handle=h)
+    ref = oracle.compute_flow(pair.frame0, pair.frame1, prm, bit_depth0=bits)
+    err = torch.max(torch.abs(got.cpu().double() - ref)).item()
+    say("  max |dV| =", err)
+    assert err <= 1e-3
+    cons = ofv.compute_flow(f0, f1, dict(prm, update="consistent"), bit_depth=bits, handle=h)
+    assert torch.max(torch.abs(cons - got)).item() > 1e-4
+    z = ofv.compute_flow(f0, f0, prm, bit_depth=bits, handle=h)
+    assert torch.count_nonzero(z).item() == 0
+    if h is not None:
+        h.close()

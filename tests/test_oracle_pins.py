@@ -472,3 +472,92 @@ def test_planted_half_step_in_forward_additive_is_caught(monkeypatch):
         return w1, w1 - p0
     monkeypatch.setattr(O, "warp_terms_forward", mut)
     assert _check_fa_fixed_point() > 1e-3
+
+
+# ---------------------------------------------------------------- increment-form update (R25)
+
+@pytest.mark.parametrize("estimator", ["symmetric", "forward_additive"])
+@pytest.mark.parametrize("levels,kr,it", [(1, 1, 1), (1, 2, 3), (2, 1, 3), (2, 2, 2)])
+def test_increment_update_matches_bruteforce_8x8(estimator, levels, kr, it):
+    """The oracle's increment update against the brute force, which stacks one row per
+    window pixel in the unknown step and its damping rows and hands them to numpy."""
+    rng = np.random.default_rng(400 + 10 * levels + kr + it)
+    i0 = rng.uniform(0, 1, (8, 8))
+    i1 = rng.uniform(0, 1, (8, 8))
+    v0 = rng.uniform(-1, 1, (2, 8, 8))
+    prm = {"num_levels": levels, "kernel_radius": kr, "iterations": it, "norm_radius": 1,
+           "estimator": estimator, "update": "increment"}
+    got = oracle.compute_flow(i0, i1, prm, bit_depth0=0, flow_init=v0).numpy()
+    ref = bf.bf_compute_flow(i0, i1, levels, kr, it, 1, 1e-4, 1e-3, 1e-9, flow_init=v0,
+                             forward_additive=estimator == "forward_additive", increment=True)
+    # relative: on random 8x8 pairs the forward-additive increment iteration runs away (|V| ~ 10 after
+    # a few steps) and amplifies the different rounding orders of the two computations; a slip in the
+    # formula moves the result by O(1) (test_planted_mistakes_in_the_increment_step_are_caught)
+    tol = 1e-10 if estimator == "symmetric" else 1e-8
+    assert np.max(np.abs(got - ref) / (1.0 + np.abs(ref))) < tol
+    cons = oracle.compute_flow(i0, i1, dict(prm, update="consistent"), bit_depth0=0, flow_init=v0).numpy()
+    assert np.max(np.abs(got - cons)) > 1e-3      # a different update where the field varies
+
+
+def test_increment_update_equals_consistent_where_the_field_is_uniform():
+    """With V(k) = V(m) over every window the two linearisations coincide: exactly at V = 0 (both
+    solve the same system), and up to rounding for a uniform non-zero field."""
+    p0, p1, _, _ = _tiny_levels(seed=9)
+    z = torch.zeros(8, 8, dtype=torch.float64)
+    a = oracle.gn_iteration(T(p0), T(p1), z, z, 2, 1e-3, 1e-9, update="increment")
+    b = oracle.gn_iteration(T(p0), T(p1), z, z, 2, 1e-3, 1e-9)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    cu = torch.full((8, 8), 0.7, dtype=torch.float64)
+    cv = torch.full((8, 8), -0.4, dtype=torch.float64)
+    for est in ("symmetric", "forward_additive"):
+        a = oracle.gn_iteration(T(p0), T(p1), cu, cv, 2, 1e-3, 1e-9, estimator=est, update="increment")
+        b = oracle.gn_iteration(T(p0), T(p1), cu, cv, 2, 1e-3, 1e-9, estimator=est)
+        assert torch.max(torch.abs(a[0] - b[0])).item() < 1e-12
+        assert torch.max(torch.abs(a[1] - b[1])).item() < 1e-12
+
+
+def test_increment_update_integer_translation_is_an_exact_fixed_point():
+    tx, ty = 2, -1
+    f0, f1 = _shifted_pair(tx, ty)
+    n = f0.shape[0]
+    init = np.stack([np.full((n, n), float(tx)), np.full((n, n), float(ty))])
+    prm = {"num_levels": 1, "kernel_radius": 3, "iterations": 1, "norm_radius": 0, "update": "increment"}
+    out = oracle.compute_flow(f0, f1, prm, bit_depth0=0, flow_init=init).numpy()
+    b = 3 + 2 + 2
+    assert np.max(np.abs(out[:, b:-b, b:-b] - init[:, b:-b, b:-b])) < 1e-12
+
+
+@pytest.mark.parametrize("mistake", ["no_anchor", "sign", "swapped"])
+def test_planted_mistakes_in_the_increment_step_are_caught(monkeypatch, mistake):
+    from oracle import ofv_oracle as O
+    steps = {
+        "no_anchor": lambda a, d, sxy, det, sxb, syb, u, v: ((d * sxb - sxy * syb) / det,
+                                                             (a * syb - sxy * sxb) / det),
+        "sign": lambda a, d, sxy, det, sxb, syb, u, v: (u - (d * sxb - sxy * syb) / det,
+                                                        v - (a * syb - sxy * sxb) / det),
+        "swapped": lambda a, d, sxy, det, sxb, syb, u, v: (u + (a * sxb - sxy * syb) / det,
+                                                           v + (d * syb - sxy * sxb) / det),
+    }
+    monkeypatch.setattr(O, "increment_step", steps[mistake])
+    rng = np.random.default_rng(411)
+    i0 = rng.uniform(0, 1, (8, 8))
+    i1 = rng.uniform(0, 1, (8, 8))
+    v0 = rng.uniform(-1, 1, (2, 8, 8))
+    prm = {"num_levels": 1, "kernel_radius": 1, "iterations": 1, "norm_radius": 1, "update": "increment"}
+    got = O.compute_flow(i0, i1, prm, bit_depth0=0, flow_init=v0).numpy()
+    ref = bf.bf_compute_flow(i0, i1, 1, 1, 1, 1, 1e-4, 1e-3, 1e-9, flow_init=v0, increment=True)
+    assert np.max(np.abs(got - ref)) > 1e-6
+
+
+def test_float32_arithmetic_option():
+    """arith="f32" (a diagnostic floor, not the reference) runs every step in float32: on a
+    well-conditioned input it stays within a few float32 roundings of the float64 reference, is
+    not identical to it, and returns float64; every intermediate is float32."""
+    pair, prm = synth.config_rankine_256()
+    ref = oracle.compute_flow(pair.frame0, pair.frame1, prm, bit_depth0=8)
+    tr = oracle.Trace()
+    got = oracle.compute_flow(pair.frame0, pair.frame1, prm, bit_depth0=8, arith="f32", trace=tr)
+    assert got.dtype == torch.float64
+    assert all(p.dtype == torch.float32 for p in tr.levels0 + tr.levels1)
+    assert all(u.dtype == torch.float32 for u, _ in tr.iterates.values())
+    assert 0 < torch.max(torch.abs(got - ref)).item() < 1e-4
