@@ -23,8 +23,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 GN_NAMES = {0: "march", 1: "tile64x32", 2: "tile64x16", 3: "tile32x16", 4: "tile16x16", 5: "tile64x32w",
-            6: "tile64x16w", 7: "tile64x64", 8: "tile16x16w", 9: "tile32x16w", 10: "tile32x32w"}
-GN_SOURCES = ["ofv_gn_impl.h", "ofv_gn_tile.h", "ofv_px.h", "ofv_internal.h"]
+            6: "tile64x16w", 7: "tile64x64", 8: "tile16x16w", 9: "tile32x16w", 10: "tile32x32w", 11: "band"}
+GN_SOURCES = ["ofv_gn_impl.h", "ofv_gn_tile.h", "ofv_gn_band.h", "ofv_px.h", "ofv_internal.h"]
 
 
 def host_cpu():

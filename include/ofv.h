@@ -225,12 +225,15 @@ ofv_status ofv_compute_flow_backward(ofv_handle h, const ofv_image* frame0, cons
 #define OFV_GN_TILE_16x16W 8  /* 16 x 16 output tiles, 1024 lanes per workgroup (coarse levels) */
 #define OFV_GN_TILE_32x16W 9  /* 32 x 16 output tiles, 512 lanes per workgroup (coarse levels) */
 #define OFV_GN_TILE_32x32W 10 /* 32 x 32 output tiles, 1024 lanes per workgroup */
+#define OFV_GN_BAND 11        /* 256-column strips marching down in blocks of 4 rows, vertical window sums
+                                 in registers; tile_h 0 = as many rows per tile as give every resident
+                                 workgroup slot one tile */
 
 /* Force a decomposition for later calls on h (OFV_GN_AUTO restores the
- * default); tile_h (rows per strip for OFV_GN_MARCH) is 0 for automatic or
+ * default); tile_h (rows per strip for OFV_GN_MARCH and OFV_GN_BAND) is 0 for automatic or
  * 4..1024.  The environment variable OFV_GN_VARIANT (march, tile64x32,
  * tile64x16, tile32x16, tile16x16, tile64x32w, tile64x16w, tile64x64,
- * tile16x16w, tile32x16w or tile32x32w; tile32 and tile16 are accepted for
+ * tile16x16w, tile32x16w, tile32x32w or band; tile32 and tile16 are accepted for
  * tile64x32 and tile64x16), read at every launch, overrides both this
  * choice and the tuned table; levels one pixel wide or high always take the
  * march. */

@@ -28,6 +28,12 @@ COMMON_FLAGS = [
     "-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
     # no packed-FP32 instructions anywhere in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # register arrays indexed by a wavefront-uniform index (the band kernel's
+    # vertical rings, up to 5 x 25 floats) stay in registers instead of going
+    # to scratch memory: the default budget for such arrays is a quarter of the
+    # registers and 16 registers per array
+    "-mllvm", "-amdgpu-promote-alloca-to-vector-vgpr-ratio=1",
+    "-mllvm", "-amdgpu-promote-alloca-to-vector-max-regs=32",
     "-Wno-unused-command-line-argument",
     f"-I{INCLUDE}", f"-I{CSRC}",
 ]

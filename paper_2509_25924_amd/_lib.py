@@ -26,7 +26,7 @@ MAX_KERNEL_RADIUS = 12
 MAX_NORM_RADIUS = 16
 GN_VARIANTS = {"auto": -1, "march": 0, "tile64x32": 1, "tile64x16": 2, "tile32x16": 3, "tile16x16": 4,
                "tile64x32w": 5, "tile64x16w": 6, "tile64x64": 7, "tile16x16w": 8, "tile32x16w": 9,
-               "tile32x32w": 10}
+               "tile32x32w": 10, "band": 11}
 
 
 class OfvImage(ctypes.Structure):

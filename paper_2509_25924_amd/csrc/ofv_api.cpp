@@ -41,6 +41,7 @@ thread_local std::string g_create_error;
 
 struct ofv_ctx {
   int device = -1;  // -1: validation-only handle (no device resources)
+  int num_cus = 256;  // compute units of the device (sizes band launches)
   hipStream_t stream = nullptr;
   int max_w = 0, max_h = 0, max_batch = 0;
   // level geometry of the largest frame; planes of smaller frames reuse it
@@ -230,8 +231,8 @@ int choose_tile_h(int64_t strips_total, int64_t rows_max) {
 // covers enough pixels to give every CU several strips (measured on MI355X:
 // march ahead from about 4 Mp per launch), 64 x 16 tiles below that.  Levels
 // one pixel wide or high always take the march.
-void pick_gn(const ofv_ctx* h, const ofv_ctx::TuneKey& key, int64_t strips, int64_t rows_max, int64_t pixels,
-             bool degenerate, int& variant, int& tile_h) {
+void pick_gn_choice(const ofv_ctx* h, const ofv_ctx::TuneKey& key, int64_t strips, int64_t rows_max, int64_t pixels,
+                    bool degenerate, int& variant, int& tile_h) {
   tile_h = choose_tile_h(strips, rows_max);
   if (degenerate) {  // a level of one row or one column: the tile kernels need 2 x 2 pixels
     variant = GN_MARCH;
@@ -249,6 +250,7 @@ void pick_gn(const ofv_ctx* h, const ofv_ctx::TuneKey& key, int64_t strips, int6
     if (!std::strcmp(e, "tile16x16w")) { variant = GN_TILE_16x16W; return; }
     if (!std::strcmp(e, "tile32x16w")) { variant = GN_TILE_32x16W; return; }
     if (!std::strcmp(e, "tile32x32w")) { variant = GN_TILE_32x32W; return; }
+    if (!std::strcmp(e, "band")) { variant = GN_BAND4; return; }
   }
   if (h->forced_variant >= 0) {
     variant = h->forced_variant;
@@ -262,6 +264,20 @@ void pick_gn(const ofv_ctx* h, const ofv_ctx::TuneKey& key, int64_t strips, int6
     return;
   }
   variant = pixels >= (int64_t{3} << 20) ? GN_MARCH : GN_TILE_64x16;
+}
+
+// pick_gn_choice, then for the band decomposition the tile height that gives
+// one round of resident workgroups (unless a tile height was forced).
+void pick_gn(const ofv_ctx* h, const ofv_ctx::TuneKey& key, int64_t strips, int64_t rows_max, int64_t pixels,
+             bool degenerate, int& variant, int& tile_h) {
+  pick_gn_choice(h, key, strips, rows_max, pixels, degenerate, variant, tile_h);
+  if (variant != GN_BAND4) return;
+  if (h->forced_variant == GN_BAND4 && h->forced_tile_h > 0) {
+    tile_h = h->forced_tile_h;
+    return;
+  }
+  const int per_cu = std::max(1, gn_band_per_cu(key.kr, key.storage, key.mode));
+  tile_h = gn_band_tile_h(strips, rows_max, static_cast<int64_t>(per_cu) * h->num_cus, key.kr);
 }
 
 hipEvent_t next_event(ofv_ctx* h) {
@@ -720,6 +736,9 @@ ofv_status ofv_create(ofv_handle* out, int device, int max_width, int max_height
       return fail(nullptr, OFV_ERR_OUT_OF_MEMORY, "hipMalloc(%zu bytes): %s", h_bytes_tmp, hipGetErrorString(e));
     }
     h->derived_counts = reinterpret_cast<unsigned int*>(h->ws + h->slot_bytes * static_cast<size_t>(max_batch));
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+      h->num_cus = cus;
   }
   *out = h;
   return OFV_OK;
@@ -818,6 +837,9 @@ ofv_status ofv_compute_flow_static(const ofv_image* frame0, const ofv_image* fra
   c.device = dev;
   c.stream = static_cast<hipStream_t>(stream);
   c.ws_bytes = kStaticScratchBytes;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+    c.num_cus = cus;
   PairPlan pp{};
   pp.f[0] = frame0;
   pp.f[1] = frame1;
@@ -1287,7 +1309,7 @@ ofv_status ofv_autotune(ofv_handle h, const ofv_image* frame0, const ofv_image* 
   const Cand cands[] = {{GN_TILE_16x16, 16},  {GN_TILE_16x16W, 16}, {GN_TILE_32x16, 16}, {GN_TILE_32x16W, 16},
                         {GN_TILE_64x16, 16},  {GN_TILE_64x32, 32},  {GN_TILE_64x16W, 16}, {GN_TILE_64x32W, 32},
                         {GN_TILE_32x32W, 32}, {GN_TILE_64x64, 64},  {GN_MARCH, 16},       {GN_MARCH, 32},
-                        {GN_MARCH, 64}};
+                        {GN_MARCH, 64},       {GN_BAND4, 0}};
   constexpr int nc = static_cast<int>(sizeof(cands) / sizeof(cands[0]));
   // launch times per (level key, candidate); the candidates take turns within every
   // repeat, so that slow drifts of the clock affect them alike
@@ -1362,7 +1384,9 @@ ofv_status ofv_tuning_import(ofv_handle h, const char* text) {
   int line = 0;
   while (is >> k.kr >> k.storage >> k.mode >> k.w >> k.hgt >> k.n >> c.variant >> c.tile_h) {
     ++line;
-    if (c.variant < GN_MARCH || c.variant >= kGnVariants || c.tile_h < 4 || c.tile_h > 1024)
+    // band entries record tile height 0: it is sized at every launch
+    if (c.variant < GN_MARCH || c.variant >= kGnVariants ||
+        (c.variant == GN_BAND4 ? c.tile_h != 0 : (c.tile_h < 4 || c.tile_h > 1024)))
       return fail(h, OFV_ERR_INVALID_ARG, "tuning entry %d is invalid", line);
     add[k] = c;
   }

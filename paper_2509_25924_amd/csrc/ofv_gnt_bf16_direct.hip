@@ -1,10 +1,13 @@
-// Fused Gauss-Newton iteration, 2-D tile variants: bf16_t image storage, input flow mode FLOW_DIRECT.
-#include "ofv_gn_tile.h"
+// Fused Gauss-Newton iteration, 2-D tile and band variants: bf16_t image storage, input flow mode FLOW_DIRECT.
+#include "ofv_gn_band.h"
 
 namespace ofv {
 
 hipError_t launch_gnt_bf16_direct(const GnArgs& a, int kr, int variant, int nblocks, hipStream_t s, bool generic) {
+  if (variant == GN_BAND4 && !generic) return launch_gn_band_typed<FLOW_DIRECT, bf16_t>(a, kr, nblocks, s);
   return launch_gn_tile_typed<FLOW_DIRECT, bf16_t>(a, kr, variant, nblocks, s, generic);
 }
+
+int gn_band_per_cu_bf16_direct(int kr) { return gn_band_typed_per_cu<FLOW_DIRECT, bf16_t>(kr); }
 
 }  // namespace ofv

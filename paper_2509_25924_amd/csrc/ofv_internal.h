@@ -156,9 +156,10 @@ enum GnVariant {
   GN_TILE_64x64 = 7,
   GN_TILE_16x16W = 8,
   GN_TILE_32x16W = 9,
-  GN_TILE_32x32W = 10
+  GN_TILE_32x32W = 10,
+  GN_BAND4 = 11
 };
-constexpr int kGnVariants = 11;
+constexpr int kGnVariants = 12;
 
 // Columns of output produced by one 256-lane strip for window radius kr.
 inline int gn_tile_w(int kr) { return kGnThreads - 2 * kr - 2; }
@@ -180,7 +181,23 @@ inline void gn_tile_dims(int variant, int kr, int tile_h, int& tw, int& th) {
   else if (variant == GN_TILE_32x16 || variant == GN_TILE_32x16W) { tw = 32; th = 16; }
   else if (variant == GN_TILE_32x32W) { tw = 32; th = 32; }
   else if (variant == GN_TILE_16x16 || variant == GN_TILE_16x16W) { tw = 16; th = 16; }
-  else { tw = gn_tile_w(kr); th = tile_h; }
+  else { tw = gn_tile_w(kr); th = tile_h; }   // the march and the band: 256-column strips
+}
+
+// Band decomposition: workgroups of the band kernel for window radius kr,
+// storage and input-flow mode that fit on one compute unit at once (0 if
+// the runtime cannot tell).
+int gn_band_per_cu(int kr, int storage, int mode);
+// Output rows per band tile: enough tiles to give every resident workgroup
+// slot one (a single round), no fewer rows than keep the vertical halo
+// (2 kr + 2 rows) below about a third of the rows computed.
+inline int gn_band_tile_h(int64_t strips, int64_t rows_max, int64_t slots, int kr) {
+  const int64_t per_strip = slots / (strips > 0 ? strips : 1);
+  int64_t th = per_strip > 0 ? (rows_max + per_strip - 1) / per_strip : rows_max;
+  const int64_t lo = 4 * kr + 8;
+  if (th < lo) th = lo;
+  if (th > rows_max) th = rows_max;
+  return static_cast<int>(th < 4 ? 4 : th);
 }
 
 hipError_t launch_normalize(const NormArgs& a, int nblocks, hipStream_t s);

@@ -571,7 +571,8 @@ OFV_DECL(bf16, direct)
 OFV_DECL(bf16, upsample)
 #undef OFV_DECL
 #define OFV_DECLT(ST, MD) \
-  hipError_t launch_gnt_##ST##_##MD(const GnArgs& a, int kr, int variant, int nblocks, hipStream_t s, bool generic);
+  hipError_t launch_gnt_##ST##_##MD(const GnArgs& a, int kr, int variant, int nblocks, hipStream_t s, bool generic); \
+  int gn_band_per_cu_##ST##_##MD(int kr);
 OFV_DECLT(f32, zero)
 OFV_DECLT(f32, direct)
 OFV_DECLT(f32, upsample)
@@ -582,6 +583,17 @@ OFV_DECLT(bf16, zero)
 OFV_DECLT(bf16, direct)
 OFV_DECLT(bf16, upsample)
 #undef OFV_DECLT
+
+int gn_band_per_cu(int kr, int storage, int mode) {
+#define OFV_OCC(ST)                                                \
+  if (mode == FLOW_ZERO) return gn_band_per_cu_##ST##_zero(kr);     \
+  if (mode == FLOW_DIRECT) return gn_band_per_cu_##ST##_direct(kr); \
+  return gn_band_per_cu_##ST##_upsample(kr);
+  if (storage == ST_F32) { OFV_OCC(f32) }
+  if (storage == ST_F16) { OFV_OCC(f16) }
+  OFV_OCC(bf16)
+#undef OFV_OCC
+}
 
 hipError_t launch_gn(const GnArgs& a, int kr, int storage, int mode, int variant, int nblocks, hipStream_t s,
                      bool generic) {

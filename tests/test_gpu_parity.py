@@ -441,7 +441,7 @@ def test_graph_replay_matches_eager(ofv):
 @pytest.mark.parametrize("variant,tile_h", [("march", 0), ("march", 8), ("tile64x32", 0), ("tile64x16", 0),
                                             ("tile32x16", 0), ("tile16x16", 0), ("tile64x32w", 0),
                                             ("tile64x16w", 0), ("tile64x64", 0), ("tile16x16w", 0),
-                                            ("tile32x16w", 0), ("tile32x32w", 0)])
+                                            ("tile32x16w", 0), ("tile32x32w", 0), ("band", 0), ("band", 24)])
 def test_every_decomposition_matches_oracle(ofv, variant, tile_h):
     say("decomposition", variant, tile_h)
     pair, prm = synth.config_shear_1mp(size=300)
@@ -490,7 +490,7 @@ def test_autotune_table_roundtrip(ofv):
     assert len(lines) >= prm["num_levels"]
     for l in lines:
         kr, st, mode, w, hh, n, var, th = map(int, l.split())
-        assert kr == prm["kernel_radius"] and n == 1 and var in range(11)
+        assert kr == prm["kernel_radius"] and n == 1 and var in range(12)
     tuned = ofv.compute_flow(f0, f1, prm, bit_depth=8, handle=h)
     ref = oracle.compute_flow(pair.frame0, pair.frame1, prm, bit_depth0=8)
     assert torch.max(torch.abs(o64(tuned) - ref)).item() <= FLOW_TOL
@@ -500,7 +500,7 @@ def test_autotune_table_roundtrip(ofv):
     assert h2.tuning_table() == table
     assert torch.equal(ofv.compute_flow(f0, f1, prm, bit_depth=8, handle=h2), tuned)
     with pytest.raises(ofv.OfvError):
-        h2.load_tuning_table("5 0 1 64 64 1 11 16\n")
+        h2.load_tuning_table("5 0 1 64 64 1 12 16\n")
     h.close()
     h2.close()
 
