@@ -22,6 +22,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+# Non-packed FP32/integer VALU issue rate of the chip: 256 CUs x 4 SIMDs x 16
+# lanes x 2.4 GHz (a wave64 VALU instruction holds a 16-lane SIMD for 4 cycles;
+# packed-FP32 instructions, which would double it, are not used).
+VALU_LANE_INSTR_PER_S = 256 * 4 * 16 * 2.4e9
 GN_NAMES = {0: "march", 1: "tile64x32", 2: "tile64x16", 3: "tile32x16", 4: "tile16x16", 5: "tile64x32w",
             6: "tile64x16w", 7: "tile64x64", 8: "tile16x16w", 9: "tile32x16w", 10: "tile32x32w", 11: "band"}
 GN_SOURCES = ["ofv_gn_impl.h", "ofv_gn_tile.h", "ofv_gn_band.h", "ofv_px.h", "ofv_internal.h"]
@@ -50,10 +54,11 @@ def gn_source_digest():
     return hsh.hexdigest()[:16]
 
 
-def measured_traffic(workload, storage, decomposition):
-    """HBM bytes per launch of the full-resolution Gauss-Newton kernel, from the committed
-    hardware-counter summary, or None when there is none for these kernel sources."""
-    path = os.path.join(ROOT, "profiles", f"gn_traffic_{workload}_{storage}.md")
+def measured_traffic(workload, storage, decomposition, kind="traffic"):
+    """HBM bytes (kind "traffic") or VALU instructions (kind "valu") per launch of the full-resolution
+    Gauss-Newton kernel, from the committed hardware-counter summary, or None when there is none for these
+    kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"gn_{kind}_{workload}_{storage}.md")
     if not os.path.exists(path):
         return None
     digest, table = None, {}
@@ -76,7 +81,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="shear_1mp", choices=["shear_1mp", "rankine_256", "paper_1mp"])
+    ap.add_argument("--workload", default="shear_1mp", choices=["shear_1mp", "rankine_256", "paper_1mp", "wake_21mp"],
+                    help="wake_21mp (5120x4096 cylinder wake, KR 10) only with --pmc-probe")
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--no-graph", action="store_true", help="launch eagerly instead of replaying a hipGraph")
     ap.add_argument("--variant", default="tuned", choices=["tuned", "auto"] + list(GN_NAMES.values()),
@@ -88,6 +94,8 @@ def parse():
     ap.add_argument("--kernel-launches", type=int, default=200, help="launches timed for the dominant kernel")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-21mp", action="store_true",
+                    help="skip the roofline of the 5120x4096 level-0 Gauss-Newton launch (above the Infinity Cache)")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="for hardware-counter runs: launch a 256 MiB elementwise negation and a 256 MiB copy 3 times each, then the full-resolution "
                          "Gauss-Newton kernel 5 times in each decomposition, and exit")
@@ -257,10 +265,13 @@ def suite_live21mp(args, dev):
     crop2 = (slice(1024, 3072), slice(1536, 3584))
     crop1 = (slice(1536, 2560), slice(2048, 3072))
 
+    hdef = ofv.Handle(W, H, 3)      # no tuned table: the default decomposition choice
+    cur = [hb]
+
     def batch_of(a, b, p):
         f0 = [a, a[crop2], a[crop1]]
         f1 = [b, b[crop2], b[crop1]]
-        ofv.compute_flow_batch(f0, f1, p, bit_depth=12, outs=outs, handle=hb)
+        ofv.compute_flow_batch(f0, f1, p, bit_depth=12, outs=outs, handle=cur[0])
 
     def capture(fn):
         s = torch.cuda.Stream()
@@ -271,15 +282,21 @@ def suite_live21mp(args, dev):
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
             fn()
-        hb.bind_stream()
+        cur[0].bind_stream()
         return g
 
-    res, acc = {}, {}
+    res, acc, tables = {}, {}, {}
     steps = 500
     for storage in ("bf16", "f32"):
         p = dict(prm, storage=storage)
-        for variant in ("auto", "tile64x32", "tile64x32w", "tile64x16w", "march"):
-            hb.set_gn_variant(variant)
+        # the autotuner on the uneven batch itself: per launch group (level, flow mode) the fastest
+        # decomposition, keyed by the batch's geometry
+        hb.set_gn_variant("auto")
+        a0, b0 = pairs[0]
+        hb.autotune_batch([a0, a0[crop2], a0[crop1]], [b0, b0[crop2], b0[crop1]], p, bit_depth=12, repeats=3)
+        tables[storage] = [l for l in hb.tuning_table().splitlines() if l.split()[1] == str({"f32": 0, "bf16": 2}[storage])]
+        for variant in ("tuned", "default"):
+            cur[0] = hb if variant == "tuned" else hdef
             graphs = [capture(lambda ph=ph: batch_of(*pairs[ph], p)) for ph in range(phases)]
             k = [0]
 
@@ -288,8 +305,8 @@ def suite_live21mp(args, dev):
                 k[0] += 1
             res[f"{storage}/{variant}"] = _timed(step, steps, 16)
             del graphs
-        # accuracy of the 1024^2 crop of phase 0 against the FP64 oracle (default decomposition)
-        hb.set_gn_variant("auto")
+        # accuracy of the 1024^2 crop of phase 0 against the FP64 oracle (tuned decompositions)
+        cur[0] = hb
         batch_of(*pairs[0], p)
         v = outs[2].cpu().double().numpy()
         a0 = pairs[0][0][crop1].cpu().numpy().astype(np.uint16)
@@ -311,7 +328,16 @@ def suite_live21mp(args, dev):
     # frame k+1) from a ring of three device frames while frame k+2 is copied in on a second stream
     storage, variant = best_key.split("/")
     p = dict(prm, storage=storage)
-    hb.set_gn_variant(variant)
+    cur[0] = hb if variant == "tuned" else hdef
+
+    # the paper's live criterion: frames arrive at a fixed rate, raised until overruns appear (a frame
+    # whose field is not complete when the next frame arrives); compute-only graph steps, host clock
+    from paper_2509_25924_amd.live import LiveLoop, max_overrun_free_rate
+    ograph = [capture(lambda ph=ph: batch_of(*pairs[ph], p)) for ph in range(phases)]
+    overrun = max_overrun_free_rate(
+        lambda period: LiveLoop(lambda k: ograph[k % phases].replay(), period, wait=torch.cuda.synchronize),
+        [90.0, 200.0, 300.0, 350.0, 400.0, 450.0, 500.0, 600.0], 200)
+    del ograph
     nhost = 4
     host = [torch.empty((H, W), dtype=torch.int16, pin_memory=True) for _ in range(nhost)]
     for j in range(nhost):
@@ -402,6 +428,8 @@ def suite_live21mp(args, dev):
                     "recirculation_area_cm2": round(float(eager["area"].item()) * 1e4, 3)}
     return {"metric": "live steps/s (5120x4096 + 2048^2 + 1024^2 uneven batch per step, hipGraph)",
             "value": round(1.0 / best, 1), "unit": "steps/s", "steps": steps, "best": best_key,
+            "tuning_table": tables,
+            "overrun_sweep": overrun,
             "gvectors_per_s": round(vec / best / 1e9, 3), "steps_per_s_by_config": per,
             "fields_per_s_each_size": round(1.0 / best, 1),
             "step_algorithmic_GBps": round(byts / best / 1e9, 1),
@@ -743,6 +771,148 @@ def run_suite(args):
         print(json.dumps(r), flush=True)
 
 
+def time_gn_launch(ofv, p0, p1, fin, kr, reg_rel, reg_abs, handle, n, graph=True):
+    """Average duration of one full-resolution Gauss-Newton launch (the stage entry point, same launch
+    configuration and decomposition as inside the pipeline): n launches captured back to back in a hipGraph,
+    each of five replays bracketed by HIP events on the stream the kernel is launched on, median replay.
+    Also returns an eager loop of the same calls and event pairs around single eager launches."""
+    import torch
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    for _ in range(3):
+        ofv.stage_gn_iteration(p0, p1, fin, "direct", kr, reg_rel, reg_abs, handle=handle)
+    torch.cuda.synchronize()
+    for a, b in evs:
+        a.record()
+        ofv.stage_gn_iteration(p0, p1, fin, "direct", kr, reg_rel, reg_abs, handle=handle)
+        b.record()
+    torch.cuda.synchronize()
+    pair_s = sum(a.elapsed_time(b) for a, b in evs) / 1e3 / n
+    ev0.record()
+    for _ in range(n):
+        ofv.stage_gn_iteration(p0, p1, fin, "direct", kr, reg_rel, reg_abs, handle=handle)
+    ev1.record()
+    torch.cuda.synchronize()
+    eager_s = ev0.elapsed_time(ev1) / 1e3 / n
+    kern_s = eager_s
+    if graph:
+        kgraph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(kgraph):
+            for _ in range(n):
+                ofv.stage_gn_iteration(p0, p1, fin, "direct", kr, reg_rel, reg_abs, handle=handle)
+        handle.bind_stream()
+        kgraph.replay()
+        torch.cuda.synchronize()
+        reps = []
+        for _ in range(5):
+            ev0.record()
+            kgraph.replay()
+            ev1.record()
+            torch.cuda.synchronize()
+            reps.append(ev0.elapsed_time(ev1))
+        kern_s = sorted(reps)[len(reps) // 2] / 1e3 / n
+        del kgraph
+    return kern_s, eager_s, pair_s
+
+
+def tuned_decomposition(handle, kr, w, h):
+    """Name of the tuned decomposition of the level-0 direct-flow launch, 'auto' if none."""
+    for line in handle.tuning_table().splitlines():
+        f = [int(x) for x in line.split()]
+        if f[0] == kr and f[2] == 1 and f[3] == w and f[4] == h and f[5] == 1:
+            return GN_NAMES[f[6]]
+    return "auto"
+
+
+def valu_ceiling(workload, storage, decomp, px, kern_s):
+    """VALU issue ceiling of the launch: its instructions per pixel (committed SQ_INSTS_VALU summary for the
+    current kernel sources) at the chip's non-packed issue rate, and the fraction of that ceiling reached."""
+    instr = measured_traffic(workload, storage, decomp, kind="valu")
+    if instr is None:
+        return None
+    per_px = instr * 64 / px               # wavefront instructions x 64 lanes
+    ceil_s = px * per_px / VALU_LANE_INSTR_PER_S
+    return {"bound": "alu", "instr_per_px": round(per_px, 1), "peak": VALU_LANE_INSTR_PER_S,
+            "unit": "lane-instr/s", "ceiling_us": round(ceil_s * 1e6, 3), "frac": round(ceil_s / kern_s, 4),
+            "note": "time the launch would take issuing its VALU instructions at the non-packed issue rate, "
+                    "over its measured duration"}
+
+
+def wake_21mp_setup(dev, storage, autotune=True):
+    """5120x4096 12-bit cylinder-wake pair (the live workload's frame) on the device, its normalised planes,
+    a handle tuned on the pair, and the estimated field as the input flow of the level-0 launch."""
+    import paper_2509_25924_amd as ofv
+    import synth
+    from synth.gpu_render import make_pair_device
+    W, H = 5120, 4096
+    flow = synth.CylinderWake(H, W, t=0.0, dmax=10.0)
+    a, b, _ = make_pair_device(H, W, flow, fwhm=2.5, ppp=0.1, seed=4000, bit_depth=12, noise=0.01 * 4095,
+                               device=dev, max_disp=10.0, with_gt=False)
+    prm = {"num_levels": 4, "kernel_radius": 10, "iterations": 3, "norm_radius": 2, "storage": storage}
+    hd = ofv.Handle(W, H, 1)
+    if autotune:
+        fin = hd.autotune(a, b, prm, bit_depth=12, repeats=3)
+    else:
+        fin = ofv.compute_flow(a, b, prm, bit_depth=12, handle=hd)
+    p0 = ofv.stage_normalize(a, 2, 1e-4, storage, bit_depth=12, handle=hd)
+    p1 = ofv.stage_normalize(b, 2, 1e-4, storage, bit_depth=12, handle=hd)
+    return hd, p0, p1, fin.contiguous(), prm
+
+
+def roofline_21mp(dev, storage, launches):
+    """Roofline of the level-0 Gauss-Newton launch at 5120x4096 (KR 10): about 500 MB per launch (FP32), far
+    above the 256 MB Infinity Cache, so the bytes stream from HBM."""
+    import torch
+    W, H = 5120, 4096
+    hd, p0, p1, fin, prm = wake_21mp_setup(dev, storage)
+    decomp = tuned_decomposition(hd, 10, W, H)
+    kern_s, eager_s, _ = time_gn_launch(__import__("paper_2509_25924_amd"), p0, p1, fin, 10, 1e-3, 1e-9, hd,
+                                        launches)
+    s_bytes = 4 if storage == "f32" else 2
+    byts = (2 * s_bytes + 16) * W * H
+    achieved = byts / kern_s / 1e9
+    out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4),
+           "traffic": measured_traffic("wake_21mp", storage, decomp),
+           "kernel": f"Gauss-Newton iteration, {decomp}, KR 10, {storage}, full resolution {W}x{H}",
+           "bytes_per_launch": byts, "us_per_launch": round(kern_s * 1e6, 3), "launches_timed": launches,
+           "timed_as": "median of 5 hipGraph replays of back-to-back launches",
+           "us_eager_loop_per_launch": round(eager_s * 1e6, 3),
+           "workload": "5120x4096 12-bit cylinder-wake pair (live workload frame), L 4, KR 10, IT 3, NR 2; "
+                       "input flow = the estimated field"}
+    out["valu"] = valu_ceiling("wake_21mp", storage, decomp, W * H, kern_s)
+    hd.close()
+    del p0, p1, fin
+    torch.cuda.empty_cache()
+    return out
+
+
+def pmc_probe_21mp(args, dev):
+    """For hardware-counter runs: the 256 MiB elementwise negation and copy (calibration), then the
+    5120x4096 level-0 Gauss-Newton launch (KR 10) 5 times in every decomposition that fits KR 10."""
+    import torch
+    import paper_2509_25924_amd as ofv
+    hd, p0, p1, fin, prm = wake_21mp_setup(dev, args.storage, autotune=False)
+    src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    for variant in GN_NAMES.values():
+        hd.set_gn_variant(variant)
+        for _ in range(5):
+            ofv.stage_gn_iteration(p0, p1, fin, "direct", 10, 1e-3, 1e-9, handle=hd)
+        torch.cuda.synchronize()
+    s_bytes = 4 if args.storage == "f32" else 2
+    print(json.dumps({"pmc_probe": "wake_21mp", "copy_bytes_each_way": src.numel() * 4,
+                      "gn_bytes_per_launch": (2 * s_bytes + 16) * 5120 * 4096}))
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -767,6 +937,13 @@ def main():
         sys.exit(1)
     ofv.load()
     dev = torch.device("cuda:0")
+    if args.workload == "wake_21mp":
+        if not args.pmc_probe:
+            print("--workload wake_21mp is for --pmc-probe runs (the headline's 21 Mp roofline measures it "
+                  "otherwise)", file=sys.stderr)
+            sys.exit(2)
+        pmc_probe_21mp(args, dev)
+        return
     pair, prm, desc, bits = workload(args.workload)
     prm = dict(prm, storage=args.storage)
     h, w = pair.frame0.shape
@@ -855,54 +1032,13 @@ def main():
     p0 = ofv.stage_normalize(f0, prm["norm_radius"], prm["norm_eps"], args.storage, bit_depth=bits, handle=handle)
     p1 = ofv.stage_normalize(f1, prm["norm_radius"], prm["norm_eps"], args.storage, bit_depth=bits, handle=handle)
     fin = out.clone()
-    for _ in range(10):
-        ofv.stage_gn_iteration(p0, p1, fin, "direct", kr, prm["reg_rel"], prm["reg_abs"], handle=handle)
-    # The roofline's launch duration: the launches captured back to back in a
-    # hipGraph (as inside the pipeline), each of five replays bracketed by a
-    # pair of events on the launch stream, so that host-side call overhead
-    # cannot open gaps between them; the median replay is reported.  Two eager figures are reported beside it: an
-    # event pair around each launch (one queue barrier per event) and a pair
-    # around an eager loop of back-to-back calls (host-bound when a call
-    # takes longer to issue than the kernel runs).
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.kernel_launches)]
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    for a, b in evs:
-        a.record()
-        ofv.stage_gn_iteration(p0, p1, fin, "direct", kr, prm["reg_rel"], prm["reg_abs"], handle=handle)
-        b.record()
-    torch.cuda.synchronize()
-    pair_s = sum(a.elapsed_time(b) for a, b in evs) / 1e3 / args.kernel_launches
-    ev0.record()
-    for _ in range(args.kernel_launches):
-        ofv.stage_gn_iteration(p0, p1, fin, "direct", kr, prm["reg_rel"], prm["reg_abs"], handle=handle)
-    ev1.record()
-    torch.cuda.synchronize()
-    eager_s = ev0.elapsed_time(ev1) / 1e3 / args.kernel_launches
-    if graph is not None:
-        kgraph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(kgraph):
-            for _ in range(args.kernel_launches):
-                ofv.stage_gn_iteration(p0, p1, fin, "direct", kr, prm["reg_rel"], prm["reg_abs"], handle=handle)
-        handle.bind_stream()
-        kgraph.replay()
-        torch.cuda.synchronize()
-        reps = []
-        for _ in range(5):
-            ev0.record()
-            kgraph.replay()
-            ev1.record()
-            torch.cuda.synchronize()
-            reps.append(ev0.elapsed_time(ev1))
-        kern_s = sorted(reps)[len(reps) // 2] / 1e3 / args.kernel_launches
-        del kgraph
-    else:
-        kern_s = eager_s
+    kern_s, eager_s, pair_s = time_gn_launch(ofv, p0, p1, fin, kr, prm["reg_rel"], prm["reg_abs"], handle,
+                                             args.kernel_launches, graph=graph is not None)
     # practical HBM ceiling for context: a 256 MiB device-to-device copy (512 MiB moved), event-timed
     csrc = torch.empty(64 << 20, dtype=torch.float32, device=dev)
     cdst = torch.empty_like(csrc)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
     for _ in range(3):
         cdst.copy_(csrc)
     ev0.record()
@@ -914,11 +1050,7 @@ def main():
     del csrc, cdst
     decomp = args.variant
     if args.variant == "tuned":
-        decomp = "auto"
-        for line in handle.tuning_table().splitlines():
-            f = [int(x) for x in line.split()]
-            if f[0] == kr and f[2] == 1 and f[3] == w and f[4] == h and f[5] == 1:
-                decomp = GN_NAMES[f[6]]
+        decomp = tuned_decomposition(handle, kr, w, h)
     if decomp == "auto":
         decomp = "march" if w * h >= (3 << 20) else "tile64x16"
     s_bytes = 4 if args.storage == "f32" else 2
@@ -970,8 +1102,16 @@ def main():
                      "timed_as": "median of 5 hipGraph replays of back-to-back launches" if graph is not None else "eager loop",
                      "us_eager_loop_per_launch": round(eager_s * 1e6, 3),
                      "us_event_pair_per_launch": round(pair_s * 1e6, 3),
-                     "stream_copy_GBps": round(copy_gbps, 1)},
+                     "stream_copy_GBps": round(copy_gbps, 1),
+                     "working_set_MB": round(algo_bytes / 1e6, 1),
+                     "cache_resident": "the launch's working set fits the 256 MB Infinity Cache, so back-to-back "
+                                       "launches are served partly from it; roofline_21mp is the HBM-bound "
+                                       "measurement",
+                     "valu": valu_ceiling(args.workload, args.storage, decomp, w * h, kern_s)},
     }
+    if not args.no_21mp:
+        for st in ("f32", "bf16"):
+            result[f"roofline_21mp_{st}"] = roofline_21mp(dev, st, 20)
 
     if not args.no_cpu_baseline:
         import oracle

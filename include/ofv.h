@@ -30,6 +30,14 @@
  *   along +y (rows); V maps frame0 to frame1 and is defined at the
  *   midpoint of the two frames (Eq. of_symmetric).
  * - A handle must not be used from two threads at once.
+ * - Fault injection for tests: the environment variable OFV_FAULT_INJECT,
+ *   read at every call, may name "alloc" (device allocations fail:
+ *   OFV_ERR_OUT_OF_MEMORY), "launch" (compute and stage calls fail with
+ *   OFV_ERR_DEVICE after validation, before anything is enqueued, so
+ *   nothing is written) and "sync" (every synchronisation of the library,
+ *   in ofv_destroy, ofv_autotune and a reservation-replacing
+ *   ofv_reserve_backward, reports OFV_ERR_DEVICE; ofv_destroy still
+ *   releases everything), alone or together (e.g. "alloc,sync").
  */
 #ifndef OFV_H
 #define OFV_H
@@ -251,6 +259,15 @@ ofv_status ofv_set_gn_variant(ofv_handle h, int variant, int tile_h);
  * set-up, not inside graph capture.  1 <= repeats <= 1000. */
 ofv_status ofv_autotune(ofv_handle h, const ofv_image* frame0, const ofv_image* frame1, const ofv_params* params,
                         float* flow_out, int repeats);
+
+/* The autotuner on a batch: as ofv_autotune, with n pairs (possibly of
+ * different sizes) computed together as ofv_compute_flow_batch computes
+ * them, so the recorded choices are keyed by the batch's launch groups
+ * (largest level size in the group, batch size n) and later batch calls of
+ * the same geometry use them.  Arrays as ofv_compute_flow_batch (no initial
+ * fields); 1 <= n <= max_batch. */
+ofv_status ofv_autotune_batch(ofv_handle h, int n, const ofv_image* frame0, const ofv_image* frame1,
+                              const ofv_params* params, float* const* flow_out, int repeats);
 
 /* The tuned table as text, one entry per line:
  * "kr storage mode width height batch variant tile_h".  Writes at most cap

@@ -57,6 +57,8 @@ EXPORTS = {
                                        POINTER(c_void_p), POINTER(c_void_p)]),
     "ofv_compute_flow_static": (c_int, [POINTER(OfvImage), POINTER(OfvImage), POINTER(OfvParams), c_void_p,
                                         c_void_p]),
+    "ofv_autotune_batch": (c_int, [c_void_p, c_int, POINTER(OfvImage), POINTER(OfvImage), POINTER(OfvParams),
+                                   POINTER(c_void_p), c_int]),
     "ofv_destroy": (c_int, [c_void_p]),
     "ofv_reserve_backward": (c_int, [c_void_p, c_int, c_int]),
     "ofv_compute_flow_backward": (c_int, [c_void_p, POINTER(OfvImage), POINTER(OfvImage), POINTER(OfvParams),

@@ -73,6 +73,20 @@ class Handle:
               self.ptr)
         return out
 
+    def autotune_batch(self, frames0: Sequence[torch.Tensor], frames1: Sequence[torch.Tensor], params: Dict,
+                       bit_depth: Optional[int] = None, repeats: int = 3) -> List[torch.Tensor]:
+        """Time every decomposition on this batch (computed as compute_flow_batch computes it) and keep the
+        fastest per launch group (synchronises)."""
+        self.bind_stream()
+        n = len(frames0)
+        outs = [torch.empty((2,) + tuple(f.shape), dtype=torch.float32, device=f.device) for f in frames0]
+        arr0 = (OfvImage * n)(*[image_desc(f, bit_depth) for f in frames0])
+        arr1 = (OfvImage * n)(*[image_desc(f, bit_depth) for f in frames1])
+        out_ptrs = (c_void_p * n)(*[o.data_ptr() for o in outs])
+        p = params_struct(params)
+        check(load().ofv_autotune_batch(self.ptr, n, arr0, arr1, byref(p), out_ptrs, int(repeats)), self.ptr)
+        return outs
+
     def tuning_table(self) -> str:
         need = c_size_t()
         check(load().ofv_tuning_export(self.ptr, None, 0, byref(need)), self.ptr)

@@ -106,6 +106,14 @@ bool fault_injected(const char* what) {
   return e && std::strstr(e, what) != nullptr;
 }
 
+// The library's only synchronisation points (ofv_destroy, ofv_autotune, a
+// reserve_backward that replaces a smaller reservation) go through this;
+// OFV_FAULT_INJECT=sync makes each report a device error.
+hipError_t sync_stream(hipStream_t s) {
+  if (fault_injected("sync")) return hipErrorLaunchFailure;
+  return hipStreamSynchronize(s);
+}
+
 // Makes the handle's device current for the duration of a call.
 struct DeviceGuard {
   int prev = -1;
@@ -877,7 +885,7 @@ ofv_status ofv_reserve_backward(ofv_handle h, int max_levels, int max_iterations
   const size_t plane0 = static_cast<size_t>(h->lpitch[0]) * h->lh[0];
   const size_t floats = bw_saved_floats(h, max_levels, max_iterations) + kBwPlanes * plane0 + h->frame_bytes / 2;
   if (h->bw) {
-    if (hipStreamSynchronize(h->stream) != hipSuccess || hipFree(h->bw) != hipSuccess)
+    if (sync_stream(h->stream) != hipSuccess || hipFree(h->bw) != hipSuccess)
       return fail(h, OFV_ERR_DEVICE, "releasing the previous backward workspace failed");
     h->bw = nullptr;
     h->bw_bytes = 0;
@@ -1138,9 +1146,11 @@ ofv_status ofv_compute_flow_backward(ofv_handle h, const ofv_image* frame0, cons
 ofv_status ofv_destroy(ofv_handle h) {
   if (!h) return OFV_OK;
   ofv_status r = OFV_OK;
+  // a validation-only handle has no stream to drain, but an injected sync failure is reported all the same
+  if (h->device < 0 && fault_injected("sync")) r = OFV_ERR_DEVICE;
   if (h->device >= 0) {
     DeviceGuard g(h->device);
-    if (hipStreamSynchronize(h->stream) != hipSuccess) r = OFV_ERR_DEVICE;
+    if (sync_stream(h->stream) != hipSuccess) r = OFV_ERR_DEVICE;
     for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
     if (h->bw && hipFree(h->bw) != hipSuccess) r = OFV_ERR_DEVICE;
     if (h->ws && hipFree(h->ws) != hipSuccess) r = OFV_ERR_DEVICE;
@@ -1292,14 +1302,19 @@ ofv_status ofv_set_gn_variant(ofv_handle h, int variant, int tile_h) {
   return OFV_OK;
 }
 
-ofv_status ofv_autotune(ofv_handle h, const ofv_image* frame0, const ofv_image* frame1, const ofv_params* params,
-                        float* flow_out, int repeats) {
+namespace {
+
+// Times every candidate decomposition on the n pairs (one batch call per
+// run, so the launch groups and their keys are the batch's) and records the
+// fastest per key in the handle.
+ofv_status autotune_impl(ofv_handle h, int n, const ofv_image* frame0, const ofv_image* frame1,
+                         const ofv_params* params, float* const* flow_out, int repeats) {
   if (check_handle(h) != OFV_OK) return OFV_ERR_INVALID_ARG;
   if (repeats < 1 || repeats > 1000) return fail(h, OFV_ERR_INVALID_ARG, "repeats %d outside 1..1000", repeats);
   if (params && (params->flags & (OFV_FLAG_FORWARD_ADDITIVE | OFV_FLAG_INCREMENT_UPDATE)))
     return fail(h, OFV_ERR_UNSUPPORTED, "the autotuner times the symmetric estimator's decompositions");
   // validate exactly like a compute call (the validation-only handle stops there)
-  ofv_status r = compute_common(h, 1, frame0, frame1, params, nullptr, &flow_out);
+  ofv_status r = compute_common(h, n, frame0, frame1, params, nullptr, flow_out);
   if (r != OFV_OK) return r;
   DeviceGuard g(h->device);
   struct Cand {
@@ -1322,11 +1337,11 @@ ofv_status ofv_autotune(ofv_handle h, const ofv_image* frame0, const ofv_image* 
       h->capture = k >= 0;
       h->events_used = 0;
       h->recs.clear();
-      r = compute_common(h, 1, frame0, frame1, params, nullptr, &flow_out);
+      r = compute_common(h, n, frame0, frame1, params, nullptr, flow_out);
       h->capture = false;
       if (r != OFV_OK) break;
       if (k < 0) continue;
-      if (hipStreamSynchronize(h->stream) != hipSuccess) {
+      if (sync_stream(h->stream) != hipSuccess) {
         r = fail(h, OFV_ERR_DEVICE, "synchronisation failed while tuning");
         break;
       }
@@ -1358,6 +1373,18 @@ ofv_status ofv_autotune(ofv_handle h, const ofv_image* frame0, const ofv_image* 
   if (r != OFV_OK) return r;
   for (const auto& kv : best) h->tuned[kv.first] = kv.second.second;
   return OFV_OK;
+}
+
+}  // namespace
+
+ofv_status ofv_autotune(ofv_handle h, const ofv_image* frame0, const ofv_image* frame1, const ofv_params* params,
+                        float* flow_out, int repeats) {
+  return autotune_impl(h, 1, frame0, frame1, params, &flow_out, repeats);
+}
+
+ofv_status ofv_autotune_batch(ofv_handle h, int n, const ofv_image* frame0, const ofv_image* frame1,
+                              const ofv_params* params, float* const* flow_out, int repeats) {
+  return autotune_impl(h, n, frame0, frame1, params, flow_out, repeats);
 }
 
 ofv_status ofv_tuning_export(ofv_handle h, char* buf, size_t cap, size_t* needed) {

@@ -334,3 +334,20 @@ def test_static_entry_point_validation(lib, monkeypatch):
     monkeypatch.setenv("OFV_FAULT_INJECT", "launch")
     assert call(fit0, fit1, _params(), out=0x80000000) == _lib.OFV_ERR_DEVICE
     assert b"injected" in lib.ofv_last_error(None)
+
+
+def test_sync_fault_injection_on_destroy(lib, monkeypatch):
+    """OFV_FAULT_INJECT=sync: the synchronisation in ofv_destroy reports a device error (the handle is
+    released all the same); without the injection the same call succeeds."""
+    h = c_void_p()
+    assert lib.ofv_create(byref(h), -1, 64, 64, 1, None) == _lib.OFV_OK
+    monkeypatch.setenv("OFV_FAULT_INJECT", "sync")
+    assert lib.ofv_destroy(h) == _lib.OFV_ERR_DEVICE
+    monkeypatch.setenv("OFV_FAULT_INJECT", "alloc,sync")
+    h2 = c_void_p()
+    assert lib.ofv_create(byref(h2), -1, 64, 64, 1, None) == _lib.OFV_OK   # validation-only: nothing allocated
+    assert lib.ofv_destroy(h2) == _lib.OFV_ERR_DEVICE
+    monkeypatch.delenv("OFV_FAULT_INJECT")
+    h3 = c_void_p()
+    assert lib.ofv_create(byref(h3), -1, 64, 64, 1, None) == _lib.OFV_OK
+    assert lib.ofv_destroy(h3) == _lib.OFV_OK
