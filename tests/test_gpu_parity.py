@@ -647,3 +647,26 @@ def test_batched_turbulence_2048_fp16_at_its_shape(ofv):
         assert np.quantile(d_gpu, 0.999) <= 2 * np.quantile(d_floor, 0.999) + 1e-3
         assert rms(got) <= 1.05 * rms(ref)
     h.close()
+
+
+def test_autotune_batch_uneven(ofv):
+    """ofv_autotune_batch on an uneven batch: the table is keyed by the batch's launch groups
+    (batch size 3), later batch calls use it, and every pair still matches the oracle."""
+    say("autotune an uneven batch")
+    sizes = [(256, 320), (128, 128), (96, 200)]
+    pairs = [synth.make_pair(h, w, synth.Translation(0.8, -0.5), fwhm=2.5, ppp=0.1, seed=900 + k, bit_depth=8,
+                             noise=2.0) for k, (h, w) in enumerate(sizes)]
+    prm = {"num_levels": 3, "kernel_radius": 4, "iterations": 3, "norm_radius": 1}
+    f0 = [dev_tensor(p.frame0) for p in pairs]
+    f1 = [dev_tensor(p.frame1) for p in pairs]
+    h = ofv.Handle(320, 256, 3)
+    h.autotune_batch(f0, f1, prm, bit_depth=8, repeats=2)
+    lines = [l.split() for l in h.tuning_table().splitlines() if l.strip()]
+    assert lines and all(int(l[5]) == 3 for l in lines)
+    got = ofv.compute_flow_batch(f0, f1, prm, bit_depth=8, handle=h)
+    for k, p in enumerate(pairs):
+        ref = oracle.compute_flow(p.frame0, p.frame1, prm, bit_depth0=8)
+        err = torch.max(torch.abs(o64(got[k]) - ref)).item()
+        say(f"  pair {k} {sizes[k]}: max |dV| = {err:.2e}")
+        assert err <= FLOW_TOL
+    h.close()
