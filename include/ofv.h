@@ -36,7 +36,7 @@
  *   OFV_ERR_DEVICE after validation, before anything is enqueued, so
  *   nothing is written) and "sync" (every synchronisation of the library,
  *   in ofv_destroy, ofv_autotune and a reservation-replacing
- *   ofv_reserve_backward, reports OFV_ERR_DEVICE; ofv_destroy still
+ *   ofv_reserve_backward(_ex), reports OFV_ERR_DEVICE; ofv_destroy still
  *   releases everything), alone or together (e.g. "alloc,sync").
  */
 #ifndef OFV_H
@@ -94,7 +94,8 @@ typedef struct {
   float reg_abs;         /* >= 0, typical 1e-9; reg_rel = reg_abs = 0 gives NaN on textureless windows */
   int32_t storage;       /* ofv_storage */
   uint32_t flags;        /* 0 or an OR of OFV_FLAG_FORWARD_ADDITIVE, OFV_FLAG_INCREMENT_UPDATE,
-                            OFV_FLAG_NO_FP64_FALLBACK */
+                            OFV_FLAG_NO_FP64_FALLBACK, OFV_FLAG_STORE_ALL, OFV_FLAG_SAVE_ITERATES,
+                            OFV_FLAG_SAVED_FORWARD */
 } ofv_params;
 
 /* params.flags: the forward-additive Lucas-Kanade estimator that the paper
@@ -125,6 +126,36 @@ typedef struct {
  * 1e-2 have the determinant and the solution recomputed in float64 from the
  * float32 sums).  For A/B comparisons of the fallback's effect. */
 #define OFV_FLAG_NO_FP64_FALLBACK 4u
+
+/* params.flags, read by the backward calls only (the forward ignores it):
+ * store instead of recompute.  The backward's forward pass then keeps, per
+ * level and iteration, the five window sums and Gx, Gy, b of every pixel (40
+ * bytes per pixel with the output field, against 8 when recomputing), and
+ * the adjoint reads them back instead of re-warping and re-summing.  Needs a
+ * reservation made with OFV_BACKWARD_STORE_ALL. */
+#define OFV_FLAG_STORE_ALL 8u
+
+/* params.flags of the forward calls (ofv_compute_flow, _ex, _batch): also
+ * keep every iteration's output field in the handle's backward workspace
+ * (the last one of level 0 is flow_out itself), as the backward's own
+ * forward pass does, so that a backward call with OFV_FLAG_SAVED_FORWARD on
+ * the same inputs can skip that pass (the usual forward-then-backward of
+ * training).  Costs what a plain forward costs.  With OFV_FLAG_STORE_ALL
+ * the store-all record is kept too.  Needs a reservation covering the
+ * levels, iterations, pairs and mode, F32 storage and the symmetric
+ * estimator's consistent update (OFV_ERR_CAPACITY / OFV_ERR_UNSUPPORTED
+ * otherwise); ofv_compute_flow_static, ofv_stream_push and the autotuner
+ * reject it. */
+#define OFV_FLAG_SAVE_ITERATES 16u
+
+/* params.flags of the backward calls: skip the forward pass where the handle
+ * holds the iterates of a forward with OFV_FLAG_SAVE_ITERATES (or of a
+ * backward call) on the same inputs: the same frame and initial-field
+ * pointers, sizes, pitches and types, and the same parameters (these two
+ * flags aside).  Any other forward call on the handle, and a new
+ * reservation, discard them; the backward then runs the forward itself.  The
+ * frames and initial fields must not have been modified since. */
+#define OFV_FLAG_SAVED_FORWARD 32u
 
 /* Fill *p with the defaults: 3 levels, KR 4, IT 3, NR 1, eps 1e-4,
  * reg_rel 1e-3, reg_abs 1e-9, F32 storage.  p == NULL is ignored. */
@@ -191,12 +222,28 @@ ofv_status ofv_compute_flow_batch(ofv_handle h, int n, const ofv_image* frame0, 
 ofv_status ofv_compute_flow_static(const ofv_image* frame0, const ofv_image* frame1, const ofv_params* params,
                                    float* flow_out, void* stream);
 
-/* Reserve device memory for ofv_compute_flow_backward on pairs up to the
- * handle's max size with up to max_levels levels and max_iterations
- * iterations per level: the output field of every iteration (8 bytes per
- * pixel of each level per iteration), 41 scratch planes and two gradient
- * pyramids.  A set-up call: it allocates (and may synchronise to release a
- * smaller reservation). */
+/* ofv_reserve_backward_ex mode: also reserve the store-all record (OFV_FLAG_STORE_ALL). */
+#define OFV_BACKWARD_STORE_ALL 1u
+
+/* Device bytes that ofv_reserve_backward_ex(h, max_levels, max_iterations,
+ * max_pairs, mode) allocates, for pairs up to the handle's max size: per
+ * pair the output field of every iteration of every level (8 bytes per
+ * pixel of the level per iteration), with OFV_BACKWARD_STORE_ALL also the
+ * record (32 bytes per pixel per iteration, and the first iteration's input
+ * field per level), 15 level-0 scratch planes, and two image-gradient
+ * pyramids.  No allocation. */
+ofv_status ofv_backward_workspace_bytes(ofv_handle h, int max_levels, int max_iterations, int max_pairs,
+                                        uint32_t mode, size_t* bytes);
+
+/* Reserve device memory for the backward calls on batches of up to
+ * max_pairs pairs (at most the handle's max_batch) with up to max_levels
+ * levels and max_iterations iterations per level; mode 0 or
+ * OFV_BACKWARD_STORE_ALL.  A set-up call: it allocates, and to replace a
+ * smaller reservation it synchronises the handle's stream and frees it (the
+ * new one covers both).  Reserving no more than is held does nothing. */
+ofv_status ofv_reserve_backward_ex(ofv_handle h, int max_levels, int max_iterations, int max_pairs, uint32_t mode);
+
+/* ofv_reserve_backward_ex(h, max_levels, max_iterations, 1, 0). */
 ofv_status ofv_reserve_backward(ofv_handle h, int max_levels, int max_iterations);
 
 /* Reverse-mode derivative of the whole estimator (normalisation, pyramid,
@@ -205,17 +252,30 @@ ofv_status ofv_reserve_backward(ofv_handle h, int max_levels, int max_iterations
  *   grad_frame0, grad_frame1: dL/dframe, device float32 [H][W] (row pitch W),
  *     in the frames' own units (integer frames: per digital number);
  *   grad_flow_init: dL/dflow_init, device float32 [2][H][W] (needs flow_init).
- * Each output may be NULL.  The forward is re-run first, keeping only each
- * iteration's output field; warps, gradients, products and window sums are
- * recomputed per iteration rather than stored.  The image gradients are
- * accumulated with float atomics, so results are reproducible only up to
- * summation order.  Needs F32 storage (OFV_ERR_UNSUPPORTED otherwise) and a
- * prior ofv_reserve_backward covering the levels and iterations
- * (OFV_ERR_CAPACITY otherwise).  Enqueues only: no allocation, no sync.
- * Outputs must not overlap the inputs or each other. */
+ * Each output may be NULL.  The forward is re-run first (unless
+ * OFV_FLAG_SAVED_FORWARD finds it saved), keeping only each iteration's
+ * output field; the adjoint of each iteration recomputes the
+ * warps, gradients, products and window sums of its tiles in on-chip memory
+ * (or, with OFV_FLAG_STORE_ALL, reads the stored record).  The image
+ * gradients are accumulated with float atomics, so results are
+ * reproducible only up to summation order.  Needs the symmetric
+ * estimator's consistent update and F32 storage (OFV_ERR_UNSUPPORTED
+ * otherwise) and a reservation covering the levels, iterations, one pair and
+ * the mode (OFV_ERR_CAPACITY otherwise).  Enqueues only: no allocation, no
+ * sync.  Outputs must not overlap the inputs or each other. */
 ofv_status ofv_compute_flow_backward(ofv_handle h, const ofv_image* frame0, const ofv_image* frame1,
                                      const ofv_params* params, const float* flow_init, const float* grad_flow,
                                      float* grad_frame0, float* grad_frame1, float* grad_flow_init);
+
+/* ofv_compute_flow_backward over n pairs (sizes may differ), each stage one
+ * launch for up to 16 pairs: frames0[i], frames1[i], grad_flow[i]; the
+ * pointer arrays flow_init, grad_frame0, grad_frame1 and grad_flow_init may
+ * each be NULL (no pair has one) or hold NULL entries.  The reservation must
+ * cover n pairs.  No output may overlap any input or output of the batch. */
+ofv_status ofv_compute_flow_backward_batch(ofv_handle h, int n, const ofv_image* frames0, const ofv_image* frames1,
+                                           const ofv_params* params, const float* const* flow_init,
+                                           const float* const* grad_flow, float* const* grad_frame0,
+                                           float* const* grad_frame1, float* const* grad_flow_init);
 
 /* Work decompositions of the fused Gauss-Newton kernel, chosen per pyramid
  * level and input-flow mode.  All give the same results up to float32

@@ -20,7 +20,8 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libofv.so")
 ARCH = os.environ.get("OFV_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["ofv_api.cpp", "ofv_kernels.hip", "ofv_adjoint.hip", "ofv_derived.hip"] + [f"ofv_{k}_{st}_{md}.hip" for k in ("gn", "gnt")
+SOURCES = ["ofv_api.cpp", "ofv_kernels.hip", "ofv_adjoint.hip", "ofv_adj_sums.hip", "ofv_adj_scatter.hip",
+           "ofv_derived.hip"] + [f"ofv_{k}_{st}_{md}.hip" for k in ("gn", "gnt")
                                                 for st in ("f32", "f16", "bf16")
                                                 for md in ("zero", "direct", "upsample")]
 

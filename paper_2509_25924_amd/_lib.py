@@ -22,6 +22,10 @@ MAX_LEVELS = 16
 FLAG_FORWARD_ADDITIVE = 1
 FLAG_INCREMENT_UPDATE = 2
 FLAG_NO_FP64_FALLBACK = 4
+FLAG_STORE_ALL = 8
+FLAG_SAVE_ITERATES = 16
+FLAG_SAVED_FORWARD = 32
+BACKWARD_STORE_ALL = 1
 MAX_KERNEL_RADIUS = 12
 MAX_NORM_RADIUS = 16
 GN_VARIANTS = {"auto": -1, "march": 0, "tile64x32": 1, "tile64x16": 2, "tile32x16": 3, "tile16x16": 4,
@@ -61,6 +65,11 @@ EXPORTS = {
                                    POINTER(c_void_p), c_int]),
     "ofv_destroy": (c_int, [c_void_p]),
     "ofv_reserve_backward": (c_int, [c_void_p, c_int, c_int]),
+    "ofv_reserve_backward_ex": (c_int, [c_void_p, c_int, c_int, c_int, c_uint32]),
+    "ofv_backward_workspace_bytes": (c_int, [c_void_p, c_int, c_int, c_int, c_uint32, POINTER(c_size_t)]),
+    "ofv_compute_flow_backward_batch": (c_int, [c_void_p, c_int, POINTER(OfvImage), POINTER(OfvImage),
+                                                POINTER(OfvParams), POINTER(c_void_p), POINTER(c_void_p),
+                                                POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p)]),
     "ofv_compute_flow_backward": (c_int, [c_void_p, POINTER(OfvImage), POINTER(OfvImage), POINTER(OfvParams),
                                           c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "ofv_set_gn_variant": (c_int, [c_void_p, c_int, c_int]),

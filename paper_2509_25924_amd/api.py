@@ -52,9 +52,19 @@ class Handle:
         check(load().ofv_workspace_bytes(self.ptr, byref(n)), self.ptr)
         return n.value
 
-    def reserve_backward(self, levels: int, iterations: int) -> None:
-        """Allocate the adjoint's workspace for up to `levels` x `iterations` (set-up call)."""
-        check(load().ofv_reserve_backward(self.ptr, int(levels), int(iterations)), self.ptr)
+    def reserve_backward(self, levels: int, iterations: int, pairs: int = 1, store_all: bool = False) -> None:
+        """Allocate the adjoint's workspace for batches of up to `pairs` pairs with up to `levels` x
+        `iterations`, with the store-all record if asked (set-up call)."""
+        mode = _lib.BACKWARD_STORE_ALL if store_all else 0
+        check(load().ofv_reserve_backward_ex(self.ptr, int(levels), int(iterations), int(pairs), mode), self.ptr)
+
+    def backward_workspace_bytes(self, levels: int, iterations: int, pairs: int = 1, store_all: bool = False) -> int:
+        """Device bytes reserve_backward would allocate for these limits (no allocation)."""
+        out = c_size_t()
+        mode = _lib.BACKWARD_STORE_ALL if store_all else 0
+        check(load().ofv_backward_workspace_bytes(self.ptr, int(levels), int(iterations), int(pairs), mode,
+                                                  byref(out)), self.ptr)
+        return int(out.value)
 
     def set_gn_variant(self, variant: str = "auto", tile_h: int = 0) -> None:
         """Force a work decomposition of the Gauss-Newton kernel ('auto', 'march', 'tile64x32', 'tile64x16',
@@ -186,17 +196,28 @@ def params_struct(params: Dict) -> OfvParams:
         p.flags |= _lib.FLAG_INCREMENT_UPDATE
     if not params.get("fp64_fallback", True):
         p.flags |= _lib.FLAG_NO_FP64_FALLBACK
+    if params.get("store_all", False):
+        p.flags |= _lib.FLAG_STORE_ALL
+    if params.get("save_iterates", False):
+        p.flags |= _lib.FLAG_SAVE_ITERATES
+    if params.get("saved_forward", False):
+        p.flags |= _lib.FLAG_SAVED_FORWARD
     return p
 
 
 def compute_flow(frame0: torch.Tensor, frame1: torch.Tensor, params: Dict, flow_init: Optional[torch.Tensor] = None,
                  bit_depth: Optional[int] = None, out: Optional[torch.Tensor] = None,
                  handle: Optional[Handle] = None) -> torch.Tensor:
-    """Dense flow [2, H, W] float32 (u, v in px/frame) of one pair."""
+    """Dense flow [2, H, W] float32 (u, v in px/frame) of one pair.  params["save_iterates"] keeps the
+    iterates in the handle's backward workspace for a following backward with params["saved_forward"]
+    (reserves it first)."""
     h, w = frame0.shape
     hd = handle or default_handle(w, h, 1, frame0.device.index)
     if handle is not None:
         hd.bind_stream()
+    if params.get("save_iterates", False):
+        hd.reserve_backward(params.get("num_levels", 3), params.get("iterations", 3),
+                            store_all=bool(params.get("store_all", False)))
     if out is None:
         out = torch.empty((2, h, w), dtype=torch.float32, device=frame0.device)
     _check_flow(out, h, w, "out")
@@ -234,7 +255,8 @@ def compute_flow_batch(frames0: Sequence[torch.Tensor], frames1: Sequence[torch.
                        flow_init: Optional[Sequence[Optional[torch.Tensor]]] = None, bit_depth: Optional[int] = None,
                        outs: Optional[Sequence[torch.Tensor]] = None, handle: Optional[Handle] = None
                        ) -> List[torch.Tensor]:
-    """Dense flows of n pairs (sizes may differ), each stage one launch over all pairs."""
+    """Dense flows of n pairs (sizes may differ), each stage one launch over all pairs (params["save_iterates"]
+    as for compute_flow)."""
     n = len(frames0)
     if n != len(frames1):
         raise ValueError("frames0 and frames1 differ in length")
@@ -243,6 +265,9 @@ def compute_flow_batch(frames0: Sequence[torch.Tensor], frames1: Sequence[torch.
     hd = handle or default_handle(mw, mh, n, frames0[0].device.index)
     if handle is not None:
         hd.bind_stream()
+    if params.get("save_iterates", False):
+        hd.reserve_backward(params.get("num_levels", 3), params.get("iterations", 3), pairs=n,
+                            store_all=bool(params.get("store_all", False)))
     if outs is None:
         outs = [torch.empty((2,) + tuple(f.shape), dtype=torch.float32, device=f.device) for f in frames0]
     arr0 = (OfvImage * n)(*[image_desc(f, bit_depth) for f in frames0])
@@ -262,12 +287,16 @@ def compute_flow_backward(frame0: torch.Tensor, frame1: torch.Tensor, params: Di
     """Hand-written adjoint: (dL/dframe0, dL/dframe1, dL/dflow_init) for dL/dflow = grad_flow.
 
     Frame gradients are float32 [H, W] in the frames' own units; entries not
-    requested (or dL/dflow_init without flow_init) are None.
+    requested (or dL/dflow_init without flow_init) are None.  params["store_all"] selects the
+    store-all mode; params["saved_forward"] skips the forward pass where the handle holds the
+    iterates of a saving forward (params["save_iterates"]) on the same inputs.
     """
     h, w = frame0.shape
     hd = handle or default_handle(w, h, 1, frame0.device.index)
     hd.bind_stream()
-    hd.reserve_backward(params.get("num_levels", 3), params.get("iterations", 3))
+    hd.reserve_backward(params.get("num_levels", 3), params.get("iterations", 3),
+                        store_all=bool(params.get("store_all", False)))
+    params = {k: v for k, v in params.items() if k != "save_iterates"}
     _check_flow(grad_flow, h, w, "grad_flow")
     g0 = torch.empty((h, w), dtype=torch.float32, device=frame0.device) if need_frames else None
     g1 = torch.empty((h, w), dtype=torch.float32, device=frame0.device) if need_frames else None
@@ -284,20 +313,69 @@ def compute_flow_backward(frame0: torch.Tensor, frame1: torch.Tensor, params: Di
     return g0, g1, gi
 
 
+def compute_flow_backward_batch(frames0: Sequence[torch.Tensor], frames1: Sequence[torch.Tensor], params: Dict,
+                                grad_flows: Sequence[torch.Tensor],
+                                flow_init: Optional[Sequence[Optional[torch.Tensor]]] = None,
+                                bit_depth: Optional[int] = None, need_frames: bool = True, need_init: bool = True,
+                                handle: Optional[Handle] = None):
+    """The adjoint of n pairs (sizes may differ), each stage one launch over all pairs: lists of
+    dL/dframe0, dL/dframe1, dL/dflow_init (None where not requested or without flow_init).
+    params["store_all"] selects the store-all mode."""
+    n = len(frames0)
+    if n != len(frames1) or n != len(grad_flows):
+        raise ValueError("frames0, frames1 and grad_flows differ in length")
+    mw = max(f.shape[1] for f in frames0)
+    mh = max(f.shape[0] for f in frames0)
+    hd = handle or default_handle(mw, mh, n, frames0[0].device.index)
+    hd.bind_stream()
+    hd.reserve_backward(params.get("num_levels", 3), params.get("iterations", 3), pairs=n,
+                        store_all=bool(params.get("store_all", False)))
+    params = {k: v for k, v in params.items() if k != "save_iterates"}
+    dev = frames0[0].device
+    g0, g1, gi = [None] * n, [None] * n, [None] * n
+    for i in range(n):
+        h, w = frames0[i].shape
+        _check_flow(grad_flows[i], h, w, "grad_flow")
+        if need_frames:
+            g0[i] = torch.empty((h, w), dtype=torch.float32, device=dev)
+            g1[i] = torch.empty((h, w), dtype=torch.float32, device=dev)
+        if flow_init is not None and flow_init[i] is not None:
+            _check_flow(flow_init[i], h, w, "flow_init")
+            if need_init:
+                gi[i] = torch.empty((2, h, w), dtype=torch.float32, device=dev)
+    ptrs = lambda ts: (c_void_p * n)(*[(t.data_ptr() if t is not None else None) for t in ts])  # noqa: E731
+    arr0 = (OfvImage * n)(*[image_desc(f, bit_depth) for f in frames0])
+    arr1 = (OfvImage * n)(*[image_desc(f, bit_depth) for f in frames1])
+    p = params_struct(params)
+    check(load().ofv_compute_flow_backward_batch(hd.ptr, n, arr0, arr1, byref(p),
+                                                 ptrs(flow_init) if flow_init is not None else None,
+                                                 ptrs(grad_flows), ptrs(g0) if need_frames else None,
+                                                 ptrs(g1) if need_frames else None,
+                                                 ptrs(gi) if any(t is not None for t in gi) else None), hd.ptr)
+    return g0, g1, gi
+
+
 class OFVFunction(torch.autograd.Function):
     """Dense flow with gradients w.r.t. both frames and the initial field.
 
     ``OFVFunction.apply(frame0, frame1, flow_init, params, handle)``; frames
     are float32 [H, W] device tensors (integer frames give no frame
-    gradient), flow_init is None or float32 [2, H, W].  The backward calls the
-    library's hand-written adjoint (recompute mode).
+    gradient), flow_init is None or float32 [2, H, W].  The forward keeps its
+    iterates in the handle's backward workspace; the backward calls the
+    library's hand-written adjoint on them (recompute mode; it re-runs the
+    forward itself if another forward on the handle has replaced them).
     """
 
     @staticmethod
     def forward(ctx, frame0, frame1, flow_init, params, handle=None):
-        out = compute_flow(frame0, frame1, params, flow_init=flow_init, handle=handle)
-        ctx.params = dict(params)
-        ctx.handle = handle
+        h, w = frame0.shape
+        hd = handle or default_handle(w, h, 1, frame0.device.index)
+        # the iterates are kept where the adjoint can use them (its estimator and storage)
+        keep = (params.get("storage", "f32") == "f32" and params.get("estimator", "symmetric") == "symmetric"
+                and params.get("update", "consistent") == "consistent")
+        out = compute_flow(frame0, frame1, dict(params, save_iterates=keep), flow_init=flow_init, handle=hd)
+        ctx.params = dict(params, saved_forward=keep)
+        ctx.handle = hd
         ctx.has_init = flow_init is not None
         ctx.save_for_backward(frame0, frame1, flow_init if flow_init is not None else frame0.new_empty(0))
         return out

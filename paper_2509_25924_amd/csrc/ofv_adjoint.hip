@@ -1,25 +1,18 @@
-// Hand-written adjoint of the estimator (reverse mode, float32).
+// Point-wise pieces of the hand-written adjoint (reverse mode, float32),
+// batched over the pairs of a backward call (one launch per stage, the pair in
+// blockIdx.z or in a job table): the adjoint of the solve from stored window
+// sums (store-all mode), the up-sampling of a level's input field and its
+// transpose, the transpose of REDUCE (image pyramids and the initial-field
+// restriction) and of the local z-score normalisation.  The iteration
+// kernels proper (window sums, warps) are in ofv_adj_tile.h.
 //
-// Forward (section "Live-Optical Flow Velocimetry", Eq. of_symmetric): per
-// pixel k, W0 = P0(k - V/2), W1 = P1(k + V/2) (bilinear, clamped), S = (W0 +
-// W1)/2, T = W1 - W0, G = central difference of S (clamped), b = G.V(k) - T,
-// products p = (Gx^2, GxGy, Gy^2, Gx b, Gy b); per pixel m, sums A = Box(p)
-// over the truncated (2KR+1)^2 window; lam = reg_rel (Sxx + Syy) + reg_abs;
-// (A + lam I) V'(m) = c + lam V(m).  The backward of one iteration recomputes
-// S, T, G, b and the sums from the saved input field V and then applies, in
-// reverse order, the adjoints of the solve, the window sums (a truncated box
-// is its own transpose), the products, b, the central difference, and the two
-// bilinear warps (gathers become float atomic scatter-adds into the image
-// gradients; the sub-pixel weights give the flow gradient).  Also here: the
-// adjoints of up-sampling, REDUCE (and the initial-flow restriction) and the
-// local z-score normalisation.
-//
+// Transposes are written as gathers: every output element collects the
+// weights with which the forward's taps reach it, so no atomics are needed.
 // Derivative conventions follow the forward formulas exactly: clamp passes
 // the gradient where the coordinate lies inside [0, size - 1] (ends
 // included), floor has zero derivative, and a tap repeated at the border
 // receives both of its weights.
-#include "ofv_internal.h"
-#include "ofv_px.h"
+#include "ofv_adj_tile.h"
 
 namespace ofv {
 
@@ -27,7 +20,7 @@ namespace {
 
 constexpr int BX = 64, BY = 4;
 
-dim3 grid2(int w, int h) { return dim3((w + BX - 1) / BX, (h + BY - 1) / BY); }
+dim3 grid3(int w, int h, int n) { return dim3((w + BX - 1) / BX, (h + BY - 1) / BY, n); }
 
 __device__ __forceinline__ bool pix(int& x, int& y, int w, int h) {
   x = blockIdx.x * BX + (threadIdx.x & 63);
@@ -35,209 +28,81 @@ __device__ __forceinline__ bool pix(int& x, int& y, int w, int h) {
   return x < w && y < h;
 }
 
-// Bilinear sample with the forward's clamping; also returns the partial
-// derivatives w.r.t. the (unclamped) coordinates and the four tap weights.
-struct Bil {
-  float val, dx, dy;
-  int o00, o01, o10, o11;
-  float w00, w01, w10, w11;
-};
+// ---------------------------------------------------------------- solve adjoint from stored sums
 
-__device__ __forceinline__ Bil bil_fwd(const float* p, int pitch, int w, int h, float x, float y) {
-  Bil r;
-  const bool inx = x >= 0.0f && x <= static_cast<float>(w - 1);
-  const bool iny = y >= 0.0f && y <= static_cast<float>(h - 1);
-  const float xc = fminf(fmaxf(x, 0.0f), static_cast<float>(w - 1));
-  const float yc = fminf(fmaxf(y, 0.0f), static_cast<float>(h - 1));
-  const float xf = floorf(xc), yf = floorf(yc);
-  const float fx = xc - xf, fy = yc - yf;
-  const int ix0 = static_cast<int>(xf), iy0 = static_cast<int>(yf);
-  const int ix1 = min(ix0 + 1, w - 1), iy1 = min(iy0 + 1, h - 1);
-  r.o00 = iy0 * pitch + ix0;
-  r.o01 = iy0 * pitch + ix1;
-  r.o10 = iy1 * pitch + ix0;
-  r.o11 = iy1 * pitch + ix1;
-  const float p00 = p[r.o00], p01 = p[r.o01], p10 = p[r.o10], p11 = p[r.o11];
-  r.w00 = (1.0f - fy) * (1.0f - fx);
-  r.w01 = (1.0f - fy) * fx;
-  r.w10 = fy * (1.0f - fx);
-  r.w11 = fy * fx;
-  r.val = (1.0f - fy) * ((1.0f - fx) * p00 + fx * p01) + fy * ((1.0f - fx) * p10 + fx * p11);
-  r.dx = inx ? (1.0f - fy) * (p01 - p00) + fy * (p11 - p10) : 0.0f;
-  r.dy = iny ? ((1.0f - fx) * p10 + fx * p11) - ((1.0f - fx) * p00 + fx * p01) : 0.0f;
-  return r;
+__global__ __launch_bounds__(256) void k_solve_stored(const AdjArgs a) {
+  const AdjJob& J = a.job[find_job(a, blockIdx.x)];
+  const int nbx = (J.w + BX - 1) / BX;
+  const int b = blockIdx.x - J.tile_start;
+  const int x = (b % nbx) * BX + (threadIdx.x & 63);
+  const int y = (b / nbx) * BY + (threadIdx.x >> 6);
+  if (x >= J.w || y >= J.h) return;
+  const float* r = J.st + y * J.stp + x;
+  float g5[5], du, dv;
+  solve_adj(r[0], r[J.sts], r[2 * J.sts], r[3 * J.sts], r[4 * J.sts], J.vu[y * J.vp + x], J.vv[y * J.vp + x],
+            J.gu[y * J.gp + x], J.gv[y * J.gp + x], a.reg_rel, a.reg_abs, g5, du, dv);
+  float* o = J.gA + y * J.sp + x;
+#pragma unroll
+  for (int q = 0; q < 5; ++q) o[q * J.ps] = g5[q];
+  o[5 * J.ps] = du;
+  o[6 * J.ps] = dv;
 }
 
-// ---------------------------------------------------------------- forward recompute of one iteration
+// ---------------------------------------------------------------- up-sampling and its transpose
 
-__global__ __launch_bounds__(256) void k_terms(const AdjLevel a) {
+// V_fine(X) = 2 bilinear(V_coarse, X / 2), the forward kernels' arithmetic.
+__global__ __launch_bounds__(256) void k_upsample(const AuxArgs a) {
+  const AuxJob& J = a.job[blockIdx.z];
   int x, y;
-  if (!pix(x, y, a.w, a.h)) return;
-  const int ov = y * a.vp + x;
-  const float u = a.vu[ov], v = a.vv[ov];
-  const Bil b0 = bil_fwd(a.p0, a.ip, a.w, a.h, x - 0.5f * u, y - 0.5f * v);
-  const Bil b1 = bil_fwd(a.p1, a.ip, a.w, a.h, x + 0.5f * u, y + 0.5f * v);
-  const int o = y * a.sp + x;
-  a.S[o] = 0.5f * (b0.val + b1.val);
-  a.T[o] = b1.val - b0.val;
+  if (!pix(x, y, J.w, J.h)) return;
+  const uint32_t cp = static_cast<uint32_t>(J.ip);
+  const PlaneView cu = plane_view(J.in0, cp * static_cast<uint32_t>(J.ch) * 4u);
+  const PlaneView cv = plane_view(J.in1, cp * static_cast<uint32_t>(J.ch) * 4u);
+  const float cwm1 = static_cast<float>(J.cw - 1), chm1 = static_cast<float>(J.ch - 1);
+  const float cwm2 = static_cast<float>(J.cw - 2), chm2 = static_cast<float>(J.ch - 2);
+  const uint32_t sx = J.cw > 1 ? 1u : 0u, sy = J.ch > 1 ? cp : 0u;
+  const float fx = 0.5f * static_cast<float>(x), fy = 0.5f * static_cast<float>(y);
+  J.out0[y * J.op + x] = 2.0f * adj_bil(cu, fx, fy, cwm1, chm1, cwm2, chm2, cp, sx, sy);
+  J.out1[y * J.op + x] = 2.0f * adj_bil(cv, fx, fy, cwm1, chm1, cwm2, chm2, cp, sx, sy);
 }
 
-__global__ __launch_bounds__(256) void k_products(const AdjLevel a) {
-  int x, y;
-  if (!pix(x, y, a.w, a.h)) return;
-  const int o = y * a.sp + x;
-  const float* S = a.S;
-  const float gx = 0.5f * (S[y * a.sp + min(x + 1, a.w - 1)] - S[y * a.sp + max(x - 1, 0)]);
-  const float gy = 0.5f * (S[min(y + 1, a.h - 1) * a.sp + x] - S[max(y - 1, 0) * a.sp + x]);
-  const int ov = y * a.vp + x;
-  const float b = gx * a.vu[ov] + gy * a.vv[ov] - a.T[o];
-  a.GX[o] = gx;
-  a.GY[o] = gy;
-  a.B[o] = b;
-  a.A[0][o] = gx * gx;
-  a.A[1][o] = gx * gy;
-  a.A[2][o] = gy * gy;
-  a.A[3][o] = gx * b;
-  a.A[4][o] = gy * b;
+// weight with which fine coordinate X (sampled at X / 2, clamped) reaches coarse index i
+__device__ __forceinline__ float up_weight(int X, int i, int cw) {
+  const float xc = fminf(0.5f * static_cast<float>(X), static_cast<float>(cw - 1));
+  const float xf = floorf(xc);
+  const float f = xc - xf;
+  const int i0 = static_cast<int>(xf);
+  const int i1 = min(i0 + 1, cw - 1);
+  return (i0 == i ? 1.0f - f : 0.0f) + (i1 == i ? f : 0.0f);
 }
 
-// truncated box sums of radius r over up to 5 planes: horizontal pass then vertical pass
-struct PlaneList {
-  const float* in[5];
-  float* out[5];
-};
-
-__global__ __launch_bounds__(256) void k_box_h5(const PlaneList l, int n, int w, int h, int pitch, int r) {
-  int x, y;
-  if (!pix(x, y, w, h)) return;
-  const int x0 = max(x - r, 0), x1 = min(x + r, w - 1);
-  for (int q = 0; q < n; ++q) {
-    const float* row = l.in[q] + y * pitch;
-    float s = 0.0f;
-    for (int i = x0; i <= x1; ++i) s += row[i];
-    l.out[q][y * pitch + x] = s;
+// coarse (i, j) <- sum over fine (X, Y) with X in [2i - 2, 2i + 2] of 2 w(X, i) w(Y, j) g(X, Y)
+__global__ __launch_bounds__(256) void k_upsample_adj(const AuxArgs a) {
+  const AuxJob& J = a.job[blockIdx.z];
+  int i, j;
+  if (!pix(i, j, J.cw, J.ch)) return;
+  const int xa = max(2 * i - 2, 0), xb = min(2 * i + 2, J.w - 1);
+  const int ya = max(2 * j - 2, 0), yb = min(2 * j + 2, J.h - 1);
+  float su = 0.0f, sv = 0.0f;
+  for (int Y = ya; Y <= yb; ++Y) {
+    const float wy = up_weight(Y, j, J.ch);
+    if (wy == 0.0f) continue;
+    float ru = 0.0f, rv = 0.0f;
+    for (int X = xa; X <= xb; ++X) {
+      const float wx = up_weight(X, i, J.cw);
+      ru += wx * J.in0[Y * J.ip + X];
+      rv += wx * J.in1[Y * J.ip + X];
+    }
+    su += wy * ru;
+    sv += wy * rv;
   }
+  J.out0[j * J.op + i] = 2.0f * su;
+  J.out1[j * J.op + i] = 2.0f * sv;
 }
 
-__global__ __launch_bounds__(256) void k_box_v5(const PlaneList l, int n, int w, int h, int pitch, int r) {
-  int x, y;
-  if (!pix(x, y, w, h)) return;
-  const int y0 = max(y - r, 0), y1 = min(y + r, h - 1);
-  for (int q = 0; q < n; ++q) {
-    float s = 0.0f;
-    for (int j = y0; j <= y1; ++j) s += l.in[q][j * pitch + x];
-    l.out[q][y * pitch + x] = s;
-  }
-}
+// ---------------------------------------------------------------- REDUCE transposed
 
-// ---------------------------------------------------------------- adjoints
-
-// solve: x = M^-1 rhs with M = [[Sxx+lam, Sxy], [Sxy, Syy+lam]], rhs = (Sxb + lam u, Syb + lam v)
-__global__ __launch_bounds__(256) void k_solve_adj(const AdjLevel a) {
-  int x, y;
-  if (!pix(x, y, a.w, a.h)) return;
-  const int o = y * a.sp + x;
-  const int ov = y * a.vp + x;
-  const float sxx = a.A[0][o], sxy = a.A[1][o], syy = a.A[2][o], sxb = a.A[3][o], syb = a.A[4][o];
-  const float um = a.vu[ov], vm = a.vv[ov];
-  const float lam = a.reg_rel * (sxx + syy) + a.reg_abs;
-  const float aa = sxx + lam, dd = syy + lam;
-  const float det = aa * dd - sxy * sxy;
-  const float r1 = sxb + lam * um, r2 = syb + lam * vm;
-  const float xu = (dd * r1 - sxy * r2) / det;
-  const float xv = (aa * r2 - sxy * r1) / det;
-  const float gu = a.gu[y * a.gp + x], gv = a.gv[y * a.gp + x];
-  const float z1 = (dd * gu - sxy * gv) / det;   // dL/drhs = M^-T g
-  const float z2 = (aa * gv - sxy * gu) / det;
-  const float g_aa = -z1 * xu, g_dd = -z2 * xv, g_sxy = -(z1 * xv + z2 * xu);
-  const float g_lam = z1 * um + z2 * vm + g_aa + g_dd;
-  a.gA[0][o] = g_aa + a.reg_rel * g_lam;
-  a.gA[1][o] = g_sxy;
-  a.gA[2][o] = g_dd + a.reg_rel * g_lam;
-  a.gA[3][o] = z1;
-  a.gA[4][o] = z2;
-  a.gVu[o] = lam * z1;
-  a.gVv[o] = lam * z2;
-}
-
-// products and b: gp = Box(gA) is in gA (after the box pass)
-__global__ __launch_bounds__(256) void k_prod_adj(const AdjLevel a) {
-  int x, y;
-  if (!pix(x, y, a.w, a.h)) return;
-  const int o = y * a.sp + x;
-  const int ov = y * a.vp + x;
-  const float gx = a.GX[o], gy = a.GY[o], b = a.B[o];
-  const float g0 = a.gA[0][o], g1 = a.gA[1][o], g2 = a.gA[2][o], g3 = a.gA[3][o], g4 = a.gA[4][o];
-  const float gb = gx * g3 + gy * g4;
-  a.gGx[o] = 2.0f * gx * g0 + gy * g1 + b * g3 + a.vu[ov] * gb;
-  a.gGy[o] = gx * g1 + 2.0f * gy * g2 + b * g4 + a.vv[ov] * gb;
-  a.gT[o] = -gb;
-  a.gVu[o] += gx * gb;
-  a.gVv[o] += gy * gb;
-}
-
-// central difference transposed, S and T -> W0, W1, bilinear warps transposed
-__global__ __launch_bounds__(256) void k_warp_adj(const AdjLevel a) {
-  int x, y;
-  if (!pix(x, y, a.w, a.h)) return;
-  const int sp = a.sp;
-  const int w = a.w, h = a.h;
-  // gS(j) = sum over k whose clamped +1 neighbour is j of gG(k)/2 minus those whose clamped -1 neighbour is j
-  float gs = 0.0f;
-  if (x - 1 >= 0) gs += 0.5f * a.gGx[y * sp + x - 1];
-  if (x == w - 1) gs += 0.5f * a.gGx[y * sp + x];
-  if (x + 1 <= w - 1) gs -= 0.5f * a.gGx[y * sp + x + 1];
-  if (x == 0) gs -= 0.5f * a.gGx[y * sp + x];
-  if (y - 1 >= 0) gs += 0.5f * a.gGy[(y - 1) * sp + x];
-  if (y == h - 1) gs += 0.5f * a.gGy[y * sp + x];
-  if (y + 1 <= h - 1) gs -= 0.5f * a.gGy[(y + 1) * sp + x];
-  if (y == 0) gs -= 0.5f * a.gGy[y * sp + x];
-  const int o = y * sp + x;
-  const float gt = a.gT[o];
-  const float gw0 = 0.5f * gs - gt;
-  const float gw1 = 0.5f * gs + gt;
-  const int ov = y * a.vp + x;
-  const float u = a.vu[ov], v = a.vv[ov];
-  const Bil b0 = bil_fwd(a.p0, a.ip, w, h, x - 0.5f * u, y - 0.5f * v);
-  const Bil b1 = bil_fwd(a.p1, a.ip, w, h, x + 0.5f * u, y + 0.5f * v);
-  atomicAdd(a.gP0 + b0.o00, gw0 * b0.w00);
-  atomicAdd(a.gP0 + b0.o01, gw0 * b0.w01);
-  atomicAdd(a.gP0 + b0.o10, gw0 * b0.w10);
-  atomicAdd(a.gP0 + b0.o11, gw0 * b0.w11);
-  atomicAdd(a.gP1 + b1.o00, gw1 * b1.w00);
-  atomicAdd(a.gP1 + b1.o01, gw1 * b1.w01);
-  atomicAdd(a.gP1 + b1.o10, gw1 * b1.w10);
-  atomicAdd(a.gP1 + b1.o11, gw1 * b1.w11);
-  const int oo = y * a.op + x;
-  a.ou[oo] = a.gVu[o] - 0.5f * gw0 * b0.dx + 0.5f * gw1 * b1.dx;
-  a.ov[oo] = a.gVv[o] - 0.5f * gw0 * b0.dy + 0.5f * gw1 * b1.dy;
-}
-
-// V_fine(X) = 2 bilinear(V_coarse, X / 2): scatter 2 w g into the coarse gradient
-__global__ __launch_bounds__(256) void k_upsample_adj(const float* gfu, const float* gfv, int w, int h, int fp,
-                                                      float* gcu, float* gcv, int cw, int ch, int cp) {
-  int x, y;
-  if (!pix(x, y, w, h)) return;
-  const float gu = 2.0f * gfu[y * fp + x], gv = 2.0f * gfv[y * fp + x];
-  const float xc = fminf(0.5f * x, static_cast<float>(cw - 1));
-  const float yc = fminf(0.5f * y, static_cast<float>(ch - 1));
-  const float xf = floorf(xc), yf = floorf(yc);
-  const float fx = xc - xf, fy = yc - yf;
-  const int ix0 = static_cast<int>(xf), iy0 = static_cast<int>(yf);
-  const int ix1 = min(ix0 + 1, cw - 1), iy1 = min(iy0 + 1, ch - 1);
-  const float w00 = (1.0f - fy) * (1.0f - fx), w01 = (1.0f - fy) * fx, w10 = fy * (1.0f - fx), w11 = fy * fx;
-  atomicAdd(gcu + iy0 * cp + ix0, gu * w00);
-  atomicAdd(gcu + iy0 * cp + ix1, gu * w01);
-  atomicAdd(gcu + iy1 * cp + ix0, gu * w10);
-  atomicAdd(gcu + iy1 * cp + ix1, gu * w11);
-  atomicAdd(gcv + iy0 * cp + ix0, gv * w00);
-  atomicAdd(gcv + iy0 * cp + ix1, gv * w01);
-  atomicAdd(gcv + iy1 * cp + ix0, gv * w10);
-  atomicAdd(gcv + iy1 * cp + ix1, gv * w11);
-}
-
-// REDUCE transposed, as a gather: fine pixel X collects w_i from every coarse
-// x whose clamped tap 2x + i lands on X.
+// weight with which coarse index xc's clamped tap 2 xc + k (k = -2..2) reaches fine X
 __device__ __forceinline__ float reduce_t_weight(int X, int xc, int w) {
   const float w5[5] = {1.0f / 16, 4.0f / 16, 6.0f / 16, 4.0f / 16, 1.0f / 16};
   float s = 0.0f;
@@ -247,27 +112,47 @@ __device__ __forceinline__ float reduce_t_weight(int X, int xc, int w) {
   return s;
 }
 
-__global__ __launch_bounds__(256) void k_reduce_adj(const float* gc, int cw, int ch, int cp, float* gf, int w, int h,
-                                                    int fp, float scale, int accumulate) {
-  int x, y;
-  if (!pix(x, y, w, h)) return;
-  // coarse neighbours that can reach (x, y): |2 xc - x| <= 2 (plus the clamped border taps)
-  const int xa = max((x - 2) / 2 - 1, 0), xb = min((x + 2) / 2 + 1, cw - 1);
-  const int ya = max((y - 2) / 2 - 1, 0), yb = min((y + 2) / 2 + 1, ch - 1);
-  float s = 0.0f;
-  for (int j = ya; j <= yb; ++j) {
-    const float wy = reduce_t_weight(y, j, h);
-    if (wy == 0.0f) continue;
-    float row = 0.0f;
-    for (int i = xa; i <= xb; ++i) {
-      const float wx = reduce_t_weight(x, i, w);
-      row += wx * gc[j * cp + i];
-    }
-    s += wy * row;
+// Fine index X is reached only from coarse indices X/2 - 1 .. X/2 + 1
+// (rounded down; the end indices collect the taps clamped onto them too):
+// their summed weights, 0 for indices outside the coarse plane.
+__device__ __forceinline__ void reduce_t_taps(int X, int w, int cw, int* xc, float* wt) {
+  const int c = X >> 1;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const int k = c - 1 + i;
+    const bool in = k >= 0 && k < cw;
+    xc[i] = in ? k : 0;
+    wt[i] = in ? reduce_t_weight(X, k, w) : 0.0f;
   }
-  s *= scale;
-  float* dst = gf + y * fp + x;
-  *dst = accumulate ? *dst + s : s;
+}
+
+// fine (x, y) <- scale * sum over coarse neighbours of w(x) w(y) g_coarse; in0 coarse (pitch ip), out0 fine
+__global__ __launch_bounds__(256) void k_reduce_adj(const AuxArgs a) {
+  const AuxJob& J = a.job[blockIdx.z];
+  int x, y;
+  if (!pix(x, y, J.w, J.h)) return;
+  int xc[3], yc[3];
+  float wx[3], wy[3];
+  reduce_t_taps(x, J.w, J.cw, xc, wx);
+  reduce_t_taps(y, J.h, J.ch, yc, wy);
+  float s = 0.0f;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const float* row = J.in0 + yc[j] * J.ip;
+    s += wy[j] * (wx[0] * row[xc[0]] + wx[1] * row[xc[1]] + wx[2] * row[xc[2]]);
+  }
+  s *= a.scale;
+  float* dst = J.out0 + y * J.op + x;
+  *dst = a.accumulate ? *dst + s : s;
+}
+
+// both planes of every job's field set to zero over w x h (pitch op)
+__global__ __launch_bounds__(256) void k_zero_fields(const AuxArgs a) {
+  const AuxJob& J = a.job[blockIdx.z];
+  int x, y;
+  if (!pix(x, y, J.w, J.h)) return;
+  J.out0[y * J.op + x] = 0.0f;
+  J.out1[y * J.op + x] = 0.0f;
 }
 
 __global__ __launch_bounds__(256) void k_fill(float* p, int64_t n, float v) {
@@ -288,49 +173,180 @@ __device__ __forceinline__ float frame_px(const ImageIn& f, int x, int y) {
   return static_cast<const float*>(f.data)[o];
 }
 
-__global__ __launch_bounds__(256) void k_norm_terms(const ImageIn f, int nr, float eps, const float* gN, int gp,
-                                                    float* I, float* sig, float* pa, float* pc, float* pcm, int sp) {
-  int x, y;
-  if (!pix(x, y, f.w, f.h)) return;
-  const int xa = max(x - nr, 0), xb = min(x + nr, f.w - 1), ya = max(y - nr, 0), yb = min(y + nr, f.h - 1);
-  const float n = static_cast<float>((xb - xa + 1) * (yb - ya + 1));
-  float s = 0.0f;
-  for (int j = ya; j <= yb; ++j)
-    for (int i = xa; i <= xb; ++i) s += frame_px(f, i, j);
-  const float mu = s / n;
-  float q = 0.0f;
-  for (int j = ya; j <= yb; ++j)
-    for (int i = xa; i <= xb; ++i) {
-      const float d = frame_px(f, i, j) - mu;
-      q += d * d;
+__device__ __forceinline__ float frame_scale(const ImageIn& f) {
+  return f.type == 2 ? 1.0f : 1.0f / static_cast<float>((1 << f.bits) - 1);
+}
+
+// One 64 x 16 tile of frame gradients per workgroup (job = blockIdx.z), all
+// in LDS: the frame over the tile + 2 NR, then for every pixel k of the tile
+// + NR its window mean and deviation and a_k, c_k, c_k mu_k, their window
+// sums (horizontal pass, then vertical per output), and the output.
+constexpr int kNAdjTW = 64, kNAdjTH = 16;
+
+__host__ __device__ constexpr int norm_adj_lds_floats(int nr) {
+  return (kNAdjTW + 4 * nr) * (kNAdjTH + 4 * nr) + 4 * (kNAdjTW + 2 * nr) * (kNAdjTH + 2 * nr) +
+         kNAdjTW * kNAdjTH + 3 * (kNAdjTH + 2 * nr) * kNAdjTW;
+}
+
+// NRC > 0: the radius as a compile-time constant (loops unrolled); 0: a.nr
+template <int NRC>
+__global__ __launch_bounds__(256) void k_norm_adj_tile(const NormAdjArgs a) {
+  extern __shared__ float lds[];
+  const NormAdjJob& J = a.job[blockIdx.z];
+  const ImageIn& f = J.f;
+  const int W = f.w, H = f.h, nr = NRC > 0 ? NRC : a.nr;
+  const int ntx = (W + kNAdjTW - 1) / kNAdjTW;
+  const int t = blockIdx.x;
+  if (t >= ntx * ((H + kNAdjTH - 1) / kNAdjTH)) return;
+  const int x0 = (t % ntx) * kNAdjTW, y0 = (t / ntx) * kNAdjTH;
+  const int FW = kNAdjTW + 4 * nr, FH = kNAdjTH + 4 * nr;  // frame region, origin (x0 - 2 nr, y0 - 2 nr)
+  const int KW = kNAdjTW + 2 * nr, KH = kNAdjTH + 2 * nr;  // window-term region, origin (x0 - nr, y0 - nr)
+  float* sF = lds;
+  float* sA = sF + FW * FH;          // a, c, c mu: three KW x KH planes
+  float* sG = sA + 3 * KW * KH;      // dL/dN over the window-term region
+  float* sSig = sG + KW * KH;        // sigma of the tile pixels
+  float* sH = sSig + kNAdjTW * kNAdjTH;  // horizontal sums: three KH x 64 planes
+  const int tid = threadIdx.x;
+  // the frame and dL/dN; with the radius known at compile time every load of
+  // the lane is issued (at a clamped address) before any is stored
+  if (NRC > 0) {
+    constexpr int NF = ((kNAdjTW + 4 * NRC) * (kNAdjTH + 4 * NRC) + 255) / 256;
+    constexpr int NG = ((kNAdjTW + 2 * NRC) * (kNAdjTH + 2 * NRC) + 255) / 256;
+    float fv[NF], gv[NG];
+#pragma unroll
+    for (int k = 0; k < NF; ++k) {
+      const int e = min(tid + 256 * k, FW * FH - 1);
+      const int fy = e / FW, fx = e - fy * FW;
+      fv[k] = frame_px(f, min(max(x0 - 2 * nr + fx, 0), W - 1), min(max(y0 - 2 * nr + fy, 0), H - 1));
     }
-  const float sg = sqrtf(q / n + eps);
-  const float ik = frame_px(f, x, y);
-  const float g = gN[y * gp + x];
-  const int o = y * sp + x;
-  I[o] = ik;
-  sig[o] = sg;
-  pa[o] = g / (n * sg);
-  const float c = g * (ik - mu) / (n * sg * sg * sg);
-  pc[o] = c;
-  pcm[o] = c * mu;
+#pragma unroll
+    for (int k = 0; k < NG; ++k) {
+      const int e = min(tid + 256 * k, KW * KH - 1);
+      const int ky = e / KW, kx = e - ky * KW;
+      gv[k] = J.gN[min(max(y0 - nr + ky, 0), H - 1) * J.gp + min(max(x0 - nr + kx, 0), W - 1)];
+    }
+#pragma unroll
+    for (int k = 0; k < NF; ++k) {
+      const int e = tid + 256 * k;
+      if (e < FW * FH) {
+        const int fy = e / FW, fx = e - fy * FW;
+        const int gx = x0 - 2 * nr + fx, gy = y0 - 2 * nr + fy;
+        const bool in = static_cast<unsigned>(gx) < static_cast<unsigned>(W) &&
+                        static_cast<unsigned>(gy) < static_cast<unsigned>(H);
+        sF[e] = in ? fv[k] : 0.0f;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NG; ++k) {
+      const int e = tid + 256 * k;
+      if (e < KW * KH) sG[e] = gv[k];
+    }
+  } else {
+    for (int e = tid; e < FW * FH; e += 256) {
+      const int fy = e / FW, fx = e - fy * FW;
+      const int gx = x0 - 2 * nr + fx, gy = y0 - 2 * nr + fy;
+      const bool in = static_cast<unsigned>(gx) < static_cast<unsigned>(W) && static_cast<unsigned>(gy) < static_cast<unsigned>(H);
+      sF[e] = in ? frame_px(f, gx, gy) : 0.0f;
+    }
+    for (int e = tid; e < KW * KH; e += 256) {
+      const int ky = e / KW, kx = e - ky * KW;
+      const int gx = min(max(x0 - nr + kx, 0), W - 1), gy = min(max(y0 - nr + ky, 0), H - 1);
+      sG[e] = J.gN[gy * J.gp + gx];
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < KW * KH; e += 256) {
+    const int ky = e / KW, kx = e - ky * KW;
+    const int gx = x0 - nr + kx, gy = y0 - nr + ky;
+    float pa = 0.0f, pc = 0.0f, pcm = 0.0f;
+    if (static_cast<unsigned>(gx) < static_cast<unsigned>(W) && static_cast<unsigned>(gy) < static_cast<unsigned>(H)) {
+      const int xa = max(gx - nr, 0), xb = min(gx + nr, W - 1), ya = max(gy - nr, 0), yb = min(gy + nr, H - 1);
+      const float n = static_cast<float>((xb - xa + 1) * (yb - ya + 1));
+      float mu, q;
+      if (NRC > 0) {
+        // the full window, unrolled: the frame region holds 0 outside the
+        // frame, and the masks keep those pixels out of the deviations
+        constexpr int NC = 2 * NRC + 1;
+        float v[NC][NC], mk[NC][NC];
+        float sm = 0.0f;
+#pragma unroll
+        for (int j = 0; j < NC; ++j)
+#pragma unroll
+          for (int i = 0; i < NC; ++i) {
+            v[j][i] = sF[(ky + j) * FW + kx + i];
+            mk[j][i] = (static_cast<unsigned>(gx - NRC + i) < static_cast<unsigned>(W) &&
+                        static_cast<unsigned>(gy - NRC + j) < static_cast<unsigned>(H)) ? 1.0f : 0.0f;
+            sm += v[j][i];
+          }
+        mu = sm / n;
+        q = 0.0f;
+#pragma unroll
+        for (int j = 0; j < NC; ++j)
+#pragma unroll
+          for (int i = 0; i < NC; ++i) {
+            const float d = v[j][i] - mu;
+            q += mk[j][i] * (d * d);
+          }
+      } else {
+        // frame-region coordinates of (xa, ya)
+        const int ox = xa - (x0 - 2 * nr), oy = ya - (y0 - 2 * nr);
+        float sm = 0.0f;
+        for (int j = 0; j <= yb - ya; ++j)
+          for (int i = 0; i <= xb - xa; ++i) sm += sF[(oy + j) * FW + ox + i];
+        mu = sm / n;
+        q = 0.0f;
+        for (int j = 0; j <= yb - ya; ++j)
+          for (int i = 0; i <= xb - xa; ++i) {
+            const float d = sF[(oy + j) * FW + ox + i] - mu;
+            q += d * d;
+          }
+      }
+      const float sg = sqrtf(q / n + a.eps);
+      const float ik = sF[(ky + nr) * FW + kx + nr];
+      const float g = sG[e];
+      pa = g / (n * sg);
+      pc = g * (ik - mu) / (n * sg * sg * sg);
+      pcm = pc * mu;
+      if (kx >= nr && kx < nr + kNAdjTW && ky >= nr && ky < nr + kNAdjTH) sSig[(ky - nr) * kNAdjTW + kx - nr] = sg;
+    }
+    sA[e] = pa;
+    sA[KW * KH + e] = pc;
+    sA[2 * KW * KH + e] = pcm;
+  }
+  __syncthreads();
+  for (int e = tid; e < KH * kNAdjTW; e += 256) {
+    const int r = e / kNAdjTW, c = e - r * kNAdjTW;
+    for (int q = 0; q < 3; ++q) {
+      const float* row = sA + q * KW * KH + r * KW + c;
+      float acc = 0.0f;
+      for (int i = 0; i <= 2 * nr; ++i) acc += row[i];
+      sH[q * KH * kNAdjTW + e] = acc;
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < kNAdjTW * kNAdjTH; e += 256) {
+    const int ty = e / kNAdjTW, tx = e - ty * kNAdjTW;
+    const int gx = x0 + tx, gy = y0 + ty;
+    if (gx >= W || gy >= H) continue;
+    float b[3];
+    for (int q = 0; q < 3; ++q) {
+      const float* col = sH + q * KH * kNAdjTW + ty * kNAdjTW + tx;
+      float acc = 0.0f;
+      for (int j = 0; j <= 2 * nr; ++j) acc += col[j * kNAdjTW];
+      b[q] = acc;
+    }
+    const float ij = sF[(ty + 2 * nr) * FW + tx + 2 * nr];
+    const float g = sG[(ty + nr) * KW + tx + nr] / sSig[e] - b[0] - ij * b[1] + b[2];
+    J.gF[gy * J.fp + gx] = g * frame_scale(f);
+  }
 }
 
-__global__ __launch_bounds__(256) void k_norm_out(int w, int h, const float* gN, int gp, const float* I,
-                                                  const float* sig, const float* ba, const float* bc,
-                                                  const float* bcm, int sp, float scale, float* gF, int fp) {
+// NR 0: N = I, so the frame gradient is the level-0 gradient in the frame's units
+__global__ __launch_bounds__(256) void k_norm_scale(const NormAdjArgs a) {
+  const NormAdjJob& J = a.job[blockIdx.z];
   int x, y;
-  if (!pix(x, y, w, h)) return;
-  const int o = y * sp + x;
-  const float g = gN[y * gp + x] / sig[o] - ba[o] - I[o] * bc[o] + bcm[o];
-  gF[y * fp + x] = g * scale;
-}
-
-__global__ __launch_bounds__(256) void k_scale_copy(const float* in, int ip, float* out, int op, int w, int h,
-                                                    float scale) {
-  int x, y;
-  if (!pix(x, y, w, h)) return;
-  out[y * op + x] = in[y * ip + x] * scale;
+  if (!pix(x, y, J.f.w, J.f.h)) return;
+  J.gF[y * J.fp + x] = J.gN[y * J.gp + x] * frame_scale(J.f);
 }
 
 }  // namespace
@@ -343,62 +359,58 @@ hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s) {
   return hipGetLastError();
 }
 
-static hipError_t box5(float* const* planes, float* const* tmp, int n, int w, int h, int pitch, int r, hipStream_t s) {
-  PlaneList a{}, b{};
-  for (int q = 0; q < n; ++q) {
-    a.in[q] = planes[q];
-    a.out[q] = tmp[q];
-    b.in[q] = tmp[q];
-    b.out[q] = planes[q];
-  }
-  hipLaunchKernelGGL(k_box_h5, grid2(w, h), dim3(256), 0, s, a, n, w, h, pitch, r);
-  hipLaunchKernelGGL(k_box_v5, grid2(w, h), dim3(256), 0, s, b, n, w, h, pitch, r);
+int adj_point_blocks(int w, int h) { return ((w + BX - 1) / BX) * ((h + BY - 1) / BY); }
+
+hipError_t launch_adj_solve_stored(const AdjArgs& a, int nblocks, hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_solve_stored, dim3(nblocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_adj_iteration(const AdjLevel& a, hipStream_t s) {
-  const dim3 g = grid2(a.w, a.h);
-  hipLaunchKernelGGL(k_terms, g, dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_products, g, dim3(256), 0, s, a);
-  hipError_t e = box5(a.A, a.tmp, 5, a.w, a.h, a.sp, a.kr, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_solve_adj, g, dim3(256), 0, s, a);
-  e = box5(a.gA, a.tmp, 5, a.w, a.h, a.sp, a.kr, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_prod_adj, g, dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_warp_adj, g, dim3(256), 0, s, a);
+hipError_t launch_upsample_batch(const AuxArgs& a, int maxw, int maxh, hipStream_t s) {
+  if (a.njobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_upsample, grid3(maxw, maxh, a.njobs), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_upsample_adj(const float* gfu, const float* gfv, int w, int h, int fp, float* gcu, float* gcv, int cw,
-                               int ch, int cp, hipStream_t s) {
-  hipLaunchKernelGGL(k_upsample_adj, grid2(w, h), dim3(256), 0, s, gfu, gfv, w, h, fp, gcu, gcv, cw, ch, cp);
+hipError_t launch_upsample_adj(const AuxArgs& a, int maxcw, int maxch, hipStream_t s) {
+  if (a.njobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_upsample_adj, grid3(maxcw, maxch, a.njobs), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_reduce_adj(const float* gc, int cw, int ch, int cp, float* gf, int w, int h, int fp, float scale,
-                             int accumulate, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_adj, grid2(w, h), dim3(256), 0, s, gc, cw, ch, cp, gf, w, h, fp, scale, accumulate);
+hipError_t launch_zero_fields(const AuxArgs& a, int maxw, int maxh, hipStream_t s) {
+  if (a.njobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_fields, grid3(maxw, maxh, a.njobs), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_norm_adj(const ImageIn& f, int nr, float eps, const float* gN, int gp, float* const* scratch, int sp,
-                           float* gF, int fp, hipStream_t s) {
-  const float scale = f.type == 2 ? 1.0f : 1.0f / static_cast<float>((1 << f.bits) - 1);
-  if (nr <= 0) {
-    hipLaunchKernelGGL(k_scale_copy, grid2(f.w, f.h), dim3(256), 0, s, gN, gp, gF, fp, f.w, f.h, scale);
+hipError_t launch_reduce_adj(const AuxArgs& a, int maxw, int maxh, hipStream_t s) {
+  if (a.njobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce_adj, grid3(maxw, maxh, a.njobs), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_norm_adj(const NormAdjArgs& a, int maxw, int maxh, hipStream_t s) {
+  if (a.njobs <= 0) return hipSuccess;
+  if (a.nr <= 0) {
+    hipLaunchKernelGGL(k_norm_scale, grid3(maxw, maxh, a.njobs), dim3(256), 0, s, a);
     return hipGetLastError();
   }
-  float* I = scratch[0];
-  float* sig = scratch[1];
-  float* planes[3] = {scratch[2], scratch[3], scratch[4]};
-  float* tmp[3] = {scratch[5], scratch[6], scratch[7]};
-  hipLaunchKernelGGL(k_norm_terms, grid2(f.w, f.h), dim3(256), 0, s, f, nr, eps, gN, gp, I, sig, planes[0], planes[1],
-                     planes[2], sp);
-  hipError_t e = box5(planes, tmp, 3, f.w, f.h, sp, nr, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_norm_out, grid2(f.w, f.h), dim3(256), 0, s, f.w, f.h, gN, gp, I, sig, planes[0], planes[1],
-                     planes[2], sp, scale, gF, fp);
+  const int tiles = ((maxw + kNAdjTW - 1) / kNAdjTW) * ((maxh + kNAdjTH - 1) / kNAdjTH);
+  const size_t lds = sizeof(float) * norm_adj_lds_floats(a.nr);
+  const dim3 g(tiles, 1, a.njobs);
+  if (a.nr == 1) {
+    hipLaunchKernelGGL(k_norm_adj_tile<1>, g, dim3(256), lds, s, a);
+  } else if (a.nr == 2) {
+    hipLaunchKernelGGL(k_norm_adj_tile<2>, g, dim3(256), lds, s, a);
+  } else {
+    static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(k_norm_adj_tile<0>),
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                       static_cast<int>(sizeof(float) * norm_adj_lds_floats(kMaxNR)));
+    if (attr != hipSuccess) return attr;
+    hipLaunchKernelGGL(k_norm_adj_tile<0>, g, dim3(256), lds, s, a);
+  }
   return hipGetLastError();
 }
 

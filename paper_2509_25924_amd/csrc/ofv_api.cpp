@@ -86,7 +86,17 @@ struct ofv_ctx {
   // backward workspace (ofv_reserve_backward): saved iterates, scratch planes, image-gradient pyramids
   float* bw = nullptr;
   size_t bw_bytes = 0;
-  int bw_levels = 0, bw_iters = 0;
+  int bw_levels = 0, bw_iters = 0, bw_pairs = 0;
+  bool bw_store_all = false;
+  // the forward whose iterates (and pyramids) the workspace holds: a backward
+  // with OFV_FLAG_SAVED_FORWARD on the same inputs skips its own forward
+  struct SavedForward {
+    bool valid = false;
+    int n = 0;
+    ofv_params params{};
+    std::vector<ofv_image> f0, f1;
+    std::vector<const float*> init;
+  } saved_fw;
 };
 
 namespace {
@@ -177,7 +187,8 @@ ofv_status check_params(ofv_ctx* h, const ofv_params* p) {
     return fail(h, OFV_ERR_INVALID_ARG, "reg_rel and reg_abs must be finite and >= 0");
   if (p->storage < OFV_STORE_F32 || p->storage > OFV_STORE_BF16)
     return fail(h, OFV_ERR_INVALID_ARG, "unknown storage %d", p->storage);
-  if (p->flags & ~(OFV_FLAG_FORWARD_ADDITIVE | OFV_FLAG_INCREMENT_UPDATE | OFV_FLAG_NO_FP64_FALLBACK))
+  if (p->flags & ~(OFV_FLAG_FORWARD_ADDITIVE | OFV_FLAG_INCREMENT_UPDATE | OFV_FLAG_NO_FP64_FALLBACK |
+                   OFV_FLAG_STORE_ALL | OFV_FLAG_SAVE_ITERATES | OFV_FLAG_SAVED_FORWARD))
     return fail(h, OFV_ERR_INVALID_ARG, "unknown flags 0x%x", p->flags);
   return OFV_OK;
 }
@@ -316,12 +327,33 @@ ofv_status run_chunked(ofv_ctx* h, int njobs, Args& args, Fill fill, Launch laun
   return OFV_OK;
 }
 
-// save (optional, n == 1): per (level l, iteration k) at index l * IT + k, the u plane
-// that receives that iteration's output (v plane lpitch[l] * lh[l] further).
+// Runs fill(job_index, job) for chunks of at most kMaxJobs jobs and launches each chunk.
+template <typename Args, typename Fill, typename Launch>
+ofv_status run_jobs(ofv_ctx* h, int njobs, Args& args, Fill fill, Launch launch, const char* what) {
+  for (int base = 0; base < njobs; base += kMaxJobs) {
+    const int cnt = std::min(kMaxJobs, njobs - base);
+    args.njobs = cnt;
+    for (int i = 0; i < cnt; ++i) fill(base + i, args.job[i]);
+    hipError_t e = launch(args);
+    if (e != hipSuccess) return device_error(h, e, what);
+  }
+  return OFV_OK;
+}
+
+// How far run_pipeline goes: the whole estimator, the pyramids only, or the
+// pyramids and the initial field's restriction (everything before step 3).
+enum PipeStop { PIPE_FULL = 0, PIPE_PYRAMID = 1, PIPE_NO_GN = 2 };
+
+// save (optional): per (pair j, level l, iteration k) at index (j * L + l) *
+// IT + k, the u plane that receives that iteration's output (v plane
+// lpitch[l] * lh[l] further); the last iteration of level 0 writes the
+// pair's flow_out instead where it has one.
 ofv_status run_pipeline(ofv_ctx* h, int n, PairPlan* pp, const ofv_params* p, float* const* save = nullptr,
-                        bool pyramid_only = false) {
-  // any run rewrites the slabs of the slots it uses: a retained streaming frame is gone
+                        PipeStop stop = PIPE_FULL) {
+  // any run rewrites the slabs of the slots it uses: a retained streaming frame
+  // and a saved forward are gone
   h->stream_valid = false;
+  h->saved_fw.valid = false;
   const int L = p->num_levels;
   // estimator variants other than the symmetric estimator's consistent update
   // run on the generic kernels, which read them at run time
@@ -412,7 +444,7 @@ ofv_status run_pipeline(ofv_ctx* h, int n, PairPlan* pp, const ofv_params* p, fl
     if (r != OFV_OK) return r;
     l += nlev;
   }
-  if (pyramid_only) return OFV_OK;
+  if (stop == PIPE_PYRAMID) return OFV_OK;
   // Initial flow: restricted to the coarsest level by REDUCE / 2 (pairs that have one).
   std::vector<int> cur(n, -1);  // flow buffer holding the current field, -1 = zero field
   std::vector<int> with_init;
@@ -462,6 +494,7 @@ ofv_status run_pipeline(ofv_ctx* h, int n, PairPlan* pp, const ofv_params* p, fl
       for (int j : with_init) cur[j] = (L - 1) & 1;
     }
   }
+  if (stop == PIPE_NO_GN) return OFV_OK;
   // Steps 3-6: Gauss-Newton iterations, coarse to fine; the up-sampling of
   // step 4 is fused into the first iteration of every finer level and the
   // last level-0 iteration writes the caller's buffer.
@@ -533,16 +566,23 @@ ofv_status run_pipeline(ofv_ctx* h, int n, PairPlan* pp, const ofv_params* p, fl
           if (save) {
             // every iteration reads its predecessor's saved output and writes its own slot
             if (mode == FLOW_UPSAMPLE) {
-              J.in_u = save[(l + 1) * it + it - 1];
+              J.in_u = save[(j * L + l + 1) * it + it - 1];
               J.in_v = J.in_u + h->lpitch[l + 1] * h->lh[l + 1];
             } else if (mode == FLOW_DIRECT && k >= 1) {
-              J.in_u = save[l * it + k - 1];
+              J.in_u = save[(j * L + l) * it + k - 1];
               J.in_v = J.in_u + h->lpitch[l] * h->lh[l];
               J.in_pitch = h->lpitch[l];
             }
-            J.out_u = save[l * it + k];
-            J.out_v = J.out_u + h->lpitch[l] * h->lh[l];
-            J.out_pitch = h->lpitch[l];
+            if (final_iter && q.out) {
+              // the adjoint never reads the last output: it goes to the caller's buffer
+              J.out_u = q.out;
+              J.out_v = q.out + static_cast<int64_t>(q.lw[0]) * q.lh[0];
+              J.out_pitch = q.lw[0];
+            } else {
+              J.out_u = save[(j * L + l) * it + k];
+              J.out_v = J.out_u + h->lpitch[l] * h->lh[l];
+              J.out_pitch = h->lpitch[l];
+            }
             next[j] = 0;
           } else if (final_iter) {
             J.out_u = q.out;
@@ -612,6 +652,247 @@ ofv_status validate_pair(ofv_ctx* h, const ofv_image* f0, const ofv_image* f1, c
   return OFV_OK;
 }
 
+// Level-0 scratch planes of one pair: dL/dA and the solve's direct gradient
+// (7), three gradient fields in rotation (6), the input field of a level's
+// first iteration (2).
+constexpr int kBwScratchPlanes = 15;
+
+// Floats of one pair's backward workspace: the output field of every
+// (level, iteration); in store-all mode also, per (level, iteration), the
+// five window sums and Gx, Gy, b, and per level the first iteration's input
+// field; the scratch planes.  The image-gradient pyramids of all pairs
+// follow the pair blocks, contiguous, so one fill clears them.
+struct BwLayout {
+  size_t saved = 0, record = 0, scratch = 0, pair = 0, gpyr = 0;
+};
+
+BwLayout bw_layout(const ofv_ctx* h, int levels, int iters, bool store_all) {
+  BwLayout b;
+  for (int l = 0; l < levels; ++l) {
+    const size_t pl = static_cast<size_t>(h->lpitch[l]) * h->lh[l];
+    b.saved += static_cast<size_t>(iters) * 2 * pl;
+    if (store_all) b.record += (static_cast<size_t>(iters) * 8 + 2) * pl;
+  }
+  b.scratch = kBwScratchPlanes * static_cast<size_t>(h->lpitch[0]) * h->lh[0];
+  b.pair = b.saved + b.record + b.scratch;
+  b.gpyr = h->frame_bytes / 2;  // two float32 pyramid slabs (frame_bytes is one slab in bytes)
+  return b;
+}
+
+size_t bw_total_bytes(const ofv_ctx* h, int levels, int iters, int pairs, bool store_all) {
+  const BwLayout b = bw_layout(h, levels, iters, store_all);
+  return (b.pair + b.gpyr) * static_cast<size_t>(pairs) * sizeof(float);
+}
+
+// Addresses in the reserved backward workspace (offsets from the reserved
+// levels and iterations, so they do not depend on the call's).
+struct BwView {
+  const ofv_ctx* h;
+  BwLayout lay;
+  explicit BwView(const ofv_ctx* c) : h(c), lay(bw_layout(c, c->bw_levels, c->bw_iters, c->bw_store_all)) {}
+  size_t plane(int l) const { return static_cast<size_t>(h->lpitch[l]) * h->lh[l]; }
+  float* pair(int j) const { return h->bw + static_cast<size_t>(j) * lay.pair; }
+  float* saved(int j, int l, int k) const {
+    size_t o = 0;
+    for (int i = 0; i < l; ++i) o += static_cast<size_t>(h->bw_iters) * 2 * plane(i);
+    return pair(j) + o + static_cast<size_t>(k) * 2 * plane(l);
+  }
+  float* rec_level(int j, int l) const {
+    size_t o = lay.saved;
+    for (int i = 0; i < l; ++i) o += (static_cast<size_t>(h->bw_iters) * 8 + 2) * plane(i);
+    return pair(j) + o;
+  }
+  float* rec(int j, int l, int k) const { return rec_level(j, l) + static_cast<size_t>(k) * 8 * plane(l); }
+  float* rec_in(int j, int l) const { return rec_level(j, l) + static_cast<size_t>(h->bw_iters) * 8 * plane(l); }
+  float* scratch(int j, int q) const {
+    return pair(j) + lay.saved + lay.record + static_cast<size_t>(q) * h->lpitch[0] * h->lh[0];
+  }
+  float* gpyr_all() const { return h->bw + static_cast<size_t>(h->bw_pairs) * lay.pair; }
+  float* gpyr(int j, int f, int l) const {
+    return gpyr_all() + static_cast<size_t>(j) * lay.gpyr + static_cast<size_t>(f) * (h->frame_bytes / 4) +
+           h->img_off[l];
+  }
+};
+
+// One batched backward (or saving forward) call: the pairs, their levels and
+// where their fields live in the backward workspace.
+struct BwPlan {
+  ofv_ctx* h;
+  int n, L, IT, kr;
+  const ofv_params* params;
+  bool store_all;
+  BwView bv;
+  std::vector<PairPlan> pp;
+  hipStream_t s;
+  int sp0, plane0;
+
+  BwPlan(ofv_ctx* c, int npairs, const ofv_params* p)
+      : h(c), n(npairs), L(p->num_levels), IT(p->iterations), kr(p->kernel_radius), params(p),
+        store_all((p->flags & OFV_FLAG_STORE_ALL) != 0), bv(c), pp(npairs), s(c->stream),
+        sp0(static_cast<int>(c->lpitch[0])), plane0(static_cast<int>(c->lpitch[0] * c->lh[0])) {}
+
+  int lp(int l) const { return static_cast<int>(h->lpitch[l]); }
+  int lplane(int l) const { return static_cast<int>(h->lpitch[l] * h->lh[l]); }
+  // the restricted initial field (coarsest level), in the pair's flow buffer
+  float* init_field(int j) const { return flow_buf(h, pp[j], L == 1 ? 1 : (L - 1) & 1); }
+
+  struct Field {
+    float* u;
+    int pitch;  // row pitch
+    int vstep;  // v plane = u + vstep
+  };
+  // input field of the first iteration of a level: up-sampled (levels above
+  // the coarsest), the restricted initial field, or zero
+  Field vin0(int j, int l) const {
+    if (l == L - 1 && pp[j].init) return {init_field(j), lp(l), lplane(l)};
+    if (store_all) return {bv.rec_in(j, l), lp(l), lplane(l)};
+    return {bv.scratch(j, 13), lp(l), lplane(l)};
+  }
+
+  // fills the first iteration's input planes of level l (up-sampling or zeros), one launch
+  ofv_status prepare_vin0(int l) {
+    AuxArgs ua{};
+    int mw = 0, mh = 0;
+    std::vector<int> js;
+    for (int j = 0; j < n; ++j) {
+      if (l == L - 1 && pp[j].init) continue;
+      js.push_back(j);
+      mw = std::max(mw, pp[j].lw[l]);
+      mh = std::max(mh, pp[j].lh[l]);
+    }
+    const bool up = l < L - 1;
+    return run_jobs(h, static_cast<int>(js.size()), ua, [&](int i, AuxJob& J) {
+      const int j = js[i];
+      if (up) {
+        J.in0 = bv.saved(j, l + 1, IT - 1);
+        J.in1 = J.in0 + lplane(l + 1);
+        J.ip = lp(l + 1);
+        J.cw = pp[j].lw[l + 1];
+        J.ch = pp[j].lh[l + 1];
+      }
+      const Field f = vin0(j, l);
+      J.out0 = f.u;
+      J.out1 = f.u + f.vstep;
+      J.op = f.pitch;
+      J.w = pp[j].lw[l];
+      J.h = pp[j].lh[l];
+    }, [&](const AuxArgs& a) { return up ? launch_upsample_batch(a, mw, mh, s) : launch_zero_fields(a, mw, mh, s); },
+                    up ? "up-sampling" : "fill");
+  }
+
+  // The forward, keeping each iteration's output in the workspace (the last
+  // of level 0 goes to the pair's flow_out where it has one); store-all: the
+  // recording iterations, which also keep each iteration's sums and Gx, Gy, b.
+  ofv_status forward() {
+    if (!store_all) {
+      std::vector<float*> save(static_cast<size_t>(n) * L * IT);
+      for (int j = 0; j < n; ++j)
+        for (int l = 0; l < L; ++l)
+          for (int k = 0; k < IT; ++k) save[(static_cast<size_t>(j) * L + l) * IT + k] = bv.saved(j, l, k);
+      return run_pipeline(h, n, pp.data(), params, save.data());
+    }
+    ofv_status r = run_pipeline(h, n, pp.data(), params, nullptr, PIPE_NO_GN);
+    if (r != OFV_OK) return r;
+    for (int l = L - 1; l >= 0; --l) {
+      r = prepare_vin0(l);
+      if (r != OFV_OK) return r;
+      for (int k = 0; k < IT; ++k) {
+        AdjArgs aa{};
+        aa.reg_rel = params->reg_rel;
+        aa.reg_abs = params->reg_abs;
+        aa.no_fp64 = (params->flags & OFV_FLAG_NO_FP64_FALLBACK) ? 1 : 0;
+        int blocks = 0;
+        r = run_jobs(h, n, aa, [&](int j, AdjJob& J) {
+          if ((j % kMaxJobs) == 0) blocks = 0;
+          J = AdjJob{};
+          J.p0 = reinterpret_cast<const float*>(img_plane(h, pp[j], 0, l, 4));
+          J.p1 = reinterpret_cast<const float*>(img_plane(h, pp[j], 1, l, 4));
+          J.ip = lp(l);
+          if (k == 0) {
+            const Field f = vin0(j, l);
+            J.vu = f.u;
+            J.vv = f.u + f.vstep;
+            J.vp = f.pitch;
+          } else {
+            J.vu = bv.saved(j, l, k - 1);
+            J.vv = J.vu + lplane(l);
+            J.vp = lp(l);
+          }
+          if (l == 0 && k == IT - 1 && pp[j].out) {
+            J.ou = pp[j].out;
+            J.ov = pp[j].out + static_cast<int64_t>(pp[j].lw[0]) * pp[j].lh[0];
+            J.op = pp[j].lw[0];
+          } else {
+            J.ou = bv.saved(j, l, k);
+            J.ov = J.ou + lplane(l);
+            J.op = lp(l);
+          }
+          J.st = bv.rec(j, l, k);
+          J.stp = lp(l);
+          J.sts = lplane(l);
+          J.w = pp[j].lw[l];
+          J.h = pp[j].lh[l];
+          J.tile_start = blocks;
+          blocks += adj_sums_blocks(J.w, J.h);
+        }, [&](const AdjArgs& a) { return launch_adj_sums(a, kr, ADJ_RECORD, blocks, s); }, "recording iteration");
+        if (r != OFV_OK) return r;
+      }
+    }
+    return OFV_OK;
+  }
+};
+
+// Flags that do not change what a forward computes or keeps.
+constexpr uint32_t kSaveFlags = OFV_FLAG_SAVE_ITERATES | OFV_FLAG_SAVED_FORWARD;
+
+bool same_image(const ofv_image& a, const ofv_image& b) {
+  return a.data == b.data && a.width == b.width && a.height == b.height && a.pitch == b.pitch && a.type == b.type &&
+         a.bit_depth == b.bit_depth;
+}
+
+bool same_params(const ofv_params& a, const ofv_params& b) {
+  return a.num_levels == b.num_levels && a.kernel_radius == b.kernel_radius && a.iterations == b.iterations &&
+         a.norm_radius == b.norm_radius && a.norm_eps == b.norm_eps && a.reg_rel == b.reg_rel &&
+         a.reg_abs == b.reg_abs && a.storage == b.storage && (a.flags & ~kSaveFlags) == (b.flags & ~kSaveFlags);
+}
+
+void record_saved_forward(ofv_ctx* h, int n, const ofv_image* f0, const ofv_image* f1, const float* const* init,
+                          const ofv_params* p) {
+  auto& sf = h->saved_fw;
+  sf.valid = true;
+  sf.n = n;
+  sf.params = *p;
+  sf.f0.assign(f0, f0 + n);
+  sf.f1.assign(f1, f1 + n);
+  sf.init.assign(n, nullptr);
+  for (int j = 0; j < n; ++j) sf.init[j] = init ? init[j] : nullptr;
+}
+
+bool saved_forward_matches(const ofv_ctx* h, int n, const ofv_image* f0, const ofv_image* f1,
+                           const float* const* init, const ofv_params* p) {
+  const auto& sf = h->saved_fw;
+  if (!sf.valid || sf.n != n || !same_params(sf.params, *p)) return false;
+  for (int j = 0; j < n; ++j)
+    if (!same_image(sf.f0[j], f0[j]) || !same_image(sf.f1[j], f1[j]) || sf.init[j] != (init ? init[j] : nullptr))
+      return false;
+  return true;
+}
+
+// A forward that saves its iterates for the adjoint (OFV_FLAG_SAVE_ITERATES):
+// the adjoint's estimator and storage, and a reservation that holds them.
+ofv_status check_saving(ofv_ctx* h, int n, const ofv_params* p) {
+  if (p->flags & (OFV_FLAG_FORWARD_ADDITIVE | OFV_FLAG_INCREMENT_UPDATE))
+    return fail(h, OFV_ERR_UNSUPPORTED, "the adjoint covers the symmetric estimator's consistent update only");
+  if (p->storage != OFV_STORE_F32) return fail(h, OFV_ERR_UNSUPPORTED, "the adjoint needs F32 storage");
+  const bool sa = (p->flags & OFV_FLAG_STORE_ALL) != 0;
+  if (!h->bw || p->num_levels > h->bw_levels || p->iterations > h->bw_iters || n > h->bw_pairs ||
+      (sa && !h->bw_store_all))
+    return fail(h, OFV_ERR_CAPACITY,
+                "backward workspace holds %d levels x %d iterations x %d pairs%s; call ofv_reserve_backward_ex",
+                h->bw_levels, h->bw_iters, h->bw_pairs, h->bw_store_all ? " (store-all)" : "");
+  return OFV_OK;
+}
+
 ofv_status compute_common(ofv_ctx* h, int n, const ofv_image* f0, const ofv_image* f1, const ofv_params* p,
                           const float* const* init, float* const* out) {
   if (check_handle(h) != OFV_OK) return OFV_ERR_INVALID_ARG;
@@ -639,6 +920,11 @@ ofv_status compute_common(ofv_ctx* h, int n, const ofv_image* f0, const ofv_imag
       if (overlap(a0, a1, c0, c1)) return fail(h, OFV_ERR_INVALID_ARG, "flow_out[%d] overlaps frame1[%d]", j, i);
     }
   }
+  const bool save = (p->flags & OFV_FLAG_SAVE_ITERATES) != 0;
+  if (save) {
+    r = check_saving(h, n, p);
+    if (r != OFV_OK) return r;
+  }
   if (fault_injected("launch")) return fail(h, OFV_ERR_DEVICE, "injected launch failure");
   if (h->device < 0) return fail(h, OFV_ERR_UNSUPPORTED, "validation-only handle (created with device -1)");
   DeviceGuard g(h->device);
@@ -651,7 +937,12 @@ ofv_status compute_common(ofv_ctx* h, int n, const ofv_image* f0, const ofv_imag
     pp[j].slot = h->ws + static_cast<size_t>(j) * h->slot_bytes;
     level_dims(f0[j].width, f0[j].height, p->num_levels, pp[j].lw, pp[j].lh);
   }
-  return run_pipeline(h, n, pp.data(), p);
+  if (!save) return run_pipeline(h, n, pp.data(), p);
+  BwPlan bp(h, n, p);
+  bp.pp = pp;
+  r = bp.forward();
+  if (r == OFV_OK) record_saved_forward(h, n, f0, f1, init, p);
+  return r;
 }
 
 // Workspace layout of a handle for pairs up to w x hgt: level sizes and
@@ -823,6 +1114,8 @@ ofv_status ofv_compute_flow_static(const ofv_image* frame0, const ofv_image* fra
   ofv_ctx c;  // host-side plan of the call: it owns no device memory
   ofv_status r = check_params(&c, params);
   if (r != OFV_OK) return static_fail(&c, r);
+  if (params->flags & OFV_FLAG_SAVE_ITERATES)
+    return static_fail(&c, fail(&c, OFV_ERR_UNSUPPORTED, "saved iterates live in a handle's backward workspace"));
   r = check_image(&c, frame0, "frame0");
   if (r != OFV_OK) return static_fail(&c, r);
   r = check_image(&c, frame1, "frame1");
@@ -861,286 +1154,372 @@ ofv_status ofv_compute_flow_static(const ofv_image* frame0, const ofv_image* fra
 
 // ------------------------------------------------------------------ adjoint
 
-namespace {
 
-constexpr int kBwPlanes = 41;  // scratch planes of level-0 size used by the backward pass
-
-size_t bw_saved_floats(const ofv_ctx* h, int levels, int iters) {
-  size_t n = 0;
-  for (int l = 0; l < levels; ++l) n += static_cast<size_t>(iters) * 2 * h->lpitch[l] * h->lh[l];
-  return n;
-}
-
-}  // namespace
-
-ofv_status ofv_reserve_backward(ofv_handle h, int max_levels, int max_iterations) {
+ofv_status ofv_backward_workspace_bytes(ofv_handle h, int max_levels, int max_iterations, int max_pairs,
+                                        uint32_t mode, size_t* bytes) {
   if (check_handle(h) != OFV_OK) return OFV_ERR_INVALID_ARG;
+  if (!bytes) return fail(h, OFV_ERR_INVALID_ARG, "bytes is NULL");
   if (max_levels < 1 || max_levels > OFV_MAX_LEVELS)
     return fail(h, OFV_ERR_INVALID_ARG, "max_levels %d outside 1..%d", max_levels, OFV_MAX_LEVELS);
   if (max_iterations < 1 || max_iterations > 64)
     return fail(h, OFV_ERR_INVALID_ARG, "max_iterations %d outside 1..64", max_iterations);
+  if (max_pairs < 1 || max_pairs > h->max_batch)
+    return fail(h, OFV_ERR_INVALID_ARG, "max_pairs %d outside 1..%d (the handle's max_batch)", max_pairs,
+                h->max_batch);
+  if (mode & ~OFV_BACKWARD_STORE_ALL) return fail(h, OFV_ERR_INVALID_ARG, "unknown mode 0x%x", mode);
+  *bytes = bw_total_bytes(h, max_levels, max_iterations, max_pairs, (mode & OFV_BACKWARD_STORE_ALL) != 0);
+  return OFV_OK;
+}
+
+ofv_status ofv_reserve_backward_ex(ofv_handle h, int max_levels, int max_iterations, int max_pairs, uint32_t mode) {
+  size_t bytes = 0;
+  ofv_status r = ofv_backward_workspace_bytes(h, max_levels, max_iterations, max_pairs, mode, &bytes);
+  if (r != OFV_OK) return r;
   if (h->device < 0) return fail(h, OFV_ERR_UNSUPPORTED, "validation-only handle (created with device -1)");
-  if (max_levels <= h->bw_levels && max_iterations <= h->bw_iters && h->bw) return OFV_OK;
-  DeviceGuard g(h->device);
-  const size_t plane0 = static_cast<size_t>(h->lpitch[0]) * h->lh[0];
-  const size_t floats = bw_saved_floats(h, max_levels, max_iterations) + kBwPlanes * plane0 + h->frame_bytes / 2;
+  const bool store_all = (mode & OFV_BACKWARD_STORE_ALL) != 0;
+  if (h->bw && max_levels <= h->bw_levels && max_iterations <= h->bw_iters && max_pairs <= h->bw_pairs &&
+      (!store_all || h->bw_store_all))
+    return OFV_OK;
+  // grow to cover the previous reservation too
   if (h->bw) {
+    max_levels = std::max(max_levels, h->bw_levels);
+    max_iterations = std::max(max_iterations, h->bw_iters);
+    max_pairs = std::max(max_pairs, h->bw_pairs);
+    const bool sa = store_all || h->bw_store_all;
+    bytes = bw_total_bytes(h, max_levels, max_iterations, max_pairs, sa);
+    mode = sa ? OFV_BACKWARD_STORE_ALL : 0u;
+  }
+  DeviceGuard g(h->device);
+  if (h->bw) {
+    h->saved_fw.valid = false;
     if (sync_stream(h->stream) != hipSuccess || hipFree(h->bw) != hipSuccess)
       return fail(h, OFV_ERR_DEVICE, "releasing the previous backward workspace failed");
     h->bw = nullptr;
     h->bw_bytes = 0;
-    h->bw_levels = h->bw_iters = 0;
+    h->bw_levels = h->bw_iters = h->bw_pairs = 0;
+    h->bw_store_all = false;
   }
   if (fault_injected("alloc")) return fail(h, OFV_ERR_OUT_OF_MEMORY, "injected allocation failure");
-  hipError_t e = hipMalloc(reinterpret_cast<void**>(&h->bw), floats * sizeof(float));
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&h->bw), bytes);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     h->bw = nullptr;
-    return fail(h, OFV_ERR_OUT_OF_MEMORY, "hipMalloc(%zu bytes): %s", floats * sizeof(float), hipGetErrorString(e));
+    return fail(h, OFV_ERR_OUT_OF_MEMORY, "hipMalloc(%zu bytes): %s", bytes, hipGetErrorString(e));
   }
-  h->bw_bytes = floats * sizeof(float);
+  h->bw_bytes = bytes;
   h->bw_levels = max_levels;
   h->bw_iters = max_iterations;
+  h->bw_pairs = max_pairs;
+  h->bw_store_all = (mode & OFV_BACKWARD_STORE_ALL) != 0;
   return OFV_OK;
 }
+
+ofv_status ofv_reserve_backward(ofv_handle h, int max_levels, int max_iterations) {
+  return ofv_reserve_backward_ex(h, max_levels, max_iterations, 1, 0u);
+}
+
+namespace {
+
+ofv_status backward_common(ofv_ctx* h, int n, const ofv_image* f0, const ofv_image* f1, const ofv_params* params,
+                           const float* const* init, const float* const* gflow, float* const* gf0,
+                           float* const* gf1, float* const* ginit) {
+  if (check_handle(h) != OFV_OK) return OFV_ERR_INVALID_ARG;
+  if (n < 1) return fail(h, OFV_ERR_INVALID_ARG, "batch size %d < 1", n);
+  if (!f0 || !f1 || !gflow) return fail(h, OFV_ERR_INVALID_ARG, "frame or grad_flow array is NULL");
+  ofv_status r = check_params(h, params);
+  if (r != OFV_OK) return r;
+  if (params->flags & (OFV_FLAG_FORWARD_ADDITIVE | OFV_FLAG_INCREMENT_UPDATE))
+    return fail(h, OFV_ERR_UNSUPPORTED, "the adjoint covers the symmetric estimator's consistent update only");
+  if (params->storage != OFV_STORE_F32) return fail(h, OFV_ERR_UNSUPPORTED, "the adjoint needs F32 storage");
+  if (n > h->max_batch) return fail(h, OFV_ERR_CAPACITY, "batch %d exceeds max_batch %d", n, h->max_batch);
+  // every input range, then every output range: outputs may overlap nothing
+  std::vector<std::pair<uintptr_t, uintptr_t>> rng;
+  for (int j = 0; j < n; ++j) {
+    r = check_image(h, &f0[j], "frame0");
+    if (r != OFV_OK) return r;
+    r = check_image(h, &f1[j], "frame1");
+    if (r != OFV_OK) return r;
+    if (f0[j].width != f1[j].width || f0[j].height != f1[j].height)
+      return fail(h, OFV_ERR_INVALID_ARG, "pair %d: frame sizes differ", j);
+    if (f0[j].width > h->max_w || f0[j].height > h->max_h)
+      return fail(h, OFV_ERR_CAPACITY, "pair %d: %dx%d exceeds the handle's %dx%d", j, f0[j].width, f0[j].height,
+                  h->max_w, h->max_h);
+    if (!gflow[j]) return fail(h, OFV_ERR_INVALID_ARG, "pair %d: grad_flow is NULL", j);
+    if (ginit && ginit[j] && !(init && init[j]))
+      return fail(h, OFV_ERR_INVALID_ARG, "pair %d: grad_flow_init needs flow_init", j);
+    const uintptr_t n1 = static_cast<uintptr_t>(f0[j].width) * f0[j].height * sizeof(float);
+    uintptr_t a0, a1;
+    image_range(&f0[j], a0, a1);
+    rng.emplace_back(a0, a1);
+    image_range(&f1[j], a0, a1);
+    rng.emplace_back(a0, a1);
+    const uintptr_t gf = reinterpret_cast<uintptr_t>(gflow[j]);
+    rng.emplace_back(gf, gf + 2 * n1);
+    if (init && init[j]) {
+      const uintptr_t fi = reinterpret_cast<uintptr_t>(init[j]);
+      rng.emplace_back(fi, fi + 2 * n1);
+    }
+  }
+  const size_t nin = rng.size();
+  for (int j = 0; j < n; ++j) {
+    const uintptr_t n1 = static_cast<uintptr_t>(f0[j].width) * f0[j].height * sizeof(float);
+    const float* outs[3] = {gf0 ? gf0[j] : nullptr, gf1 ? gf1[j] : nullptr, ginit ? ginit[j] : nullptr};
+    const uintptr_t len[3] = {n1, n1, 2 * n1};
+    for (int i = 0; i < 3; ++i) {
+      if (!outs[i]) continue;
+      const uintptr_t o0 = reinterpret_cast<uintptr_t>(outs[i]);
+      for (size_t k = 0; k < rng.size(); ++k)
+        if (overlap(o0, o0 + len[i], rng[k].first, rng[k].second))
+          return fail(h, OFV_ERR_INVALID_ARG, "pair %d: gradient output %d overlaps %s", j, i,
+                      k < nin ? "an input" : "another gradient output");
+      rng.emplace_back(o0, o0 + len[i]);
+    }
+  }
+  const int L = params->num_levels, IT = params->iterations;
+  const bool store_all = (params->flags & OFV_FLAG_STORE_ALL) != 0;
+  r = check_saving(h, n, params);
+  if (r != OFV_OK) return r;
+  if (fault_injected("launch")) return fail(h, OFV_ERR_DEVICE, "injected launch failure");
+  if (h->device < 0) return fail(h, OFV_ERR_UNSUPPORTED, "validation-only handle (created with device -1)");
+  DeviceGuard g(h->device);
+  hipStream_t s = h->stream;
+  const BwView bv(h);
+  const int kr = params->kernel_radius;
+  const int sp0 = static_cast<int>(h->lpitch[0]);
+  const int plane0 = static_cast<int>(h->lpitch[0] * h->lh[0]);
+
+  BwPlan bp(h, n, params);
+  for (int j = 0; j < n; ++j) {
+    PairPlan& q = bp.pp[j];
+    q.f[0] = &f0[j];
+    q.f[1] = &f1[j];
+    q.init = init ? init[j] : nullptr;
+    q.out = nullptr;
+    q.slot = h->ws + static_cast<size_t>(j) * h->slot_bytes;
+    level_dims(f0[j].width, f0[j].height, L, q.lw, q.lh);
+  }
+  std::vector<PairPlan>& pp = bp.pp;
+  auto lp = [&](int l) { return bp.lp(l); };
+  auto lplane = [&](int l) { return bp.lplane(l); };
+  using Field = BwPlan::Field;
+  auto vin0 = [&](int j, int l) { return bp.vin0(j, l); };
+
+  // ---- forward, keeping each iteration's output (store-all: and its record),
+  // unless the handle holds the saved forward of exactly these inputs
+  if (!((params->flags & OFV_FLAG_SAVED_FORWARD) && saved_forward_matches(h, n, f0, f1, init, params))) {
+    r = bp.forward();
+    if (r != OFV_OK) return r;
+    record_saved_forward(h, n, f0, f1, init, params);
+  }
+
+  // ---- backward
+  hipError_t e = launch_fill(bv.gpyr_all(), static_cast<int64_t>(bv.lay.gpyr) * n, 0.0f, s);
+  if (e != hipSuccess) return device_error(h, e, "fill");
+  // gradient fields in rotation: scratch planes 7 + 2i (u) and 8 + 2i (v); -1 = the caller's grad_flow
+  auto gbuf = [&](int j, int i) { return bv.scratch(j, 7 + 2 * i); };
+  int gcur = -1;
+  for (int l = 0; l < L; ++l) {
+    for (int k = IT - 1; k >= 0; --k) {
+      if (k == 0 && !store_all) {
+        r = bp.prepare_vin0(l);
+        if (r != OFV_OK) return r;
+      }
+      const int gnext = (gcur + 1 + 3) % 3;
+      AdjArgs aa{};
+      aa.reg_rel = params->reg_rel;
+      aa.reg_abs = params->reg_abs;
+      aa.no_fp64 = 0;
+      auto fill = [&](int j, AdjJob& J) {
+        J = AdjJob{};
+        J.p0 = reinterpret_cast<const float*>(img_plane(h, pp[j], 0, l, 4));
+        J.p1 = reinterpret_cast<const float*>(img_plane(h, pp[j], 1, l, 4));
+        J.ip = lp(l);
+        if (k == 0) {
+          const Field f = vin0(j, l);
+          J.vu = f.u;
+          J.vv = f.u + f.vstep;
+          J.vp = f.pitch;
+        } else {
+          J.vu = bv.saved(j, l, k - 1);
+          J.vv = J.vu + lplane(l);
+          J.vp = lp(l);
+        }
+        if (gcur < 0) {
+          J.gu = gflow[j];
+          J.gv = gflow[j] + static_cast<int64_t>(f0[j].width) * f0[j].height;
+          J.gp = f0[j].width;
+        } else {
+          J.gu = gbuf(j, gcur);
+          J.gv = J.gu + plane0;
+          J.gp = sp0;
+        }
+        J.gA = bv.scratch(j, 0);
+        J.sp = sp0;
+        J.ps = plane0;
+        if (store_all) {
+          J.st = bv.rec(j, l, k);
+          J.stp = lp(l);
+          J.sts = lplane(l);
+        }
+        J.ou = gbuf(j, gnext);
+        J.ov = J.ou + plane0;
+        J.op = sp0;
+        J.gP0 = bv.gpyr(j, 0, l);
+        J.gP1 = bv.gpyr(j, 1, l);
+        J.w = pp[j].lw[l];
+        J.h = pp[j].lh[l];
+      };
+      int blocks = 0;
+      r = run_jobs(h, n, aa, [&](int j, AdjJob& J) {
+        if ((j % kMaxJobs) == 0) blocks = 0;
+        fill(j, J);
+        J.tile_start = blocks;
+        blocks += store_all ? adj_point_blocks(J.w, J.h) : adj_sums_blocks(J.w, J.h);
+      }, [&](const AdjArgs& a) {
+        return store_all ? launch_adj_solve_stored(a, blocks, s) : launch_adj_sums(a, kr, ADJ_SOLVE, blocks, s);
+      }, "solve adjoint");
+      if (r != OFV_OK) return r;
+      r = run_jobs(h, n, aa, [&](int j, AdjJob& J) {
+        if ((j % kMaxJobs) == 0) blocks = 0;
+        fill(j, J);
+        J.tile_start = blocks;
+        blocks += adj_scatter_blocks(J.w, J.h);
+      }, [&](const AdjArgs& a) { return launch_adj_scatter(a, kr, store_all, blocks, s); }, "warp adjoint");
+      if (r != OFV_OK) return r;
+      gcur = gnext;
+    }
+    if (l < L - 1) {
+      // gradient w.r.t. the coarser level's last output: transpose of the up-sampling
+      const int gacc = (gcur + 1) % 3;
+      AuxArgs ua{};
+      int mw = 0, mh = 0;
+      for (int j = 0; j < n; ++j) mw = std::max(mw, pp[j].lw[l + 1]), mh = std::max(mh, pp[j].lh[l + 1]);
+      r = run_jobs(h, n, ua, [&](int j, AuxJob& J) {
+        J.in0 = gbuf(j, gcur);
+        J.in1 = J.in0 + plane0;
+        J.ip = sp0;
+        J.w = pp[j].lw[l];
+        J.h = pp[j].lh[l];
+        J.out0 = gbuf(j, gacc);
+        J.out1 = J.out0 + plane0;
+        J.op = sp0;
+        J.cw = pp[j].lw[l + 1];
+        J.ch = pp[j].lh[l + 1];
+      }, [&](const AuxArgs& a) { return launch_upsample_adj(a, mw, mh, s); }, "up-sampling adjoint");
+      if (r != OFV_OK) return r;
+      gcur = gacc;
+    }
+  }
+  // gbuf(j, gcur): gradient w.r.t. the coarsest level's input field = the restricted initial field
+  std::vector<int> wi;
+  for (int j = 0; j < n; ++j)
+    if (ginit && ginit[j]) wi.push_back(j);
+  if (!wi.empty()) {
+    if (L == 1) {
+      for (int j : wi)
+        for (int c = 0; c < 2; ++c) {
+          e = hipMemcpy2DAsync(ginit[j] + static_cast<int64_t>(c) * f0[j].width * f0[j].height,
+                               f0[j].width * sizeof(float), gbuf(j, gcur) + c * plane0, sp0 * sizeof(float),
+                               f0[j].width * sizeof(float), f0[j].height, hipMemcpyDeviceToDevice, s);
+          if (e != hipSuccess) return device_error(h, e, "copy");
+        }
+    } else {
+      int cur = gcur;
+      for (int l = L - 1; l >= 1; --l) {
+        const bool last = (l == 1);
+        const int tgt = (cur + 1) % 3;
+        AuxArgs ra{};
+        ra.scale = 0.5f;
+        ra.accumulate = 0;
+        int mw = 0, mh = 0;
+        for (int j : wi) mw = std::max(mw, pp[j].lw[l - 1]), mh = std::max(mh, pp[j].lh[l - 1]);
+        const int nw = static_cast<int>(wi.size());
+        r = run_jobs(h, 2 * nw, ra, [&](int i, AuxJob& J) {
+          const int j = wi[i / 2], c = i % 2;
+          J.in0 = gbuf(j, cur) + c * plane0;
+          J.ip = sp0;
+          J.cw = pp[j].lw[l];
+          J.ch = pp[j].lh[l];
+          J.w = pp[j].lw[l - 1];
+          J.h = pp[j].lh[l - 1];
+          if (last) {
+            J.out0 = ginit[j] + static_cast<int64_t>(c) * f0[j].width * f0[j].height;
+            J.op = f0[j].width;
+          } else {
+            J.out0 = gbuf(j, tgt) + c * plane0;
+            J.op = sp0;
+          }
+        }, [&](const AuxArgs& a) { return launch_reduce_adj(a, mw, mh, s); }, "restriction adjoint");
+        if (r != OFV_OK) return r;
+        cur = tgt;
+      }
+    }
+  }
+  // image-gradient pyramids: REDUCE transposed, coarse to fine, both frames of every pair
+  for (int l = L - 1; l >= 1; --l) {
+    AuxArgs ra{};
+    ra.scale = 1.0f;
+    ra.accumulate = 1;
+    int mw = 0, mh = 0;
+    for (int j = 0; j < n; ++j) mw = std::max(mw, pp[j].lw[l - 1]), mh = std::max(mh, pp[j].lh[l - 1]);
+    r = run_jobs(h, 2 * n, ra, [&](int i, AuxJob& J) {
+      const int j = i / 2, f = i % 2;
+      J.in0 = bv.gpyr(j, f, l);
+      J.ip = lp(l);
+      J.cw = pp[j].lw[l];
+      J.ch = pp[j].lh[l];
+      J.out0 = bv.gpyr(j, f, l - 1);
+      J.op = lp(l - 1);
+      J.w = pp[j].lw[l - 1];
+      J.h = pp[j].lh[l - 1];
+    }, [&](const AuxArgs& a) { return launch_reduce_adj(a, mw, mh, s); }, "pyramid adjoint");
+    if (r != OFV_OK) return r;
+  }
+  // normalisation (and intensity scaling) transposed, every requested frame gradient
+  std::vector<std::pair<int, int>> nf;
+  for (int j = 0; j < n; ++j) {
+    if (gf0 && gf0[j]) nf.emplace_back(j, 0);
+    if (gf1 && gf1[j]) nf.emplace_back(j, 1);
+  }
+  if (!nf.empty()) {
+    NormAdjArgs na{};
+    na.nr = params->norm_radius;
+    na.eps = params->norm_eps;
+    int mw = 0, mh = 0;
+    for (const auto& q : nf) mw = std::max(mw, f0[q.first].width), mh = std::max(mh, f0[q.first].height);
+    r = run_jobs(h, static_cast<int>(nf.size()), na, [&](int i, NormAdjJob& J) {
+      const int j = nf[i].first, f = nf[i].second;
+      const ofv_image* fr = f == 0 ? &f0[j] : &f1[j];
+      J.f = ImageIn{fr->data, fr->pitch, fr->width, fr->height, fr->type, fr->bit_depth};
+      J.gN = bv.gpyr(j, f, 0);
+      J.gp = lp(0);
+      J.gF = f == 0 ? gf0[j] : gf1[j];
+      J.fp = fr->width;
+    }, [&](const NormAdjArgs& a) { return launch_norm_adj(a, mw, mh, s); }, "normalisation adjoint");
+    if (r != OFV_OK) return r;
+  }
+  return OFV_OK;
+}
+
+}  // namespace
 
 ofv_status ofv_compute_flow_backward(ofv_handle h, const ofv_image* frame0, const ofv_image* frame1,
                                      const ofv_params* params, const float* flow_init, const float* grad_flow,
                                      float* grad_frame0, float* grad_frame1, float* grad_flow_init) {
   if (check_handle(h) != OFV_OK) return OFV_ERR_INVALID_ARG;
-  ofv_status r = check_params(h, params);
-  if (r != OFV_OK) return r;
-  if (params->flags & (OFV_FLAG_FORWARD_ADDITIVE | OFV_FLAG_INCREMENT_UPDATE))
-    return fail(h, OFV_ERR_UNSUPPORTED, "the adjoint covers the symmetric estimator's consistent update only");
-  r = check_image(h, frame0, "frame0");
-  if (r != OFV_OK) return r;
-  r = check_image(h, frame1, "frame1");
-  if (r != OFV_OK) return r;
-  if (frame0->width != frame1->width || frame0->height != frame1->height)
-    return fail(h, OFV_ERR_INVALID_ARG, "frame sizes differ");
-  if (frame0->width > h->max_w || frame0->height > h->max_h)
-    return fail(h, OFV_ERR_CAPACITY, "%dx%d exceeds the handle's %dx%d", frame0->width, frame0->height, h->max_w,
-                h->max_h);
+  if (!frame0 || !frame1) return fail(h, OFV_ERR_INVALID_ARG, "frame0 or frame1 is NULL");
   if (!grad_flow) return fail(h, OFV_ERR_INVALID_ARG, "grad_flow is NULL");
   if (grad_flow_init && !flow_init) return fail(h, OFV_ERR_INVALID_ARG, "grad_flow_init needs flow_init");
-  if (params->storage != OFV_STORE_F32) return fail(h, OFV_ERR_UNSUPPORTED, "the adjoint needs F32 storage");
-  const int W = frame0->width, H = frame0->height;
-  const uintptr_t n1 = static_cast<uintptr_t>(W) * H * sizeof(float);
-  {
-    // outputs must not overlap the inputs or each other
-    uintptr_t rng[7][2];
-    int cnt = 0;
-    uintptr_t a0, a1;
-    image_range(frame0, a0, a1);
-    rng[cnt][0] = a0, rng[cnt++][1] = a1;
-    image_range(frame1, a0, a1);
-    rng[cnt][0] = a0, rng[cnt++][1] = a1;
-    const uintptr_t gf = reinterpret_cast<uintptr_t>(grad_flow);
-    rng[cnt][0] = gf, rng[cnt++][1] = gf + 2 * n1;
-    if (flow_init) {
-      const uintptr_t fi = reinterpret_cast<uintptr_t>(flow_init);
-      rng[cnt][0] = fi, rng[cnt++][1] = fi + 2 * n1;
-    }
-    const int nin = cnt;
-    const float* outs[3] = {grad_frame0, grad_frame1, grad_flow_init};
-    const uintptr_t len[3] = {n1, n1, 2 * n1};
-    for (int i = 0; i < 3; ++i) {
-      if (!outs[i]) continue;
-      const uintptr_t o0 = reinterpret_cast<uintptr_t>(outs[i]);
-      for (int k = 0; k < cnt; ++k)
-        if (overlap(o0, o0 + len[i], rng[k][0], rng[k][1]))
-          return fail(h, OFV_ERR_INVALID_ARG, "gradient output %d overlaps %s", i,
-                      k < nin ? "an input" : "another gradient output");
-      rng[cnt][0] = o0, rng[cnt++][1] = o0 + len[i];
-    }
-  }
-  const int L = params->num_levels, IT = params->iterations;
-  if (!h->bw || L > h->bw_levels || IT > h->bw_iters)
-    return fail(h, OFV_ERR_CAPACITY, "backward workspace holds %d levels x %d iterations; call ofv_reserve_backward",
-                h->bw_levels, h->bw_iters);
-  if (fault_injected("launch")) return fail(h, OFV_ERR_DEVICE, "injected launch failure");
-  if (h->device < 0) return fail(h, OFV_ERR_UNSUPPORTED, "validation-only handle (created with device -1)");
-  DeviceGuard g(h->device);
-  hipStream_t s = h->stream;
+  return backward_common(h, 1, frame0, frame1, params, &flow_init, &grad_flow, &grad_frame0, &grad_frame1,
+                         &grad_flow_init);
+}
 
-  // ---- workspace carving
-  std::vector<float*> save(static_cast<size_t>(L) * IT);
-  float* cursor = h->bw;
-  for (int l = 0; l < L; ++l)
-    for (int k = 0; k < IT; ++k) {
-      save[l * IT + k] = cursor;
-      cursor += 2 * h->lpitch[l] * h->lh[l];
-    }
-  cursor = h->bw + bw_saved_floats(h, h->bw_levels, h->bw_iters);
-  const int64_t plane0 = h->lpitch[0] * h->lh[0];
-  float* pl[kBwPlanes];
-  for (int i = 0; i < kBwPlanes; ++i) pl[i] = cursor + i * plane0;
-  float* gpyr = cursor + kBwPlanes * plane0;  // two frames, same level offsets as the pyramid slabs
-  const int sp = static_cast<int>(h->lpitch[0]);
-
-  // ---- forward, keeping every iteration's output
-  PairPlan pp{};
-  pp.f[0] = frame0;
-  pp.f[1] = frame1;
-  pp.init = flow_init;
-  pp.out = nullptr;
-  pp.slot = h->ws;
-  level_dims(W, H, L, pp.lw, pp.lh);
-  r = run_pipeline(h, 1, &pp, params, save.data());
-  if (r != OFV_OK) return r;
-
-  // image-gradient pyramids: frame f, level l at gpyr + f * slab + img_off[l]
-  const int64_t slab = static_cast<int64_t>(h->frame_bytes / 4);
-  auto gP = [&](int f, int l) { return gpyr + f * slab + h->img_off[l]; };
-  hipError_t e = launch_fill(gpyr, 2 * slab, 0.0f, s);
-  if (e != hipSuccess) return device_error(h, e, "fill");
-
-  // gradient plane pairs (u plane, v plane one plane0 apart): three in rotation
-  float* gbuf[3] = {pl[30], pl[32], pl[34]};
-  float* vup = pl[36];  // up-sampled input field of a level's first iteration (pair)
-  const float* gu = grad_flow;
-  const float* gv = grad_flow + static_cast<int64_t>(W) * H;
-  int gpitch = W;
-  int gcur = -1;  // index into gbuf, -1 = the caller's grad_flow
-
-  for (int l = 0; l < L; ++l) {
-    const int lw = pp.lw[l], lh = pp.lh[l];
-    for (int k = IT - 1; k >= 0; --k) {
-      const float* vu;
-      const float* vv;
-      int vp;
-      if (k >= 1) {
-        vu = save[l * IT + k - 1];
-        vv = vu + h->lpitch[l] * h->lh[l];
-        vp = static_cast<int>(h->lpitch[l]);
-      } else if (l < L - 1) {
-        UpsampleArgs ua{};
-        ua.in_u = save[(l + 1) * IT + IT - 1];
-        ua.in_v = ua.in_u + h->lpitch[l + 1] * h->lh[l + 1];
-        ua.in_pitch = h->lpitch[l + 1];
-        ua.cw = pp.lw[l + 1];
-        ua.ch = pp.lh[l + 1];
-        ua.out_u = vup;
-        ua.out_v = vup + plane0;
-        ua.out_pitch = sp;
-        ua.w = lw;
-        ua.h = lh;
-        e = launch_upsample(ua, s);
-        if (e != hipSuccess) return device_error(h, e, "upsample");
-        vu = vup;
-        vv = vup + plane0;
-        vp = sp;
-      } else if (flow_init) {
-        const float* b = flow_buf(h, pp, L == 1 ? 1 : (L - 1) & 1);
-        vu = b;
-        vv = b + h->lpitch[l] * h->lh[l];
-        vp = static_cast<int>(h->lpitch[l]);
-      } else {
-        e = launch_fill(vup, 2 * plane0, 0.0f, s);
-        if (e != hipSuccess) return device_error(h, e, "fill");
-        vu = vup;
-        vv = vup + plane0;
-        vp = sp;
-      }
-      const int gnext = (gcur + 1 + 3) % 3;
-      AdjLevel a{};
-      a.w = lw;
-      a.h = lh;
-      a.kr = params->kernel_radius;
-      a.reg_rel = params->reg_rel;
-      a.reg_abs = params->reg_abs;
-      a.p0 = reinterpret_cast<const float*>(img_plane(h, pp, 0, l, 4));
-      a.p1 = reinterpret_cast<const float*>(img_plane(h, pp, 1, l, 4));
-      a.ip = static_cast<int>(h->lpitch[l]);
-      a.vu = vu;
-      a.vv = vv;
-      a.vp = vp;
-      a.gu = gu;
-      a.gv = gv;
-      a.gp = gpitch;
-      a.ou = gbuf[gnext];
-      a.ov = gbuf[gnext] + plane0;
-      a.op = sp;
-      a.gP0 = gP(0, l);
-      a.gP1 = gP(1, l);
-      a.sp = sp;
-      a.S = pl[0];
-      a.T = pl[1];
-      a.GX = pl[2];
-      a.GY = pl[3];
-      a.B = pl[4];
-      for (int q = 0; q < 5; ++q) {
-        a.A[q] = pl[5 + q];
-        a.gA[q] = pl[10 + q];
-        a.tmp[q] = pl[15 + q];
-      }
-      a.gGx = pl[20];
-      a.gGy = pl[21];
-      a.gT = pl[22];
-      a.gVu = pl[23];
-      a.gVv = pl[24];
-      e = launch_adj_iteration(a, s);
-      if (e != hipSuccess) return device_error(h, e, "adjoint iteration");
-      gcur = gnext;
-      gu = gbuf[gcur];
-      gv = gbuf[gcur] + plane0;
-      gpitch = sp;
-    }
-    if (l < L - 1) {
-      // gradient w.r.t. the coarser level's last output: transpose of the up-sampling
-      const int gacc = (gcur + 1) % 3;
-      e = launch_fill(gbuf[gacc], 2 * plane0, 0.0f, s);
-      if (e != hipSuccess) return device_error(h, e, "fill");
-      e = launch_upsample_adj(gu, gv, lw, lh, sp, gbuf[gacc], gbuf[gacc] + plane0, pp.lw[l + 1], pp.lh[l + 1], sp, s);
-      if (e != hipSuccess) return device_error(h, e, "upsample adjoint");
-      gcur = gacc;
-      gu = gbuf[gcur];
-      gv = gbuf[gcur] + plane0;
-    }
-  }
-  // gu, gv: gradient w.r.t. the coarsest level's input field = the restricted initial field
-  if (grad_flow_init) {
-    float* cu = const_cast<float*>(gu);
-    for (int l = L - 1; l >= 1; --l) {
-      const bool last = (l == 1);
-      const int tgt = (gcur + 1) % 3;
-      for (int c = 0; c < 2; ++c) {
-        float* dst = last ? grad_flow_init + static_cast<int64_t>(c) * W * H : gbuf[tgt] + c * plane0;
-        e = launch_reduce_adj(cu + c * plane0, pp.lw[l], pp.lh[l], sp, dst, pp.lw[l - 1], pp.lh[l - 1],
-                              last ? W : sp, 0.5f, 0, s);
-        if (e != hipSuccess) return device_error(h, e, "restriction adjoint");
-      }
-      gcur = tgt;
-      cu = gbuf[gcur];
-    }
-    if (L == 1) {
-      for (int c = 0; c < 2; ++c) {
-        e = hipMemcpy2DAsync(grad_flow_init + static_cast<int64_t>(c) * W * H, W * sizeof(float), cu + c * plane0,
-                             sp * sizeof(float), W * sizeof(float), H, hipMemcpyDeviceToDevice, s);
-        if (e != hipSuccess) return device_error(h, e, "copy");
-      }
-    }
-  }
-  // image-gradient pyramids: REDUCE transposed, coarse to fine
-  for (int f = 0; f < 2; ++f)
-    for (int l = L - 1; l >= 1; --l) {
-      e = launch_reduce_adj(gP(f, l), pp.lw[l], pp.lh[l], static_cast<int>(h->lpitch[l]), gP(f, l - 1), pp.lw[l - 1],
-                            pp.lh[l - 1], static_cast<int>(h->lpitch[l - 1]), 1.0f, 1, s);
-      if (e != hipSuccess) return device_error(h, e, "pyramid adjoint");
-    }
-  // normalisation (and intensity scaling) transposed
-  float* outs[2] = {grad_frame0, grad_frame1};
-  const ofv_image* fr[2] = {frame0, frame1};
-  for (int f = 0; f < 2; ++f) {
-    if (!outs[f]) continue;
-    ImageIn in{fr[f]->data, fr[f]->pitch, W, H, fr[f]->type, fr[f]->bit_depth};
-    float* scratch[8];
-    for (int i = 0; i < 8; ++i) scratch[i] = pl[5 + i];
-    e = launch_norm_adj(in, params->norm_radius, params->norm_eps, gP(f, 0), static_cast<int>(h->lpitch[0]), scratch,
-                        sp, outs[f], W, s);
-    if (e != hipSuccess) return device_error(h, e, "normalisation adjoint");
-  }
-  return OFV_OK;
+ofv_status ofv_compute_flow_backward_batch(ofv_handle h, int n, const ofv_image* frames0, const ofv_image* frames1,
+                                           const ofv_params* params, const float* const* flow_init,
+                                           const float* const* grad_flow, float* const* grad_frame0,
+                                           float* const* grad_frame1, float* const* grad_flow_init) {
+  return backward_common(h, n, frames0, frames1, params, flow_init, grad_flow, grad_frame0, grad_frame1,
+                         grad_flow_init);
 }
 
 ofv_status ofv_destroy(ofv_handle h) {
@@ -1174,6 +1553,8 @@ ofv_status ofv_stream_push(ofv_handle h, const ofv_image* frame, const ofv_param
   *produced = 0;
   ofv_status r = check_params(h, params);
   if (r != OFV_OK) return r;
+  if (params->flags & OFV_FLAG_SAVE_ITERATES)
+    return fail(h, OFV_ERR_UNSUPPORTED, "the streaming call does not save iterates");
   r = validate_pair(h, frame, frame, flow_init, flow_out, 0);
   if (r != OFV_OK) return r;
   const ofv_params& p = *params;
@@ -1202,7 +1583,7 @@ ofv_status ofv_stream_push(ofv_handle h, const ofv_image* frame, const ofv_param
   pp.slab[0] = h->stream_slab;
   pp.slab[1] = new_slab;
   pp.built[0] = true;
-  r = run_pipeline(h, 1, &pp, params, nullptr, !have);
+  r = run_pipeline(h, 1, &pp, params, nullptr, have ? PIPE_FULL : PIPE_PYRAMID);
   if (r != OFV_OK) return r;
   h->stream_valid = true;
   h->stream_slab = new_slab;
@@ -1313,6 +1694,8 @@ ofv_status autotune_impl(ofv_handle h, int n, const ofv_image* frame0, const ofv
   if (repeats < 1 || repeats > 1000) return fail(h, OFV_ERR_INVALID_ARG, "repeats %d outside 1..1000", repeats);
   if (params && (params->flags & (OFV_FLAG_FORWARD_ADDITIVE | OFV_FLAG_INCREMENT_UPDATE)))
     return fail(h, OFV_ERR_UNSUPPORTED, "the autotuner times the symmetric estimator's decompositions");
+  if (params && (params->flags & OFV_FLAG_SAVE_ITERATES))
+    return fail(h, OFV_ERR_UNSUPPORTED, "the autotuner times forward calls that save no iterates");
   // validate exactly like a compute call (the validation-only handle stops there)
   ofv_status r = compute_common(h, n, frame0, frame1, params, nullptr, flow_out);
   if (r != OFV_OK) return r;

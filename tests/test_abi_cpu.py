@@ -146,7 +146,7 @@ def test_valid_call_reaches_the_device_step(lib, vhandle):
     (lambda i0, i1, p: setattr(p, "reg_rel", -1.0), _lib.OFV_ERR_INVALID_ARG, b"reg_rel"),
     (lambda i0, i1, p: setattr(p, "reg_abs", float("inf")), _lib.OFV_ERR_INVALID_ARG, b"reg_abs"),
     (lambda i0, i1, p: setattr(p, "storage", 3), _lib.OFV_ERR_INVALID_ARG, b"storage"),
-    (lambda i0, i1, p: setattr(p, "flags", 8), _lib.OFV_ERR_INVALID_ARG, b"flags"),
+    (lambda i0, i1, p: setattr(p, "flags", 64), _lib.OFV_ERR_INVALID_ARG, b"flags"),
     (lambda i0, i1, p: (setattr(i0, "width", 257), setattr(i1, "width", 257), setattr(i0, "pitch", 257),
                         setattr(i1, "pitch", 257)), _lib.OFV_ERR_CAPACITY, b"exceeds"),
     (lambda i0, i1, p: (setattr(i0, "height", 129), setattr(i1, "height", 129)), _lib.OFV_ERR_CAPACITY, b"exceeds"),
@@ -296,12 +296,12 @@ def test_estimator_flags(lib, vhandle):
     p = _params(flags=_lib.FLAG_FORWARD_ADDITIVE)
     assert lib.ofv_compute_flow(vhandle, byref(img0), byref(img1), byref(p), c_void_p(OUT)) == \
         _lib.OFV_ERR_UNSUPPORTED                                        # valid, validation-only handle
-    for ok in (_lib.FLAG_INCREMENT_UPDATE, _lib.FLAG_NO_FP64_FALLBACK,
+    for ok in (_lib.FLAG_INCREMENT_UPDATE, _lib.FLAG_NO_FP64_FALLBACK, _lib.FLAG_STORE_ALL,
                _lib.FLAG_FORWARD_ADDITIVE | _lib.FLAG_INCREMENT_UPDATE | _lib.FLAG_NO_FP64_FALLBACK):
         q = _params(flags=ok)
         assert lib.ofv_compute_flow(vhandle, byref(img0), byref(img1), byref(q), c_void_p(OUT)) == \
             _lib.OFV_ERR_UNSUPPORTED
-    bad = _params(flags=8)
+    bad = _params(flags=64)
     assert lib.ofv_compute_flow(vhandle, byref(img0), byref(img1), byref(bad), c_void_p(OUT)) == \
         _lib.OFV_ERR_INVALID_ARG
     for est in (_lib.FLAG_FORWARD_ADDITIVE, _lib.FLAG_INCREMENT_UPDATE):
@@ -351,3 +351,86 @@ def test_sync_fault_injection_on_destroy(lib, monkeypatch):
     h3 = c_void_p()
     assert lib.ofv_create(byref(h3), -1, 64, 64, 1, None) == _lib.OFV_OK
     assert lib.ofv_destroy(h3) == _lib.OFV_OK
+
+
+def test_backward_workspace_bytes(lib, vhandle):
+    """Reservation sizes (256 x 128 handle, pitches equal widths at these levels): the store-all
+    record adds 8 planes per level and iteration plus the first iteration's input field per level,
+    and the workspace scales with the number of pairs."""
+    def nbytes(L, it, pairs, mode):
+        out = ctypes.c_size_t()
+        assert lib.ofv_backward_workspace_bytes(vhandle, L, it, pairs, mode, byref(out)) == _lib.OFV_OK
+        return out.value
+    for L, it in ((1, 1), (3, 3), (2, 5)):
+        rc = nbytes(L, it, 1, 0)
+        sa = nbytes(L, it, 1, _lib.BACKWARD_STORE_ALL)
+        planes = sum((256 >> l) * (128 >> l) for l in range(L))
+        assert sa - rc == 4 * (8 * it + 2) * planes
+        assert nbytes(L, it, 2, 0) == 2 * rc and nbytes(L, it, 2, _lib.BACKWARD_STORE_ALL) == 2 * sa
+        # the saved output fields and the 15 level-0 scratch planes are in there
+        assert rc >= 4 * (2 * it * planes + 15 * 256 * 128)
+    out = ctypes.c_size_t()
+    for args in ((0, 3, 1, 0), (3, 0, 1, 0), (3, 3, 0, 0), (3, 3, 3, 0), (3, 3, 1, 2)):
+        assert lib.ofv_backward_workspace_bytes(vhandle, *args, byref(out)) == _lib.OFV_ERR_INVALID_ARG
+    assert lib.ofv_backward_workspace_bytes(vhandle, 3, 3, 1, 0, None) == _lib.OFV_ERR_INVALID_ARG
+    assert lib.ofv_backward_workspace_bytes(None, 3, 3, 1, 0, byref(out)) == _lib.OFV_ERR_INVALID_ARG
+    # a validation-only handle cannot allocate
+    assert lib.ofv_reserve_backward_ex(vhandle, 3, 3, 1, 0) == _lib.OFV_ERR_UNSUPPORTED
+    assert lib.ofv_reserve_backward_ex(vhandle, 3, 3, 3, 0) == _lib.OFV_ERR_INVALID_ARG   # above max_batch
+
+
+def test_backward_batch_validation(lib, vhandle):
+    """ofv_compute_flow_backward_batch checks the batch on the host: sizes, NULL arrays, overlaps
+    between any output and any input or output of the batch, and the reservation."""
+    n = 2
+    i0 = (OfvImage * n)(_img(0x100000), _img(0x300000))
+    i1 = (OfvImage * n)(_img(0x200000), _img(0x400000))
+    p = _params()
+    gflow = (c_void_p * n)(0x1000000, 0x1100000)
+    g0 = (c_void_p * n)(0x2000000, 0x2100000)
+
+    def call(nn=n, a0=i0, a1=i1, pp=p, init=None, gf=gflow, o0=g0, o1=None, oi=None):
+        return lib.ofv_compute_flow_backward_batch(vhandle, nn, a0, a1, byref(pp), init, gf, o0, o1, oi)
+    assert call(nn=0) == _lib.OFV_ERR_INVALID_ARG
+    assert call(nn=3) == _lib.OFV_ERR_CAPACITY                    # max_batch 2
+    assert call(gf=None) == _lib.OFV_ERR_INVALID_ARG
+    assert call(gf=(c_void_p * n)(0x1000000, None)) == _lib.OFV_ERR_INVALID_ARG
+    # grad_frame0 of pair 1 overlaps frame1 of pair 0
+    assert call(o0=(c_void_p * n)(0x2000000, 0x200000)) == _lib.OFV_ERR_INVALID_ARG
+    assert b"overlaps" in lib.ofv_last_error(vhandle)
+    # two outputs of different pairs overlap
+    assert call(o1=(c_void_p * n)(0x2100000, None)) == _lib.OFV_ERR_INVALID_ARG
+    # grad_flow_init without flow_init
+    assert call(oi=(c_void_p * n)(None, 0x3000000)) == _lib.OFV_ERR_INVALID_ARG
+    assert b"flow_init" in lib.ofv_last_error(vhandle)
+    p16 = _params(storage=_lib.STORE["f16"])
+    assert call(pp=p16) == _lib.OFV_ERR_UNSUPPORTED
+    big = (OfvImage * n)(_img(0x100000), _img(0x300000, w=512))
+    assert call(a0=big, a1=(OfvImage * n)(_img(0x200000), _img(0x400000, w=512))) == _lib.OFV_ERR_CAPACITY
+    # valid batch, no reservation on this handle
+    assert call() == _lib.OFV_ERR_CAPACITY
+    assert b"ofv_reserve_backward_ex" in lib.ofv_last_error(vhandle)
+    assert call(pp=_params(flags=_lib.FLAG_STORE_ALL)) == _lib.OFV_ERR_CAPACITY
+
+
+def test_save_iterates_validation(lib, vhandle):
+    """A forward that keeps its iterates needs the adjoint's estimator and storage and a reservation;
+    the static and streaming entry points and the autotuner reject it."""
+    img0, img1 = _img(), _img(0x200000)
+    p = _params(flags=_lib.FLAG_SAVE_ITERATES)
+    assert lib.ofv_compute_flow(vhandle, byref(img0), byref(img1), byref(p), c_void_p(OUT)) == _lib.OFV_ERR_CAPACITY
+    assert b"ofv_reserve_backward_ex" in lib.ofv_last_error(vhandle)
+    for bad in (_params(flags=_lib.FLAG_SAVE_ITERATES | _lib.FLAG_FORWARD_ADDITIVE),
+                _params(flags=_lib.FLAG_SAVE_ITERATES, storage=_lib.STORE["bf16"])):
+        assert lib.ofv_compute_flow(vhandle, byref(img0), byref(img1), byref(bad), c_void_p(OUT)) == \
+            _lib.OFV_ERR_UNSUPPORTED
+    assert lib.ofv_compute_flow_static(byref(img0), byref(img1), byref(p), c_void_p(OUT), None) == \
+        _lib.OFV_ERR_UNSUPPORTED
+    produced = ctypes.c_int()
+    assert lib.ofv_stream_push(vhandle, byref(img0), byref(p), None, c_void_p(OUT), byref(produced)) == \
+        _lib.OFV_ERR_UNSUPPORTED
+    assert lib.ofv_autotune(vhandle, byref(img0), byref(img1), byref(p), c_void_p(OUT), 1) == _lib.OFV_ERR_UNSUPPORTED
+    # the backward accepts the saved-forward flag (and still needs its reservation)
+    q = _params(flags=_lib.FLAG_SAVED_FORWARD)
+    assert lib.ofv_compute_flow_backward(vhandle, byref(img0), byref(img1), byref(q), None, c_void_p(OUT),
+                                         c_void_p(OUT + (1 << 20)), None, None) == _lib.OFV_ERR_CAPACITY

@@ -39,25 +39,31 @@ def _metrics(a, b):
     return rel, cos
 
 
-def _oracle_grads(f0, f1, init, prm, g_up, bits):
-    x0 = torch.as_tensor(f0.astype(np.float64) / (1.0 if bits == 0 else 2 ** bits - 1)).requires_grad_(True)
-    x1 = torch.as_tensor(f1.astype(np.float64) / (1.0 if bits == 0 else 2 ** bits - 1)).requires_grad_(True)
-    xi = None if init is None else torch.as_tensor(init.astype(np.float64)).requires_grad_(True)
-    v = oracle.compute_flow(x0, x1, prm, bit_depth0=0, flow_init=xi)
+def _oracle_grads(f0, f1, init, prm, g_up, bits, arith=None):
+    """Autograd of the oracle; arith="f32" runs it in float32 arithmetic (a diagnostic floor)."""
+    dt = torch.float32 if arith == "f32" else torch.float64
+    x0 = torch.as_tensor(f0.astype(np.float64) / (1.0 if bits == 0 else 2 ** bits - 1)).to(dt).requires_grad_(True)
+    x1 = torch.as_tensor(f1.astype(np.float64) / (1.0 if bits == 0 else 2 ** bits - 1)).to(dt).requires_grad_(True)
+    xi = None if init is None else torch.as_tensor(init.astype(np.float64)).to(dt).requires_grad_(True)
+    v = oracle.compute_flow(x0, x1, prm, bit_depth0=0, flow_init=xi, arith=arith)
     ins = [x0, x1] + ([xi] if xi is not None else [])
-    gs = torch.autograd.grad(torch.sum(v * g_up), ins)
+    gs = torch.autograd.grad(torch.sum(v * g_up.to(v.dtype)), ins)
     scale = 1.0 if bits == 0 else 1.0 / (2 ** bits - 1)
+    gs = [g.double() for g in gs]
     return gs[0] * scale, gs[1] * scale, (gs[2] if xi is not None else None)
 
 
+@pytest.mark.parametrize("store_all", [False, True])
 @pytest.mark.parametrize("shape,levels,kr,it,nr,bits,with_init", [
     ((96, 80), 3, 3, 2, 1, 0, True),
     ((64, 64), 2, 4, 3, 2, 0, False),
     ((70, 90), 2, 2, 2, 1, 8, True),
     ((48, 48), 1, 3, 2, 0, 0, True),
+    ((150, 200), 2, 7, 2, 1, 0, True),
+    ((40, 56), 2, 2, 2, 3, 0, False),
 ])
-def test_adjoint_matches_oracle_autograd(ofv, shape, levels, kr, it, nr, bits, with_init):
-    say("adjoint", shape, levels, kr, it, nr, bits, with_init)
+def test_adjoint_matches_oracle_autograd(ofv, shape, levels, kr, it, nr, bits, with_init, store_all):
+    say("adjoint", shape, levels, kr, it, nr, bits, with_init, "store-all" if store_all else "recompute")
     h, w = shape
     flow = synth.Rankine(w / 2 - 0.3, h / 2 + 0.2, 0.25 * min(h, w), 1.5)
     pair = synth.make_pair(h, w, flow, fwhm=2.5, ppp=0.1, seed=h + w + levels, bit_depth=bits,
@@ -73,16 +79,27 @@ def test_adjoint_matches_oracle_autograd(ofv, shape, levels, kr, it, nr, bits, w
     f0 = torch.from_numpy(pair.frame0).cuda()
     f1 = torch.from_numpy(pair.frame1).cuda()
     gi_in = None if init is None else torch.from_numpy(init).cuda()
-    g0, g1, gi = ofv.compute_flow_backward(f0, f1, prm, g_up.float().cuda().contiguous(), flow_init=gi_in,
-                                           bit_depth=bits or None)
+    g0, g1, gi = ofv.compute_flow_backward(f0, f1, dict(prm, store_all=store_all), g_up.float().cuda().contiguous(),
+                                           flow_init=gi_in, bit_depth=bits or None)
     torch.cuda.synchronize()
-    for name, got, ref in (("frame0", g0, r0), ("frame1", g1, r1), ("flow_init", gi, ri)):
+    floor = None
+    for idx, (name, got, ref) in enumerate((("frame0", g0, r0), ("frame1", g1, r1), ("flow_init", gi, ri))):
         if ref is None:
             assert got is None
             continue
         rel, cos = _metrics(got, ref)
         say(f"  {name}: rel-L2 {rel:.2e} cosine {cos:.7f}")
-        assert rel <= 1e-3 and cos >= 0.9999
+        assert cos >= 0.9999
+        if rel > 1e-3:
+            # Where the float64 gradient is a small difference of large terms (dL/dflow_init of
+            # well-converged iterations: the output hardly depends on the input field), float32
+            # arithmetic alone misses by more than 1e-3.  The gate is then the oracle's own error
+            # when it runs the same steps in float32 arithmetic.
+            if floor is None:
+                floor = _oracle_grads(pair.frame0, pair.frame1, init, prm, g_up, bits, arith="f32")
+            frel, _ = _metrics(floor[idx], ref)
+            say(f"    float32-arithmetic oracle: rel-L2 {frel:.2e}")
+            assert rel <= 1.5 * frel
 
 
 def test_autograd_function(ofv):
@@ -150,3 +167,123 @@ def test_adjoint_matches_oracle_autograd_512(ofv):
         rel, cos = _metrics(got, ref)
         say(f"  {name}: rel-L2 {rel:.2e} cosine {cos:.7f}")
         assert rel <= 1e-3 and cos >= 0.9999
+
+
+def _pair_case(i, shape):
+    h, w = shape
+    flow = synth.Rankine(w / 2 + 0.4 * i, h / 2 - 0.3, 0.25 * min(h, w), 1.5 + 0.2 * i)
+    return synth.make_pair(h, w, flow, fwhm=2.5, ppp=0.1, seed=70 + i, bit_depth=0, noise=2.0 / 255.0)
+
+
+@pytest.mark.parametrize("store_all", [False, True])
+def test_batched_backward_matches_single_pairs(ofv, store_all):
+    """One batched call over pairs of uneven sizes (with and without an initial field, one without
+    frame gradients) against the same pairs one at a time: the same kernels, so equal up to the
+    order of the float atomics."""
+    say("batched backward", "store-all" if store_all else "recompute")
+    shapes = [(96, 80), (64, 130), (33, 47)]
+    prm = {"num_levels": 3, "kernel_radius": 3, "iterations": 2, "norm_radius": 1, "store_all": store_all}
+    pairs = [_pair_case(i, sh) for i, sh in enumerate(shapes)]
+    f0 = [torch.from_numpy(p.frame0).cuda() for p in pairs]
+    f1 = [torch.from_numpy(p.frame1).cuda() for p in pairs]
+    gen = torch.Generator().manual_seed(11)
+    gf = [torch.randn((2,) + sh, generator=gen).cuda() for sh in shapes]
+    init = [torch.from_numpy(pairs[0].gt.astype(np.float32)).cuda(), None,
+            torch.from_numpy(pairs[2].gt.astype(np.float32)).cuda()]
+    hb = ofv.Handle(130, 96, 3)
+    b0, b1, bi = ofv.compute_flow_backward_batch(f0, f1, prm, gf, flow_init=init, handle=hb)
+    torch.cuda.synchronize()
+    assert bi[1] is None and bi[0] is not None and bi[2] is not None
+    for i in range(3):
+        hs = ofv.Handle(shapes[i][1], shapes[i][0], 1)
+        s0, s1, si = ofv.compute_flow_backward(f0[i], f1[i], prm, gf[i], flow_init=init[i], handle=hs)
+        torch.cuda.synchronize()
+        for name, a, b in (("frame0", b0[i], s0), ("frame1", b1[i], s1), ("flow_init", bi[i], si)):
+            if b is None:
+                assert a is None
+                continue
+            rel, cos = _metrics(a, b)
+            say(f"  pair {i} {name}: rel-L2 {rel:.2e}")
+            assert rel <= 1e-5 and cos >= 0.99999
+        hs.close()
+    # no frame gradients requested
+    _, _, ni = ofv.compute_flow_backward_batch(f0, f1, prm, gf, flow_init=init, need_frames=False, handle=hb)
+    torch.cuda.synchronize()
+    rel, _ = _metrics(ni[0], bi[0])
+    assert rel <= 1e-5
+    hb.close()
+
+
+def test_store_all_matches_recompute_512_batch(ofv):
+    """The differentiation workload's shape, 16 x 512^2 float pairs (3 levels, KR 4, IT 3, NR 1), in
+    one batched call in each mode: the two modes agree (their forwards run different kernels over
+    the same arithmetic), and pair 0 matches the single-pair call."""
+    say("store-all vs recompute, 16 x 512^2")
+    n = 16
+    cases = [synth.config_adjoint_512(i) for i in range(n)]
+    prm = dict(cases[0][1])
+    f0 = [torch.from_numpy(p.frame0).cuda() for p, _ in cases]
+    f1 = [torch.from_numpy(p.frame1).cuda() for p, _ in cases]
+    gt = [torch.from_numpy(p.gt.astype(np.float32)).cuda() for p, _ in cases]
+    h = ofv.Handle(512, 512, n)
+    outs = ofv.compute_flow_batch(f0, f1, prm, handle=h)
+    gf = [(2 * (outs[i] - gt[i])).contiguous() for i in range(n)]
+    r0, r1, _ = ofv.compute_flow_backward_batch(f0, f1, prm, gf, handle=h)
+    s0, s1, _ = ofv.compute_flow_backward_batch(f0, f1, dict(prm, store_all=True), gf, handle=h)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for i in range(n):
+        for a, b in ((s0[i], r0[i]), (s1[i], r1[i])):
+            rel, cos = _metrics(a, b)
+            worst = max(worst, rel)
+            assert rel <= 1e-3 and cos >= 0.9999
+    say(f"  worst rel-L2 store-all vs recompute {worst:.2e}")
+    q0, q1, _ = ofv.compute_flow_backward(f0[0], f1[0], prm, gf[0], handle=h)
+    torch.cuda.synchronize()
+    for a, b in ((q0, r0[0]), (q1, r1[0])):
+        rel, cos = _metrics(a, b)
+        assert rel <= 1e-5
+    h.close()
+
+
+def test_saved_forward_reuse(ofv):
+    """A forward that keeps its iterates returns the plain forward's field bit for bit, and a backward
+    that reuses them equals a self-contained one; a forward on other inputs replaces them, after which
+    the backward runs its own forward and still agrees.  Likewise in store-all mode."""
+    say("saved forward")
+    shapes = [(96, 80), (80, 96)]
+    prm = {"num_levels": 3, "kernel_radius": 3, "iterations": 2, "norm_radius": 1}
+    pairs = [_pair_case(i, sh) for i, sh in enumerate(shapes)]
+    f0 = [torch.from_numpy(p.frame0).cuda() for p in pairs]
+    f1 = [torch.from_numpy(p.frame1).cuda() for p in pairs]
+    gen = torch.Generator().manual_seed(5)
+    gf = [torch.randn((2,) + sh, generator=gen).cuda() for sh in shapes]
+    h = ofv.Handle(96, 96, 2)
+    plain = ofv.compute_flow_batch(f0, f1, prm, handle=h)
+    ref = ofv.compute_flow_backward_batch(f0, f1, prm, gf, handle=h)
+    saved = ofv.compute_flow_batch(f0, f1, dict(prm, save_iterates=True), handle=h)
+    torch.cuda.synchronize()
+    for a, b in zip(plain, saved):
+        assert torch.equal(a, b)
+    got = ofv.compute_flow_backward_batch(f0, f1, dict(prm, saved_forward=True), gf, handle=h)
+    again = ofv.compute_flow_backward_batch(f0, f1, dict(prm, saved_forward=True), gf, handle=h)
+    # another forward replaces the saved iterates: the backward runs its own forward
+    ofv.compute_flow_batch([f1[0], f1[1]], [f0[0], f0[1]], prm, handle=h)
+    rerun = ofv.compute_flow_backward_batch(f0, f1, dict(prm, saved_forward=True), gf, handle=h)
+    torch.cuda.synchronize()
+    for res in (got, again, rerun):
+        for i in range(2):
+            for a, b in ((res[0][i], ref[0][i]), (res[1][i], ref[1][i])):
+                rel, cos = _metrics(a, b)
+                assert rel <= 1e-5 and cos >= 0.99999
+    # store-all: the recording forward is the estimator too, and its record serves the backward
+    sa = dict(prm, store_all=True)
+    rec = ofv.compute_flow_batch(f0, f1, dict(sa, save_iterates=True), handle=h)
+    got_sa = ofv.compute_flow_backward_batch(f0, f1, dict(sa, saved_forward=True), gf, handle=h)
+    torch.cuda.synchronize()
+    for i in range(2):
+        assert float((rec[i] - plain[i]).abs().max()) <= 1e-4
+        for a, b in ((got_sa[0][i], ref[0][i]), (got_sa[1][i], ref[1][i])):
+            rel, cos = _metrics(a, b)
+            assert rel <= 1e-3 and cos >= 0.9999
+    h.close()
