@@ -102,8 +102,8 @@ def parse():
     ap.add_argument("--sweep-realisations", type=int, default=10,
                     help="particle fields per image of the accuracy sweep (the paper uses 10)")
     ap.add_argument("--suite", default=None,
-                    choices=["batch4mp", "live21mp", "stream21mp", "sweep", "adjoint512", "paper", "oracle",
-                             "preprocess", "all"],
+                    choices=["batch4mp", "live21mp", "stream21mp", "sweep", "estimators", "adjoint512", "paper",
+                             "oracle", "preprocess", "all"],
                     help="run an additional measurement instead of the default workload (one JSON line each)")
     return ap.parse_args()
 
@@ -612,6 +612,76 @@ def suite_sweep(args, dev):
                     "noise, no out-of-plane loss) standing in for the paper's generator images"}
 
 
+def suite_estimators(args, dev):
+    """The three estimators side by side on the paper's Rankine image grid (72 images of 1024^2, 8-bit,
+    no noise; `--sweep-realisations` particle fields): the symmetric estimator with its consistent
+    update, the symmetric estimator with the increment-form update, and forward-additive Lucas-Kanade,
+    at KR 3, 5 and 7 with PSL 3, IT 3, NR 2; scored by Psi and <Err> as in the sweep."""
+    import itertools
+    import numpy as np
+    import torch
+    import paper_2509_25924_amd as ofv
+    import synth
+    from synth import metrics as M
+    from synth.gpu_render import make_pair_device
+    S = 1024
+    c = (S - 1) / 2.0
+    nreal = args.sweep_realisations
+    ig = M.rankine_grid()
+    imgs = list(itertools.product(ig["dmax"], ig["part_per_iw"], ig["radius"]))
+    fwhm = 0.75 * synth.FWHM_PER_SIGMA
+    vort = [synth.Rankine(c, c, float(R), float(D)) for D, _, R in imgs]
+    yy, xx = np.mgrid[0:S, 0:S].astype(np.float64)
+    gts = torch.stack([torch.as_tensor(np.stack(v(xx, yy)), dtype=torch.float32) for v in vort]).to(dev)
+    del yy, xx
+    radii = sorted(set(R for _, _, R in imgs))
+    unf = {R: M.Unfolding(c, c, M.default_r_max(R, S, S), dev) for R in radii}
+    groups = {R: [i for i, (_, _, r) in enumerate(imgs) if r == R] for R in radii}
+    theory = {R: torch.stack([unf[R].theory(vort[i], torch.float32) for i in groups[R]]) for R in radii}
+    n = len(imgs)
+    estimators = {"symmetric_consistent": {}, "symmetric_increment": {"update": "increment"},
+                  "forward_additive": {"estimator": "forward_additive"}}
+    krs = (3, 5, 7)
+    hd = ofv.Handle(S, S, n)
+    outs = [torch.empty((2, S, S), dtype=torch.float32, device=dev) for _ in range(n)]
+    psi = {e: np.zeros((n, len(krs))) for e in estimators}
+    err = {e: np.zeros((n, len(krs))) for e in estimators}
+    for rz in range(nreal):
+        f0, f1 = [], []
+        for i, (D, ppi, R) in enumerate(imgs):
+            a, b, _ = make_pair_device(S, S, vort[i], fwhm=fwhm, ppp=ppi / 256.0, seed=7000 + 1000 * rz + i,
+                                       bit_depth=8, noise=0.0, device=dev, max_disp=float(D))
+            f0.append(a)
+            f1.append(b)
+        for name, extra in estimators.items():
+            for ki, kr in enumerate(krs):
+                prm = dict({"num_levels": 4, "kernel_radius": kr, "iterations": 3, "norm_radius": 2}, **extra)
+                ofv.compute_flow_batch(f0, f1, prm, bit_depth=8, outs=outs, handle=hd)
+                for R in radii:
+                    idx = groups[R]
+                    fl = torch.stack([outs[i] for i in idx])
+                    psi[name][idx, ki] += unf[R].psi(fl, theory[R]).cpu().numpy()
+                    err[name][idx, ki] += M.mean_endpoint_error(fl, gts[idx], 16).cpu().numpy()
+        del f0, f1
+    names = list(estimators)
+    stack_err = np.stack([err[e] / nreal for e in names])        # estimator x image x KR
+    best = np.argmin(stack_err, axis=0)
+    res = {}
+    for k, e in enumerate(names):
+        res[e] = {"mean_psi": round(float(np.mean(psi[e] / nreal)), 4),
+                  "mean_err_px": round(float(np.mean(err[e] / nreal)), 4),
+                  "median_err_px": round(float(np.median(err[e] / nreal)), 4),
+                  "mean_err_px_by_KR": {str(kr): round(float(np.mean(err[e][:, ki] / nreal)), 4)
+                                        for ki, kr in enumerate(krs)},
+                  "lowest_err_share": round(float(np.mean(best == k)), 3)}
+    return {"metric": "estimator comparison on the Rankine image grid (mean <Err> px, lower is better)",
+            "value": res["symmetric_consistent"]["mean_err_px"], "unit": "px", "higher_is_better": False,
+            "estimators": res, "settings": {"KR": list(krs), "PSL": 3, "IT": 3, "NR": 2},
+            "images": n, "realisations": nreal,
+            "data": "synthetic Rankine vortices at 1024^2 (Gaussian particles of 3 px e^-2 diameter, 8-bit, no "
+                    "noise, no out-of-plane loss) standing in for the paper's generator images"}
+
+
 def suite_oracle(args, dev):
     """The FP64 CPU oracle's own throughput on the host of the GPU: the 256^2 Rankine and 1024^2 shear
     configurations with every thread and with one, one 2048^2 turbulence pair and a 2048^2 crop of a
@@ -779,10 +849,10 @@ def run_suite(args):
         _build.build()
     ofv.load()
     dev = torch.device("cuda:0")
-    names = (["batch4mp", "live21mp", "stream21mp", "sweep", "adjoint512", "paper"] if args.suite == "all"
+    names = (["batch4mp", "live21mp", "stream21mp", "sweep", "estimators", "adjoint512", "paper"] if args.suite == "all"
              else [args.suite])
     fns = {"batch4mp": suite_batch4mp, "live21mp": suite_live21mp, "stream21mp": suite_stream21mp,
-           "sweep": suite_sweep, "oracle": suite_oracle,
+           "sweep": suite_sweep, "estimators": suite_estimators, "oracle": suite_oracle,
            "adjoint512": suite_adjoint512, "paper": suite_paper, "preprocess": suite_preprocess}
     for nm in names:
         print(f"# suite {nm} ...", file=sys.stderr, flush=True)
