@@ -287,3 +287,66 @@ def test_saved_forward_reuse(ofv):
             rel, cos = _metrics(a, b)
             assert rel <= 1e-3 and cos >= 0.9999
     h.close()
+
+
+def test_adjoint_against_central_differences_32(ofv):
+    """The GPU adjoint against central differences of the FP64 oracle on 32 x 32 crops, per input
+    (both frames and the initial field), along random directions: <dL/dx, d> from the GPU against
+    (L(x + h d) - L(x - h d)) / 2h with h = 1e-5, L = sum(g . V).  (Central differences of the
+    float32 forward itself cannot serve: at h = 1e-3 the float32 rounding of V and the bilinear
+    floors crossed by the step leave them 3e-3 .. 0.5 off the exact derivative even for the oracle
+    run in float32 arithmetic; at h = 1e-5 the FP64 oracle's own differences agree with its autograd
+    to 4e-5.)"""
+    say("adjoint vs central differences, 32x32")
+    h, w = 32, 32
+    flow = synth.Rankine(w / 2 - 0.3, h / 2 + 0.2, 8.0, 1.5)
+    pair = synth.make_pair(h, w, flow, fwhm=2.5, ppp=0.1, seed=7, bit_depth=0, noise=2.0 / 255.0)
+    prm = {"num_levels": 2, "kernel_radius": 3, "iterations": 2, "norm_radius": 1, "norm_eps": 1e-4,
+           "reg_rel": 1e-3, "reg_abs": 1e-9}
+    init = (pair.gt + np.random.default_rng(3).normal(0, 0.2, pair.gt.shape)).astype(np.float32)
+    g = np.random.default_rng(4).normal(0, 1, (2, h, w))
+    gpu = ofv.compute_flow_backward(torch.from_numpy(pair.frame0).cuda(), torch.from_numpy(pair.frame1).cuda(), prm,
+                                    torch.from_numpy(g).float().cuda().contiguous(),
+                                    flow_init=torch.from_numpy(init).cuda())
+    torch.cuda.synchronize()
+    gpu = [t.double().cpu().numpy() for t in gpu]
+    base = [pair.frame0.astype(np.float64), pair.frame1.astype(np.float64), init.astype(np.float64)]
+    gt = torch.from_numpy(g)
+    rng = np.random.default_rng(5)
+    step = 1e-5
+    for which, name in enumerate(("frame0", "frame1", "flow_init")):
+        for _ in range(4):
+            d = rng.normal(0, 1, base[which].shape)
+
+            def loss(sign):
+                b = [x.copy() for x in base]
+                b[which] = b[which] + sign * step * d
+                v = oracle.compute_flow(torch.from_numpy(b[0]), torch.from_numpy(b[1]), prm, bit_depth0=0,
+                                        flow_init=torch.from_numpy(b[2]))
+                return float(torch.sum(v * gt))
+            fd = (loss(1) - loss(-1)) / (2 * step)
+            an = float(np.sum(gpu[which] * d))
+            rel = abs(an - fd) / abs(fd)
+            say(f"  {name}: directional derivative GPU {an:.6e} central differences {fd:.6e} rel {rel:.1e}")
+            assert rel <= 2e-3
+
+
+def test_adjoint_repeatable(ofv):
+    """Two identical backward calls: equal up to the order in which the float atomics of the image
+    gradients land (rel-L2 <= 1e-6), the flow-init gradient (no atomics) bit for bit."""
+    say("adjoint repeatability")
+    pair, prm = synth.config_adjoint_512(1, size=256)
+    f0 = torch.from_numpy(pair.frame0).cuda()
+    f1 = torch.from_numpy(pair.frame1).cuda()
+    init = torch.from_numpy(pair.gt.astype(np.float32)).cuda()
+    g = torch.randn((2, 256, 256), generator=torch.Generator().manual_seed(9)).cuda()
+    h = ofv.Handle(256, 256, 1)
+    a = ofv.compute_flow_backward(f0, f1, prm, g, flow_init=init, handle=h)
+    b = ofv.compute_flow_backward(f0, f1, prm, g, flow_init=init, handle=h)
+    torch.cuda.synchronize()
+    for x, y in zip(a[:2], b[:2]):
+        rel, _ = _metrics(x, y)
+        say(f"  frame gradient: rel-L2 between runs {rel:.1e}")
+        assert rel <= 1e-6
+    assert torch.equal(a[2], b[2])
+    h.close()
