@@ -5,14 +5,17 @@
 
 namespace ofv {
 
-int adj_scatter_blocks(int w, int h) { return ((w + 63) / 64) * ((h + 15) / 16); }
+int adj_scatter_blocks(int w, int h, int ty) { return ((w + 63) / 64) * ((h + ty - 1) / ty); }
 
-hipError_t launch_adj_scatter(const AdjArgs& a, int kr, bool stored, int nblocks, hipStream_t s) {
+hipError_t launch_adj_scatter(const AdjArgs& a, int kr, bool stored, int ty, int nblocks, hipStream_t s) {
   if (nblocks <= 0) return hipSuccess;
 #define OFV_ADJX_CASE(R)                                                                           \
   case R:                                                                                          \
-    return stored ? launch_adj_scatter_cfg<R, true>(a, nblocks, s)                                 \
-                  : launch_adj_scatter_cfg<R, false>(a, nblocks, s);
+    if (ty == 8)                                                                                   \
+      return stored ? launch_adj_scatter_cfg<R, true, 8>(a, nblocks, s)                            \
+                    : launch_adj_scatter_cfg<R, false, 8>(a, nblocks, s);                          \
+    return stored ? launch_adj_scatter_cfg<R, true, 16>(a, nblocks, s)                             \
+                  : launch_adj_scatter_cfg<R, false, 16>(a, nblocks, s);
   switch (kr) {
     OFV_ADJX_CASE(1)
     OFV_ADJX_CASE(2)

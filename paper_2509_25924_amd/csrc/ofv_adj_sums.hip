@@ -4,14 +4,17 @@
 
 namespace ofv {
 
-int adj_sums_blocks(int w, int h) { return ((w + 63) / 64) * ((h + 15) / 16); }
+int adj_sums_blocks(int w, int h, int ty) { return ((w + 63) / 64) * ((h + ty - 1) / ty); }
 
-hipError_t launch_adj_sums(const AdjArgs& a, int kr, int epilogue, int nblocks, hipStream_t s) {
+hipError_t launch_adj_sums(const AdjArgs& a, int kr, int epilogue, int ty, int nblocks, hipStream_t s) {
   if (nblocks <= 0) return hipSuccess;
 #define OFV_ADJS_CASE(R)                                                                              \
   case R:                                                                                             \
-    return epilogue == ADJ_RECORD ? launch_adj_sums_cfg<R, ADJ_RECORD>(a, nblocks, s)                \
-                                  : launch_adj_sums_cfg<R, ADJ_SOLVE>(a, nblocks, s);
+    if (ty == 8)                                                                                      \
+      return epilogue == ADJ_RECORD ? launch_adj_sums_cfg<R, ADJ_RECORD, 8>(a, nblocks, s)            \
+                                    : launch_adj_sums_cfg<R, ADJ_SOLVE, 8>(a, nblocks, s);            \
+    return epilogue == ADJ_RECORD ? launch_adj_sums_cfg<R, ADJ_RECORD, 16>(a, nblocks, s)             \
+                                  : launch_adj_sums_cfg<R, ADJ_SOLVE, 16>(a, nblocks, s);
   switch (kr) {
     OFV_ADJS_CASE(1)
     OFV_ADJS_CASE(2)

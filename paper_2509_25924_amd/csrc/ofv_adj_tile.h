@@ -347,11 +347,12 @@ __global__ __launch_bounds__(NT) void adj_sums_kernel(const AdjArgs a) {
   }
 }
 
-template <int KR, int EPI>
+// TY 16 for large launches; TY 8 spreads small ones (coarse levels) over twice the workgroups
+template <int KR, int EPI, int TY>
 hipError_t launch_adj_sums_cfg(const AdjArgs& a, int nblocks, hipStream_t s) {
-  constexpr int TX = 64, TY = 16;
+  constexpr int TX = 64;
   constexpr size_t lds = sizeof(float) * AdjSumsGeom<KR, TX, TY>::FLOATS;
-  auto kern = adj_sums_kernel<KR, TX, TY, 8, 4, 256, EPI>;
+  auto kern = adj_sums_kernel<KR, TX, TY, 8, TY == 16 ? 4 : 2, 256, EPI>;
   static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                                      hipFuncAttributeMaxDynamicSharedMemorySize,
                                                      static_cast<int>(lds));
@@ -811,9 +812,9 @@ __global__ __launch_bounds__(NT) void adj_scatter_kernel(const AdjArgs a) {
   }
 }
 
-template <int KR, bool STORED>
+template <int KR, bool STORED, int TY>
 hipError_t launch_adj_scatter_cfg(const AdjArgs& a, int nblocks, hipStream_t s) {
-  constexpr int TX = 64, TY = 16, SL = 8, SLV = 6;
+  constexpr int TX = 64, SL = 8, SLV = TY == 16 ? 6 : 5;
   constexpr size_t lds = sizeof(float) * AdjScatGeom<KR, TX, TY, SL, SLV, STORED>::FLOATS;
   auto kern = adj_scatter_kernel<KR, TX, TY, SL, SLV, 256, STORED>;
   static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),

@@ -796,6 +796,9 @@ struct BwPlan {
     for (int l = L - 1; l >= 0; --l) {
       r = prepare_vin0(l);
       if (r != OFV_OK) return r;
+      int64_t px = 0;
+      for (int j = 0; j < n; ++j) px += static_cast<int64_t>(pp[j].lw[l]) * pp[j].lh[l];
+      const int ty = adj_tile_h(px);
       for (int k = 0; k < IT; ++k) {
         AdjArgs aa{};
         aa.reg_rel = params->reg_rel;
@@ -833,8 +836,8 @@ struct BwPlan {
           J.w = pp[j].lw[l];
           J.h = pp[j].lh[l];
           J.tile_start = blocks;
-          blocks += adj_sums_blocks(J.w, J.h);
-        }, [&](const AdjArgs& a) { return launch_adj_sums(a, kr, ADJ_RECORD, blocks, s); }, "recording iteration");
+          blocks += adj_sums_blocks(J.w, J.h, ty);
+        }, [&](const AdjArgs& a) { return launch_adj_sums(a, kr, ADJ_RECORD, ty, blocks, s); }, "recording iteration");
         if (r != OFV_OK) return r;
       }
     }
@@ -1319,6 +1322,9 @@ ofv_status backward_common(ofv_ctx* h, int n, const ofv_image* f0, const ofv_ima
   auto gbuf = [&](int j, int i) { return bv.scratch(j, 7 + 2 * i); };
   int gcur = -1;
   for (int l = 0; l < L; ++l) {
+    int64_t lpx = 0;
+    for (int j = 0; j < n; ++j) lpx += static_cast<int64_t>(pp[j].lw[l]) * pp[j].lh[l];
+    const int ty = adj_tile_h(lpx);
     for (int k = IT - 1; k >= 0; --k) {
       if (k == 0 && !store_all) {
         r = bp.prepare_vin0(l);
@@ -1374,17 +1380,17 @@ ofv_status backward_common(ofv_ctx* h, int n, const ofv_image* f0, const ofv_ima
         if ((j % kMaxJobs) == 0) blocks = 0;
         fill(j, J);
         J.tile_start = blocks;
-        blocks += store_all ? adj_point_blocks(J.w, J.h) : adj_sums_blocks(J.w, J.h);
+        blocks += store_all ? adj_point_blocks(J.w, J.h) : adj_sums_blocks(J.w, J.h, ty);
       }, [&](const AdjArgs& a) {
-        return store_all ? launch_adj_solve_stored(a, blocks, s) : launch_adj_sums(a, kr, ADJ_SOLVE, blocks, s);
+        return store_all ? launch_adj_solve_stored(a, blocks, s) : launch_adj_sums(a, kr, ADJ_SOLVE, ty, blocks, s);
       }, "solve adjoint");
       if (r != OFV_OK) return r;
       r = run_jobs(h, n, aa, [&](int j, AdjJob& J) {
         if ((j % kMaxJobs) == 0) blocks = 0;
         fill(j, J);
         J.tile_start = blocks;
-        blocks += adj_scatter_blocks(J.w, J.h);
-      }, [&](const AdjArgs& a) { return launch_adj_scatter(a, kr, store_all, blocks, s); }, "warp adjoint");
+        blocks += adj_scatter_blocks(J.w, J.h, ty);
+      }, [&](const AdjArgs& a) { return launch_adj_scatter(a, kr, store_all, ty, blocks, s); }, "warp adjoint");
       if (r != OFV_OK) return r;
       gcur = gnext;
     }

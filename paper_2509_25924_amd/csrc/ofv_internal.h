@@ -284,16 +284,19 @@ struct NormAdjArgs {
 };
 
 hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s);
-// Window sums of one iteration over every job's level (tiles of 64 x 16 outputs).
-hipError_t launch_adj_sums(const AdjArgs& a, int kr, int epilogue, int nblocks, hipStream_t s);
-int adj_sums_blocks(int w, int h);
+// Tile height of the adjoint's iteration kernels for a launch over `pixels`
+// pixels: 64 x 16 tiles, or 64 x 8 for launches too small to fill the chip.
+inline int adj_tile_h(int64_t pixels) { return pixels < (int64_t{2} << 20) ? 8 : 16; }
+// Window sums of one iteration over every job's level (tiles of 64 x ty outputs).
+hipError_t launch_adj_sums(const AdjArgs& a, int kr, int epilogue, int ty, int nblocks, hipStream_t s);
+int adj_sums_blocks(int w, int h, int ty);
 // Adjoint of the solve from stored sums (point-wise, blocks of 64 x 4 pixels).
 hipError_t launch_adj_solve_stored(const AdjArgs& a, int nblocks, hipStream_t s);
 int adj_point_blocks(int w, int h);
 // Window sums of gA, adjoints of the products, b, the central difference and
 // the two warps; image gradients scattered, dL/d(input field) written.
-hipError_t launch_adj_scatter(const AdjArgs& a, int kr, bool stored, int nblocks, hipStream_t s);
-int adj_scatter_blocks(int w, int h);
+hipError_t launch_adj_scatter(const AdjArgs& a, int kr, bool stored, int ty, int nblocks, hipStream_t s);
+int adj_scatter_blocks(int w, int h, int ty);
 // V = 2 bilinear(V_coarse, x / 2, y / 2) of every job (in0/in1 coarse u/v, out0/out1 fine).
 hipError_t launch_upsample_batch(const AuxArgs& a, int maxw, int maxh, hipStream_t s);
 // Transpose of the up-sampling, as a gather: out = coarse gradient (written).
