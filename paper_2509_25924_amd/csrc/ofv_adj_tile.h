@@ -36,6 +36,7 @@
 // of its weights.
 #pragma once
 
+#include "ofv_adj.h"
 #include "ofv_gn_tile.h"
 
 namespace ofv {

@@ -21,6 +21,7 @@
 #include "ofv.h"
 #include "ofv_stages.h"
 #include "ofv_internal.h"
+#include "ofv_adj.h"
 
 using namespace ofv;
 
