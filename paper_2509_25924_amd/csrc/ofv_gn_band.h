@@ -19,17 +19,18 @@
 //      planes (0 outside the level).
 //  B.  horizontal window sums by running sums: one item per (product,
 //      row, segment of SL outputs), 5 BY NSEG items over the 256 lanes.
-//  C.  vertical window sums: each output lane keeps the running sum of
-//      the last 2 KR + 1 horizontal sums of its column and those sums in a
-//      register ring indexed by the (wavefront-uniform) row number, so the
-//      vertical pass costs two additions per product and row whatever KR;
-//      damped 2x2 solve and store of every completed output row.
+//  C.  vertical window sums: each output lane keeps the sum of the last
+//      2 KR horizontal sums of its column and those sums in a register ring
+//      indexed by the (wavefront-uniform) row number, so the vertical pass
+//      costs two additions per product and row whatever KR; damped 2x2
+//      solve and store of every completed output row.
 // The horizontal segment ends are the only repeated work; the vertical halo
 // (2 KR + 2 rows) is paid once per tile, and the host sizes the tiles so that
 // one round of resident workgroups covers the level.
 #pragma once
 
 #include <type_traits>
+#include <utility>
 
 #include "ofv_gn_tile.h"
 
@@ -132,23 +133,47 @@ __device__ __forceinline__ void band_upsample(PlaneView vu, PlaneView vv, uint32
   }
 }
 
-// One entry of the vertical ring of a product: acc - (the sum leaving the
-// window) + h, the ring slot overwritten by h.  `slot` is uniform across
-// the wavefront (so the array stays in registers, indexed relative to a
-// scalar base).
-template <int NWIN>
-__device__ __forceinline__ float band_ring(float (&ring)[NWIN], int slot, float acc, float h) {
-  const float old = ring[slot];
+// One row of the vertical window sum of a product.  `part` holds the sum of
+// the window's first 2 KR rows and the ring those 2 KR horizontal sums, the
+// oldest in `slot`: the window sum is part + h, after which the oldest
+// leaves part and h takes its slot.  `slot` is uniform across the
+// wavefront, so the array stays in registers, indexed relative to a scalar
+// base.
+template <int N>
+__device__ __forceinline__ float band_ring(float (&ring)[N], int slot, float& part, float h) {
+  const float full = part + h;
+  part = full - ring[slot];
   ring[slot] = h;
-  return (acc - old) + h;
+  return full;
 }
 
-// Registers per lane: 2 KR + 1 ring entries for each of the five sums, the
-// next block's taps in flight, the block's rows: up to 256 (2 waves per SIMD).
+// f(std::integral_constant<int, I>()) for the one I of the sequence equal to
+// i (wavefront-uniform: a chain of scalar compares, one inlined copy of f
+// per I).
+template <typename F, int... I>
+__device__ __forceinline__ void band_dispatch(int i, F&& f, std::integer_sequence<int, I...>) {
+  (void)((i == I ? (f(std::integral_constant<int, I>()), true) : false) || ...);
+}
+
+// The vertical rings.  A register array indexed at run time occupies a
+// register tuple, and tuples come in 1-12 and 16 registers (an 18- to
+// 32-float array takes 32).  A ring of 2 KR = 16 + 4 m floats (KR 10, 12) is
+// therefore split into a 16-float array indexed at run time and a 4 m-float
+// tail; a block's BY = 4 rows then fall in one of the two, and the tail is
+// indexed by compile-time constants (one copy of the vertical pass per
+// 4-slot group of the tail).  The other windows keep one array (KR 9 and 11:
+// padded to 32 registers).
+// Registers per lane: the rings, the next block's taps in flight (issued
+// after the block's products, `pipelined`) where they fit beside them, the
+// block's rows: up to 256 (2 waves per SIMD).
 template <int KR>
 struct BandOcc {
   static constexpr int value = 2;
-  static constexpr bool pipelined = KR <= 7;
+  static constexpr int NR = 2 * KR;  // ring length
+  static constexpr bool split = NR > 16 && NR % 4 == 0;
+  static constexpr int A = split ? 16 : NR;      // run-time indexed part
+  static constexpr int B = split ? NR - 16 : 1;  // compile-time indexed tail (unused unless split)
+  static constexpr bool pipelined = KR <= 10 && (KR <= 8 || split);
 };
 
 // GEN: the estimator variant is read from a.est at run time (forward-additive
@@ -159,6 +184,7 @@ __global__ __launch_bounds__(kBandThreads) __attribute__((amdgpu_waves_per_eu(Ba
 void gn_band_kernel(const GnArgs a) {
   using G = BandGeom<KR, BY>;
   constexpr int NWIN = G::NWIN, TX = G::TX, PP = G::PP, NROW = G::NROW, NSEG = G::NSEG, SL = G::SL;
+  constexpr int NR = 2 * KR;  // vertical ring length
   extern __shared__ float lds[];
   const bool fa = GEN && (a.est & EST_FORWARD_ADDITIVE) != 0;
   const bool inc = GEN && (a.est & EST_INCREMENT) != 0;
@@ -257,11 +283,16 @@ void gn_band_kernel(const GnArgs a) {
     }
   }
 
-  float rg0[NWIN], rg1[NWIN], rg2[NWIN], rg3[NWIN], rg4[NWIN];
+  using O = BandOcc<KR>;
+  static_assert(!O::split || BY == 4, "split rings assume 4-row blocks");
+  float rg0[O::A], rg1[O::A], rg2[O::A], rg3[O::A], rg4[O::A];  // rings (split: slots 0..15)
+  float rt0[O::B], rt1[O::B], rt2[O::B], rt3[O::B], rt4[O::B];  // split: slots 16..NR-1
 #pragma unroll
-  for (int n = 0; n < NWIN; ++n) rg0[n] = rg1[n] = rg2[n] = rg3[n] = rg4[n] = 0.0f;
+  for (int n = 0; n < O::A; ++n) rg0[n] = rg1[n] = rg2[n] = rg3[n] = rg4[n] = 0.0f;
+#pragma unroll
+  for (int n = 0; n < O::B; ++n) rt0[n] = rt1[n] = rt2[n] = rt3[n] = rt4[n] = 0.0f;
   float acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f, acc3 = 0.0f, acc4 = 0.0f;
-  int slot = 0;
+  int slot = 0;  // ring slot of the block's first row
 
   const uint32_t obytes = static_cast<uint32_t>(J.out_pitch) * static_cast<uint32_t>(H) * 4u;
   const PlaneView wu = plane_view(J.out_u, obytes);
@@ -388,40 +419,69 @@ void gn_band_kernel(const GnArgs a) {
 #pragma unroll
         for (int j = 0; j < BY; ++j) um[j] = vm[j] = 0.0f;
       }
+      // solve and store of output row m = k BY + j - 2 KR from its window sums
+      auto finish_row = [&](int j, float f0, float f1, float f2, float f3, float f4) {
+        const int m = k * BY + j - 2 * KR;  // output row within the tile
+        if (m >= 0 && m < rows) {
+          float un, vn;
+          solve2x2(f0, f1, f2, f3, f4, um[j], vm[j], a.reg_rel, a.reg_abs, un, vn, inc, no_fp64);
+          const uint32_t oo = (__umul24(static_cast<uint32_t>(y0 + m), static_cast<uint32_t>(J.out_pitch)) +
+                               static_cast<uint32_t>(gx)) * 4u;
+          __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(un), wu, static_cast<int>(oo), 0, 0);
+          __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(vn), wv, static_cast<int>(oo), 0, 0);
+        }
+      };
+      const int sl0 = __builtin_amdgcn_readfirstlane(slot);
+      const float* hcol = lds + lds_reg(G::H_OFF + oc);
+      if (!O::split || sl0 < 16) {
 #pragma unroll
-      for (int j = 0; j < BY; ++j) {
-        const int sl = __builtin_amdgcn_readfirstlane(slot);
-        if (out_lane) {
-          const float* hcol = lds + lds_reg(G::H_OFF + oc);
-          if (PIPE) {
-            // the row's five horizontal sums of this column, read before the ring updates
-            float hv[5];
+        for (int j = 0; j < BY; ++j) {
+          // slot of row j: split rings hold 4-row blocks in slots 4 g .. 4 g + 3
+          const int sl = O::split ? sl0 + j : __builtin_amdgcn_readfirstlane((sl0 + j) % NR);
+          if (out_lane) {
+            float f0, f1, f2, f3, f4;  // the window sums of this row
+            if (PIPE) {
+              // the row's five horizontal sums of this column, read before the ring updates
+              float hv[5];
 #pragma unroll
-            for (int q = 0; q < 5; ++q) hv[q] = hcol[(q * BY + j) * PP];
-            acc0 = band_ring(rg0, sl, acc0, hv[0]);
-            acc1 = band_ring(rg1, sl, acc1, hv[1]);
-            acc2 = band_ring(rg2, sl, acc2, hv[2]);
-            acc3 = band_ring(rg3, sl, acc3, hv[3]);
-            acc4 = band_ring(rg4, sl, acc4, hv[4]);
-          } else {
-            acc0 = band_ring(rg0, sl, acc0, hcol[j * PP]);
-            acc1 = band_ring(rg1, sl, acc1, hcol[(BY + j) * PP]);
-            acc2 = band_ring(rg2, sl, acc2, hcol[(2 * BY + j) * PP]);
-            acc3 = band_ring(rg3, sl, acc3, hcol[(3 * BY + j) * PP]);
-            acc4 = band_ring(rg4, sl, acc4, hcol[(4 * BY + j) * PP]);
-          }
-          const int m = k * BY + j - 2 * KR;  // output row within the tile
-          if (m >= 0 && m < rows) {
-            float un, vn;
-            solve2x2(acc0, acc1, acc2, acc3, acc4, um[j], vm[j], a.reg_rel, a.reg_abs, un, vn, inc, no_fp64);
-            const uint32_t oo = (__umul24(static_cast<uint32_t>(y0 + m), static_cast<uint32_t>(J.out_pitch)) +
-                                 static_cast<uint32_t>(gx)) * 4u;
-            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(un), wu, static_cast<int>(oo), 0, 0);
-            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(vn), wv, static_cast<int>(oo), 0, 0);
+              for (int q = 0; q < 5; ++q) hv[q] = hcol[(q * BY + j) * PP];
+              f0 = band_ring(rg0, sl, acc0, hv[0]);
+              f1 = band_ring(rg1, sl, acc1, hv[1]);
+              f2 = band_ring(rg2, sl, acc2, hv[2]);
+              f3 = band_ring(rg3, sl, acc3, hv[3]);
+              f4 = band_ring(rg4, sl, acc4, hv[4]);
+            } else {
+              f0 = band_ring(rg0, sl, acc0, hcol[j * PP]);
+              f1 = band_ring(rg1, sl, acc1, hcol[(BY + j) * PP]);
+              f2 = band_ring(rg2, sl, acc2, hcol[(2 * BY + j) * PP]);
+              f3 = band_ring(rg3, sl, acc3, hcol[(3 * BY + j) * PP]);
+              f4 = band_ring(rg4, sl, acc4, hcol[(4 * BY + j) * PP]);
+            }
+            finish_row(j, f0, f1, f2, f3, f4);
           }
         }
-        slot = sl + 1 == NWIN ? 0 : sl + 1;
+      } else {
+        // the block's rows are tail slots 16 + 4 g .. 16 + 4 g + 3: one copy per g
+        auto tail = [&](auto gc) {
+          constexpr int t0 = 4 * decltype(gc)::value;
+#pragma unroll
+          for (int j = 0; j < BY; ++j) {
+            if (out_lane) {
+              float hv[5];
+#pragma unroll
+              for (int q = 0; q < 5; ++q) hv[q] = hcol[(q * BY + j) * PP];
+              const float f0 = band_ring(rt0, t0 + j, acc0, hv[0]);
+              const float f1 = band_ring(rt1, t0 + j, acc1, hv[1]);
+              const float f2 = band_ring(rt2, t0 + j, acc2, hv[2]);
+              const float f3 = band_ring(rt3, t0 + j, acc3, hv[3]);
+              const float f4 = band_ring(rt4, t0 + j, acc4, hv[4]);
+              finish_row(j, f0, f1, f2, f3, f4);
+            }
+          }
+        };
+        band_dispatch((sl0 - 16) / 4, tail, std::make_integer_sequence<int, O::B / 4>());
       }
+      slot = (sl0 + BY) % NR;
     }
     // rows carried into the next block
     sR[0] = sR[BY];
