@@ -103,9 +103,10 @@ typedef struct {
  * Velocimetry", after Eq. of_symmetric): minimise
  * sum_k [I0(k) - I1(k + V)]^2 instead, linearised the same way about V(k)
  * with the gradient of the warped second image; the field is then anchored
- * at the pixels of frame 0.  Runs on 16 x 16 tiles (and the strip march for
- * levels one pixel thin), ignores the decomposition choice, and has no
- * adjoint (ofv_compute_flow_backward returns OFV_ERR_UNSUPPORTED). */
+ * at the pixels of frame 0.  Runs on 16 x 16 tiles, or on the strip march
+ * where the decomposition chosen is the march or the band (the band has no
+ * build for it) and on levels one pixel thin, and has no adjoint
+ * (ofv_compute_flow_backward returns OFV_ERR_UNSUPPORTED). */
 #define OFV_FLAG_FORWARD_ADDITIVE 1u
 
 /* params.flags: the increment form of the Gauss-Newton update, the
@@ -117,8 +118,7 @@ typedef struct {
  * field is uniform over the window and at V = 0.  Combined with
  * OFV_FLAG_FORWARD_ADDITIVE it is the textbook forward-additive
  * Lucas-Kanade step on every window.  Runs on the same kernels as
- * OFV_FLAG_FORWARD_ADDITIVE (16 x 16 tiles, the strip march for levels one
- * pixel thin) and has no adjoint. */
+ * OFV_FLAG_FORWARD_ADDITIVE and has no adjoint. */
 #define OFV_FLAG_INCREMENT_UPDATE 2u
 
 /* params.flags: switch off the float64 fallback of the 2x2 solve (by
@@ -280,8 +280,8 @@ ofv_status ofv_compute_flow_backward_batch(ofv_handle h, int n, const ofv_image*
 /* Work decompositions of the fused Gauss-Newton kernel, chosen per pyramid
  * level and input-flow mode.  All give the same results up to float32
  * rounding order (parity with the FP64 reference holds for each). */
-#define OFV_GN_AUTO (-1)      /* tuned table entry if any, else the march for launches of >= 3 Mi pixels,
-                                 OFV_GN_TILE_64x16 below */
+#define OFV_GN_AUTO (-1)      /* tuned table entry if any, else for launches of >= 3 Mi pixels the band
+                                 (kernel_radius >= 8) or the march, OFV_GN_TILE_64x16 below */
 #define OFV_GN_MARCH 0        /* 256-column strips marching down tile_h rows */
 #define OFV_GN_TILE_64x32 1   /* 64 x 32 output tiles, 512 lanes per workgroup */
 #define OFV_GN_TILE_64x16 2   /* 64 x 16 output tiles, 256 lanes per workgroup */

@@ -247,10 +247,14 @@ int choose_tile_h(int64_t strips_total, int64_t rows_max) {
 
 // Work decomposition of the Gauss-Newton kernel for one launch group:
 // OFV_GN_VARIANT in the environment, then a choice forced on the handle, then
-// the handle's tuned table, then the default: the strip march once the launch
-// covers enough pixels to give every CU several strips (measured on MI355X:
-// march ahead from about 4 Mp per launch), 64 x 16 tiles below that.  Levels
-// one pixel wide or high always take the march.
+// the handle's tuned table, then the default: from 3 Mi pixels per launch
+// (enough to give every CU several strips) the band march for windows of
+// KR >= 8 and the strip march below (measured on MI355X: at 5120 x 4096,
+// KR 10 the band takes 229 us against 296 us for the strip march and more
+// for every tile shape, in both the direct and the up-sampling flow mode;
+// on 16 or 64 pairs of 2048^2 at KR 4 the strip march leads at 2048^2 and
+// the band trails it), 64 x 16 tiles below 3 Mi pixels.  Levels one pixel
+// wide or high always take the strip march.
 void pick_gn_choice(const ofv_ctx* h, const ofv_ctx::TuneKey& key, int64_t strips, int64_t rows_max, int64_t pixels,
                     bool degenerate, int& variant, int& tile_h) {
   tile_h = choose_tile_h(strips, rows_max);
@@ -283,7 +287,7 @@ void pick_gn_choice(const ofv_ctx* h, const ofv_ctx::TuneKey& key, int64_t strip
     tile_h = it->second.tile_h;
     return;
   }
-  variant = pixels >= (int64_t{3} << 20) ? GN_MARCH : GN_TILE_64x16;
+  variant = pixels >= (int64_t{3} << 20) ? (key.kr >= 8 ? GN_BAND4 : GN_MARCH) : GN_TILE_64x16;
 }
 
 // pick_gn_choice, then for the band decomposition the tile height that gives
@@ -536,6 +540,10 @@ ofv_status run_pipeline(ofv_ctx* h, int n, PairPlan* pp, const ofv_params* p, fl
         int64_t pixels = 0;
         for (int j : group) pixels += static_cast<int64_t>(pp[j].lw[l]) * pp[j].lh[l];
         pick_gn(h, key, strips, rows_max, pixels, thin, variant, tile_h);
+        if (generic && variant == GN_BAND4) {  // the band has no generic-estimator build: the strip march
+          variant = GN_MARCH;
+          tile_h = choose_tile_h(strips, rows_max);
+        }
         if (generic && variant != GN_MARCH) variant = GN_TILE_16x16;   // the generic estimator's tiles
         gn_tile_dims(variant, kr, tile_h, tw, th);
         ga.tile_h = tile_h;

@@ -188,16 +188,32 @@ inline void gn_tile_dims(int variant, int kr, int tile_h, int& tw, int& th) {
 // storage and input-flow mode that fit on one compute unit at once (0 if
 // the runtime cannot tell).
 int gn_band_per_cu(int kr, int storage, int mode);
-// Output rows per band tile: enough tiles to give every resident workgroup
-// slot one (a single round), no fewer rows than keep the vertical halo
-// (2 kr + 2 rows) below about a third of the rows computed.
+// Output rows per band tile.  A tile of th rows marches th + 2 kr + 2 product
+// rows one after another, and the launch runs ceil(tiles / slots) rounds of
+// resident workgroups: th is the one of rows_max / k (k = 1, 2, ...) that
+// minimises rounds x (th + 2 kr + 2), no smaller than keeps the vertical
+// halo below about a third of the rows computed (4 kr + 8), unless the level
+// is lower than that.  One round when every strip fits in the slots (the
+// smallest tiles that still fit); when there are more strips than slots,
+// enough tiles per strip that the last round is not mostly idle.
 inline int gn_band_tile_h(int64_t strips, int64_t rows_max, int64_t slots, int kr) {
-  const int64_t per_strip = slots / (strips > 0 ? strips : 1);
-  int64_t th = per_strip > 0 ? (rows_max + per_strip - 1) / per_strip : rows_max;
-  const int64_t lo = 4 * kr + 8;
-  if (th < lo) th = lo;
-  if (th > rows_max) th = rows_max;
-  return static_cast<int>(th < 4 ? 4 : th);
+  if (strips < 1) strips = 1;
+  if (slots < 1) slots = 1;
+  if (rows_max < 1) rows_max = 1;
+  const int64_t lo = 4 * kr + 8 < rows_max ? 4 * kr + 8 : rows_max;
+  const int64_t halo = 2 * kr + 2;
+  int64_t best = rows_max, best_cost = -1;
+  for (int64_t k = 1; k <= rows_max; ++k) {
+    const int64_t th = (rows_max + k - 1) / k;
+    if (th < lo) break;
+    const int64_t tiles = strips * ((rows_max + th - 1) / th);
+    const int64_t cost = (tiles + slots - 1) / slots * (th + halo);
+    if (best_cost < 0 || cost < best_cost) {
+      best_cost = cost;
+      best = th;
+    }
+  }
+  return static_cast<int>(best < 4 ? 4 : best);
 }
 
 hipError_t launch_normalize(const NormArgs& a, int nblocks, hipStream_t s);
