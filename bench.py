@@ -186,6 +186,13 @@ def suite_batch4mp(args, dev):
             p = dict(prm, storage=storage)
             sec = _timed(lambda: ofv.compute_flow_batch(f0s, f1s, p, bit_depth=12, outs=outs, handle=hb), 3, 1)
             res[f"{storage}/{variant}"] = sec
+    # the batch autotuner: every decomposition per level and flow mode, timed on this batch
+    hb.set_gn_variant("auto")
+    for storage in ("f16", "f32"):
+        p = dict(prm, storage=storage)
+        hb.autotune_batch(f0s, f1s, p, bit_depth=12, repeats=2)
+        res[f"{storage}/tuned"] = _timed(lambda: ofv.compute_flow_batch(f0s, f1s, p, bit_depth=12, outs=outs,
+                                                                        handle=hb), 3, 1)
     best = min((v, k) for k, v in res.items() if k.startswith("f16"))
     # accuracy of pairs 0, 21, 42 and 63 in FP16 and FP32 against the FP64 oracle and the ground truth;
     # the floor is the FP64 oracle with its image planes rounded to FP16 (the error that FP16 storage
