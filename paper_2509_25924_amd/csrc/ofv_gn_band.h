@@ -12,8 +12,9 @@
 //      (loaded two blocks ahead, or up-sampled), the two midpoint bilinear
 //      warps, S and T.  Lanes are consecutive columns, so every gather of a
 //      wavefront touches a few cache lines.  The taps are issued one block
-//      ahead, right after the previous block's products, and stay in
-//      flight behind its window sums.  S of the block's rows -> LDS.
+//      ahead, right after the previous block's products (float32 planes:
+//      half of the rows there, half after its horizontal sums), and stay
+//      in flight behind its window sums.  S of the block's rows -> LDS.
 //  A2. Gx from the neighbouring lanes' S (LDS), Gy from the lane's own
 //      rows, b = G . V - T and the five products -> BY rows of five LDS
 //      planes (0 outside the level).
@@ -69,12 +70,13 @@ struct BandTaps {
   float u[N], v[N];  // the flow the warps used
 };
 
-template <int N, typename TS>
+// Rows n0 .. n1 - 1 of the n rows (gy0 + n).
+template <int N, typename TS, int N0 = 0, int N1 = N>
 __device__ __forceinline__ void band_issue(BandTaps<N>& q, PlaneView v0, PlaneView v1, uint32_t ip, uint32_t rowb,
                                            float fx, int gy0, int H, float wm1, float hm1, float wm2, float hm2,
                                            const float* u, const float* v, bool fa) {
 #pragma unroll
-  for (int n = 0; n < N; ++n) {
+  for (int n = N0; n < N1; ++n) {
     const float fy = static_cast<float>(min(max(gy0 + n, 0), H - 1));
     const float hu = fa ? 0.0f : 0.5f * u[n];
     const float hv = fa ? 0.0f : 0.5f * v[n];
@@ -270,6 +272,10 @@ void gn_band_kernel(const GnArgs a) {
   // whose rings leave no registers for taps in flight) a block's taps are
   // issued at its start and the field is read one block ahead.
   constexpr bool PIPE = BandOcc<KR>::pipelined;
+  // float32 planes: the next block's taps go out in two halves, after A2 and after B (measured
+  // at 5120 x 4096: 5 % less time at KR 5, 2 % at KR 7; with 16-bit planes, whose taps are half
+  // the bytes, one burst after A2 is 2-9 % faster)
+  constexpr bool SPLIT = PIPE && Px<TS>::bytes == 4;
   BandTaps<BY> taps;     // PIPE: block k + 1's taps, in flight during B and C of block k
   float fu[BY], fv[BY];  // FLOW_DIRECT: the field of the next block whose taps are not yet issued
   {
@@ -365,7 +371,7 @@ void gn_band_kernel(const GnArgs a) {
         p[4 * BY * PP] = gyv * b;
       }
     }
-    // the next block's taps (and the field two blocks ahead), in flight behind the window sums
+    // the next block's taps, in flight behind the window sums
     if (PIPE && k + 1 < nblk) {
       float u[BY], v[BY];
       if (MODE == FLOW_DIRECT) {
@@ -377,8 +383,19 @@ void gn_band_kernel(const GnArgs a) {
       } else {
         flow_rows(std::integral_constant<int, BY>(), ey0 + e0 + BY, u, v);
       }
-      band_issue<BY, TS>(taps, v0, v1, ip, rowb, fx, ey0 + e0 + BY, H, wm1, hm1, wm2, hm2, u, v, fa);
-      if (MODE == FLOW_DIRECT && k + 2 < nblk) flow_rows(std::integral_constant<int, BY>(), ey0 + e0 + 2 * BY, fu, fv);
+      if (SPLIT) {
+        // the first half of the rows here, the rest after B
+#pragma unroll
+        for (int n = 0; n < BY; ++n) {
+          taps.u[n] = u[n];
+          taps.v[n] = v[n];
+        }
+        band_issue<BY, TS, 0, BY / 2>(taps, v0, v1, ip, rowb, fx, ey0 + e0 + BY, H, wm1, hm1, wm2, hm2, u, v, fa);
+      } else {
+        band_issue<BY, TS>(taps, v0, v1, ip, rowb, fx, ey0 + e0 + BY, H, wm1, hm1, wm2, hm2, u, v, fa);
+        if (MODE == FLOW_DIRECT && k + 2 < nblk)
+          flow_rows(std::integral_constant<int, BY>(), ey0 + e0 + 2 * BY, fu, fv);
+      }
     }
     // without PIPE: the next block's field, in flight behind the window sums
     if (!PIPE && MODE == FLOW_DIRECT && k + 1 < nblk)
@@ -410,6 +427,12 @@ void gn_band_kernel(const GnArgs a) {
       }
     }
     __syncthreads();
+    // the second half of the next block's taps and, two blocks ahead, the field
+    if (SPLIT && k + 1 < nblk) {
+      band_issue<BY, TS, BY / 2, BY>(taps, v0, v1, ip, rowb, fx, ey0 + e0 + BY, H, wm1, hm1, wm2, hm2, taps.u, taps.v,
+                                     fa);
+      if (MODE == FLOW_DIRECT && k + 2 < nblk) flow_rows(std::integral_constant<int, BY>(), ey0 + e0 + 2 * BY, fu, fv);
+    }
     // ---- C: vertical window sums, solve and store of the completed output rows
     {
       if (MODE == FLOW_DIRECT && !PIPE) load_anchors();
