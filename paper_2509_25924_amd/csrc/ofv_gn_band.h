@@ -53,10 +53,17 @@ struct BandGeom {
   // sums from column seg * SL on, up to NSEG * SL + 2 KR + 1 <= TX + NSEG + 2 KR
   // entries into its row; the 64 floats after each region keep the last
   // row's overrun inside the allocation (overrun entries are never used).
+  // ANCH (KR >= 6, where registers already hold the kernel to two
+  // workgroups per compute unit): the input field of the last AR ext rows,
+  // u then v per row, a ring from which the vertical pass takes the damping
+  // anchor V(m) of each output row instead of reading the field again.
+  static constexpr bool ANCH = KR >= 6;
+  static constexpr int AR = BY + KR + 1;
   static constexpr int S_OFF = 0;
   static constexpr int P_OFF = S_OFF + BY * kBandThreads;
   static constexpr int H_OFF = P_OFF + NROW * PP + 64;
-  static constexpr int FLOATS = H_OFF + NROW * PP + 64;
+  static constexpr int A_OFF = H_OFF + NROW * PP + 64;
+  static constexpr int FLOATS = A_OFF + (ANCH ? AR * 2 * kBandThreads : 0);
   static_assert(TX + NSEG + 2 * KR <= PP + 64, "segment overrun fits in the slack");
 };
 
@@ -331,8 +338,9 @@ void gn_band_kernel(const GnArgs a) {
         vR[1 + n] = taps.v[n];
       }
     }
-    // damping anchor V(m) of the output rows this block completes: PIPE, in
-    // flight until C; otherwise loaded at the start of C (fewer live registers)
+    // damping anchor V(m) of the output rows this block completes.  ANCH:
+    // from the LDS ring in C.  Otherwise read again from the field: PIPE, in
+    // flight until C; else loaded at the start of C (fewer live registers).
     const int gm0 = y0 + k * BY - 2 * KR;  // level row of the block's first output (if any)
     float um[BY], vm[BY];
     auto load_anchors = [&]() {
@@ -344,12 +352,23 @@ void gn_band_kernel(const GnArgs a) {
         vm[j] = ld_f32(vv, o);
       }
     };
-    if (MODE == FLOW_DIRECT && PIPE) load_anchors();
+    if (MODE == FLOW_DIRECT && PIPE && !G::ANCH) load_anchors();
     // S of ext rows k BY + 1 .. k BY + BY (the product rows' own rows) for Gx
 #pragma unroll
     for (int j = 0; j < BY; ++j) lds[G::S_OFF + j * kBandThreads + tid] = sR[1 + j];
     __syncthreads();
     // ---- A2: gradients, b and the five products of product rows k BY + j
+    if (G::ANCH) {
+      // the field of the block's new ext rows k BY + 2 .. k BY + BY + 1 into the anchor ring.  The
+      // vertical pass of block k - 1 read its anchors before the barrier above, and this block's
+      // reads come after the next ones; rows k BY - KR + 1 .. k BY + BY + 1 (AR rows) are live.
+#pragma unroll
+      for (int j = 1; j <= BY; ++j) {
+        const int slot_a = (k * BY + 1 + j) % G::AR;
+        lds[G::A_OFF + slot_a * 2 * kBandThreads + tid] = uR[j];
+        lds[G::A_OFF + slot_a * 2 * kBandThreads + kBandThreads + tid] = vR[j];
+      }
+    }
     {
       const int tl = max(tid - 1, 0);
       const int tr = min(tid + 1, kBandThreads - 1);
@@ -435,18 +454,26 @@ void gn_band_kernel(const GnArgs a) {
     }
     // ---- C: vertical window sums, solve and store of the completed output rows
     {
-      if (MODE == FLOW_DIRECT && !PIPE) load_anchors();
-      if (MODE == FLOW_UPSAMPLE && out_lane) {
-        band_upsample<BY>(vu, vv, fpitch, hx, gm0, H, cwm1, chm1, cwm2, chm2, csx, csy, um, vm);
-      } else if (MODE == FLOW_ZERO) {
+      if (!G::ANCH) {
+        if (MODE == FLOW_DIRECT && !PIPE) load_anchors();
+        if (MODE == FLOW_UPSAMPLE && out_lane) {
+          band_upsample<BY>(vu, vv, fpitch, hx, gm0, H, cwm1, chm1, cwm2, chm2, csx, csy, um, vm);
+        } else if (MODE == FLOW_ZERO) {
 #pragma unroll
-        for (int j = 0; j < BY; ++j) um[j] = vm[j] = 0.0f;
+          for (int j = 0; j < BY; ++j) um[j] = vm[j] = 0.0f;
+        }
       }
       // solve and store of output row m = k BY + j - 2 KR from its window sums
       auto finish_row = [&](int j, float f0, float f1, float f2, float f3, float f4) {
         const int m = k * BY + j - 2 * KR;  // output row within the tile
         if (m >= 0 && m < rows) {
           float un, vn;
+          if (G::ANCH) {
+            // V(m): the field of ext row m + KR + 1 (the same value the warps of that row used)
+            const int slot_a = (m + KR + 1) % G::AR;
+            um[j] = MODE == FLOW_ZERO ? 0.0f : lds[G::A_OFF + slot_a * 2 * kBandThreads + tid];
+            vm[j] = MODE == FLOW_ZERO ? 0.0f : lds[G::A_OFF + slot_a * 2 * kBandThreads + kBandThreads + tid];
+          }
           solve2x2(f0, f1, f2, f3, f4, um[j], vm[j], a.reg_rel, a.reg_abs, un, vn, inc, no_fp64);
           const uint32_t oo = (__umul24(static_cast<uint32_t>(y0 + m), static_cast<uint32_t>(J.out_pitch)) +
                                static_cast<uint32_t>(gx)) * 4u;
