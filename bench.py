@@ -936,33 +936,46 @@ def time_two_streams(make_step, handles, steps, warmup):
 def time_gn_launch(ofv, p0, p1, fin, kr, reg_rel, reg_abs, handle, n, graph=True):
     """Average duration of one full-resolution Gauss-Newton launch (the stage entry point, same launch
     configuration and decomposition as inside the pipeline): n launches captured back to back in a hipGraph,
-    each of five replays bracketed by HIP events on the stream the kernel is launched on, median replay.
-    Also returns an eager loop of the same calls and event pairs around single eager launches."""
+    each reading the field the previous one wrote and writing the other of two buffers, as the pipeline's
+    iterations do; each of five replays bracketed by HIP events on the stream the kernel is launched on,
+    median replay.  Also returns an eager loop of the same calls and event pairs around single eager
+    launches."""
     import torch
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
-    for _ in range(3):
-        ofv.stage_gn_iteration(p0, p1, fin, "direct", kr, reg_rel, reg_abs, handle=handle)
+    bufs = [fin.clone(), torch.empty_like(fin)]
+
+    def launch(i):
+        ofv.stage_gn_iteration(p0, p1, bufs[i % 2], "direct", kr, reg_rel, reg_abs, handle=handle,
+                               out=bufs[(i + 1) % 2])
+
+    def reset():
+        bufs[0].copy_(fin)
+    for i in range(3):
+        launch(i)
+    reset()
     torch.cuda.synchronize()
-    for a, b in evs:
+    for i, (a, b) in enumerate(evs):
         a.record()
-        ofv.stage_gn_iteration(p0, p1, fin, "direct", kr, reg_rel, reg_abs, handle=handle)
+        launch(i)
         b.record()
     torch.cuda.synchronize()
     pair_s = sum(a.elapsed_time(b) for a, b in evs) / 1e3 / n
+    reset()
     ev0.record()
-    for _ in range(n):
-        ofv.stage_gn_iteration(p0, p1, fin, "direct", kr, reg_rel, reg_abs, handle=handle)
+    for i in range(n):
+        launch(i)
     ev1.record()
     torch.cuda.synchronize()
     eager_s = ev0.elapsed_time(ev1) / 1e3 / n
     kern_s = eager_s
     if graph:
+        reset()
         kgraph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(kgraph):
-            for _ in range(n):
-                ofv.stage_gn_iteration(p0, p1, fin, "direct", kr, reg_rel, reg_abs, handle=handle)
+            for i in range(n):
+                launch(i)
         handle.bind_stream()
         kgraph.replay()
         torch.cuda.synchronize()
@@ -1065,10 +1078,12 @@ def pmc_probe_21mp(args, dev):
     for _ in range(3):
         dst.copy_(src)
     torch.cuda.synchronize()
+    bufs = [fin.clone(), torch.empty_like(fin)]     # the field ping-pongs between two buffers, as in the pipeline
     for variant in GN_NAMES.values():
         hd.set_gn_variant(variant)
-        for _ in range(5):
-            ofv.stage_gn_iteration(p0, p1, fin, "direct", 10, 1e-3, 1e-9, handle=hd)
+        bufs[0].copy_(fin)
+        for i in range(5):
+            ofv.stage_gn_iteration(p0, p1, bufs[i % 2], "direct", 10, 1e-3, 1e-9, handle=hd, out=bufs[(i + 1) % 2])
         torch.cuda.synchronize()
     s_bytes = 4 if args.storage == "f32" else 2
     print(json.dumps({"pmc_probe": "wake_21mp", "copy_bytes_each_way": src.numel() * 4,
@@ -1143,11 +1158,13 @@ def main():
             dst.copy_(src)              # runtime blit kernel, same bytes
         torch.cuda.synchronize()
         fin = out.clone()
+        bufs = [fin.clone(), torch.empty_like(fin)]  # the field ping-pongs between two buffers, as in the pipeline
         for variant in GN_NAMES.values():
             handle.set_gn_variant(variant)
-            for _ in range(5):
-                ofv.stage_gn_iteration(p0, p1, fin, "direct", prm["kernel_radius"], prm["reg_rel"], prm["reg_abs"],
-                                       handle=handle)
+            bufs[0].copy_(fin)
+            for i in range(5):
+                ofv.stage_gn_iteration(p0, p1, bufs[i % 2], "direct", prm["kernel_radius"], prm["reg_rel"],
+                                       prm["reg_abs"], handle=handle, out=bufs[(i + 1) % 2])
             torch.cuda.synchronize()
         print(json.dumps({"pmc_probe": args.workload, "copy_bytes_each_way": src.numel() * 4,
                           "gn_bytes_per_launch": (2 * (4 if args.storage == "f32" else 2) + 16) * w * h}))

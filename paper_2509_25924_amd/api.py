@@ -475,8 +475,9 @@ def stage_upsample(flow: torch.Tensor, h: int, w: int, handle: Optional[Handle] 
 
 def stage_gn_iteration(p0: torch.Tensor, p1: torch.Tensor, flow_in: Optional[torch.Tensor], mode: str,
                        kernel_radius: int, reg_rel: float = 1e-3, reg_abs: float = 1e-9,
-                       handle: Optional[Handle] = None) -> torch.Tensor:
-    """One fused Gauss-Newton iteration; mode is 'zero', 'direct' or 'upsample'."""
+                       handle: Optional[Handle] = None, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """One fused Gauss-Newton iteration; mode is 'zero', 'direct' or 'upsample'.  out: an optional
+    [2, H, W] float32 result buffer (contiguous, not overlapping flow_in)."""
     _plane_check(p0)
     _plane_check(p1, p0.dtype)
     if p1.stride(0) != p0.stride(0) or p1.shape != p0.shape:
@@ -485,7 +486,18 @@ def stage_gn_iteration(p0: torch.Tensor, p1: torch.Tensor, flow_in: Optional[tor
     h, w = p0.shape
     m = {"zero": _lib.FLOW_IN_ZERO, "direct": _lib.FLOW_IN_DIRECT, "upsample": _lib.FLOW_IN_UPSAMPLE}[mode]
     hd = _stage_handle(p0, handle)
-    out = torch.empty((2, h, w), dtype=torch.float32, device=p0.device)
+    if out is None:
+        out = torch.empty((2, h, w), dtype=torch.float32, device=p0.device)
+    elif out.dtype != torch.float32 or tuple(out.shape) != (2, h, w) or not out.is_contiguous() or \
+            out.device != p0.device:
+        raise ValueError("out must be a contiguous [2, H, W] float32 tensor on the planes' device")
+    elif flow_in is not None:
+        a0, a1 = out.data_ptr(), out.data_ptr() + out.numel() * 4
+        b0 = flow_in.data_ptr()
+        b1 = b0 + (flow_in.stride(0) * (flow_in.shape[0] - 1) + flow_in.stride(1) * (flow_in.shape[1] - 1) +
+                   flow_in.shape[2]) * flow_in.element_size()
+        if a0 < b1 and b0 < a1:
+            raise ValueError("out overlaps flow_in")
     if flow_in is None:
         fin, iw, ih = None, w, h
     else:

@@ -219,6 +219,21 @@ def test_band_every_ring_layout(ofv, kr, mode, storage):
     assert int(ill.sum()) <= 8 and err_ill < 2e-3
 
 
+def test_stage_gn_iteration_into_given_buffer(ofv):
+    """The stage call writes a caller's buffer exactly as a buffer of its own, and refuses one that overlaps
+    the input field."""
+    say("stage into a given buffer")
+    n0, n1, gt = _level_pair(96, 300, seed=77)
+    fin = dev_tensor((gt[:, :96, :300] + 0.1).astype(np.float32))
+    want = ofv.stage_gn_iteration(n0.cuda(), n1.cuda(), fin, "direct", 6)
+    out = torch.full_like(want, float("nan"))
+    got = ofv.stage_gn_iteration(n0.cuda(), n1.cuda(), fin, "direct", 6, out=out)
+    torch.cuda.synchronize()
+    assert got.data_ptr() == out.data_ptr() and torch.equal(out, want)
+    with pytest.raises(ValueError):
+        ofv.stage_gn_iteration(n0.cuda(), n1.cuda(), fin, "direct", 6, out=fin)
+
+
 # ---------------------------------------------------------------- whole pipeline
 
 def _run_both(ofv, pair, prm, bits, flow_init=None):
