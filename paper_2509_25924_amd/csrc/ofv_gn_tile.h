@@ -457,8 +457,8 @@ void gn_tile_kernel(const GnArgs a) {
                      un, vn, inc, no_fp64);
             const uint32_t oo =
                 (__umul24(static_cast<uint32_t>(gy), static_cast<uint32_t>(J.out_pitch)) + static_cast<uint32_t>(gx)) * 4u;
-            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(un), wu, static_cast<int>(oo), 0, 0);
-            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(vn), wv, static_cast<int>(oo), 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(un), wu, static_cast<int>(oo), 0, kStreamPolicy);
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(vn), wv, static_cast<int>(oo), 0, kStreamPolicy);
           }
         }
       }
