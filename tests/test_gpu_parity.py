@@ -234,6 +234,61 @@ def test_stage_gn_iteration_into_given_buffer(ofv):
         ofv.stage_gn_iteration(n0.cuda(), n1.cuda(), fin, "direct", 6, out=fin)
 
 
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_band_full_frame_sampled(ofv, storage):
+    """The level-0 launch the headline line times at full size: 5120x4096, KR 10, the band march with the
+    tile height the occupancy gives (the decomposition the autotuner picks there), direct input field.
+    240 sampled output pixels (corners, borders, strip and tile seams, random) against the FP64 oracle's
+    iteration on a 41x41 crop around each: the crop holds the window, the gradient stencil and every
+    bilinear tap of a field of at most 10 px, and where it meets the image border it is the image border,
+    so the oracle's value at the centre is its full-frame value.  Tolerance per pixel: 1e-4 px plus 1.5x
+    the float32 spacing of its column and row coordinates, which the kernels' warp positions k -/+ V/2
+    carry (4.9e-4 px from x = 4096 on; every decomposition shows the same error there)."""
+    from synth.gpu_render import make_pair_device
+    say("band full frame", storage)
+    W, H, KR, R = 5120, 4096, 10, 20
+    flow = synth.CylinderWake(H, W, t=0.0, dmax=10.0)
+    a, b, gt = make_pair_device(H, W, flow, fwhm=2.5, ppp=0.1, seed=4000, bit_depth=12, noise=0.01 * 4095,
+                                device=torch.device("cuda"), max_disp=10.0, with_gt=True)
+    hd = ofv.Handle(W, H, 1)
+    p0 = ofv.stage_normalize(a, 2, 1e-4, storage, bit_depth=12, handle=hd)
+    p1 = ofv.stage_normalize(b, 2, 1e-4, storage, bit_depth=12, handle=hd)
+    fin_np = gt.astype(np.float32)
+    hd.set_gn_variant("band", 0)
+    got = ofv.stage_gn_iteration(p0, p1, dev_tensor(fin_np), "direct", KR, handle=hd).cpu().double()
+    n0, n1 = p0.cpu().double(), p1.cpu().double()
+    hd.close()
+    tx = 256 - 2 * KR - 2
+    rng = np.random.default_rng(11)
+    pts = [(0, 0), (0, W - 1), (H - 1, 0), (H - 1, W - 1), (H // 2, 0), (H // 2, W - 1), (0, W // 2), (H - 1, W // 2)]
+    pts += [(int(rng.integers(0, H)), c) for c in (tx - 1, tx, 2 * tx - 1, 2 * tx, 21 * tx - 1, 21 * tx)]
+    pts += [(r, int(rng.integers(0, W))) for r in (178, 179, 180, 2047, 2048, 4095 - 179)]
+    pts += [(int(rng.integers(0, H)), int(rng.integers(0, W))) for _ in range(240 - len(pts))]
+    worst, worst_ill, n_ill = 0.0, 0.0, 0   # worst: largest error / tolerance
+    for y, x in pts:
+        tol = 1e-4 + 1.5 * float(np.spacing(np.float32(max(x, 1))) + np.spacing(np.float32(max(y, 1))))
+        y0, y1, x0, x1 = max(y - R, 0), min(y + R + 1, H), max(x - R, 0), min(x + R + 1, W)
+        terms = []
+        ru, rv = oracle.gn_iteration(n0[y0:y1, x0:x1], n1[y0:y1, x0:x1],
+                                     torch.as_tensor(fin_np[0, y0:y1, x0:x1].astype(np.float64)),
+                                     torch.as_tensor(fin_np[1, y0:y1, x0:x1].astype(np.float64)), KR, 1e-3, 1e-9,
+                                     terms=terms)
+        cy, cx = y - y0, x - x0
+        d = max(abs(got[0, y, x].item() - ru[cy, cx].item()), abs(got[1, y, x].item() - rv[cy, cx].item()))
+        sm = {k: v[cy, cx].item() for k, v in terms[0].sums.items()}
+        lam = 1e-3 * (sm["sxx"] + sm["syy"]) + 1e-9
+        aa, dd = sm["sxx"] + lam, sm["syy"] + lam
+        if 4 * (aa * dd - sm["sxy"] ** 2) < 1e-2 * (aa + dd) ** 2:  # the solver's own conditioning test
+            n_ill += 1
+            worst_ill = max(worst_ill, d)
+        else:
+            worst = max(worst, d / tol)
+    say(f"  max |dV| / tol {worst:.3f} over {len(pts) - n_ill} pixels; {n_ill} ill-conditioned, "
+        f"max |dV| {worst_ill:.2e}")
+    assert worst < 1.0
+    assert worst_ill < 2e-3
+
+
 # ---------------------------------------------------------------- whole pipeline
 
 def _run_both(ofv, pair, prm, bits, flow_init=None):
