@@ -343,7 +343,7 @@ def suite_live21mp(args, dev):
     ograph = [capture(lambda ph=ph: batch_of(*pairs[ph], p)) for ph in range(phases)]
     overrun = max_overrun_free_rate(
         lambda period: LiveLoop(lambda k: ograph[k % phases].replay(), period, wait=torch.cuda.synchronize),
-        [90.0, 200.0, 300.0, 350.0, 400.0, 450.0, 500.0, 600.0], 200)
+        [90.0, 200.0, 300.0, 350.0, 400.0, 450.0, 500.0, 600.0, 650.0, 700.0], 200)
     del ograph
     nhost = 4
     host = [torch.empty((H, W), dtype=torch.int16, pin_memory=True) for _ in range(nhost)]
@@ -992,11 +992,12 @@ def time_gn_launch(ofv, p0, p1, fin, kr, reg_rel, reg_abs, handle, n, graph=True
 
 
 def tuned_decomposition(handle, kr, w, h):
-    """Name of the tuned decomposition of the level-0 direct-flow launch, 'auto' if none."""
+    """Name of the tuned decomposition of the level-0 direct-flow launch, 'auto' if none; a band entry with a
+    fixed tile height carries it ('band/h128'), one sized from the occupancy at launch is plain 'band'."""
     for line in handle.tuning_table().splitlines():
         f = [int(x) for x in line.split()]
         if f[0] == kr and f[2] == 1 and f[3] == w and f[4] == h and f[5] == 1:
-            return GN_NAMES[f[6]]
+            return GN_NAMES[f[6]] + (f"/h{f[7]}" if f[6] == 11 and f[7] > 0 else "")
     return "auto"
 
 

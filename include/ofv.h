@@ -330,13 +330,16 @@ ofv_status ofv_autotune_batch(ofv_handle h, int n, const ofv_image* frame0, cons
                               const ofv_params* params, float* const* flow_out, int repeats);
 
 /* The tuned table as text, one entry per line:
- * "kr storage mode width height batch variant tile_h".  Writes at most cap
+ * "kr storage mode width height batch variant tile_h" (tile_h 4..1024; for
+ * OFV_GN_BAND also 0: sized at every launch from the occupancy query, as
+ * the autotuner's fixed heights 64, 128 and 256 are not).  Writes at most cap
  * bytes (NUL-terminated) to buf when buf is not NULL; *needed (if not NULL)
  * receives the size including the NUL.  OFV_ERR_CAPACITY if cap is short. */
 ofv_status ofv_tuning_export(ofv_handle h, char* buf, size_t cap, size_t* needed);
 
-/* Merge entries in the export format into h's table; nothing is merged if
- * any entry is malformed (OFV_ERR_INVALID_ARG). */
+/* Merge entries in the export format into h's table, one per line (blank
+ * lines skipped); nothing is merged if any line is malformed (not exactly
+ * eight integers) or invalid (OFV_ERR_INVALID_ARG). */
 ofv_status ofv_tuning_import(ofv_handle h, const char* text);
 
 /* ---- Time-resolved streaming (the paper's live regime: consecutive frames

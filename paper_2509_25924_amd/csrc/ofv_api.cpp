@@ -274,11 +274,12 @@ void pick_gn_choice(const ofv_ctx* h, const ofv_ctx::TuneKey& key, int64_t strip
     if (!std::strcmp(e, "tile16x16w")) { variant = GN_TILE_16x16W; return; }
     if (!std::strcmp(e, "tile32x16w")) { variant = GN_TILE_32x16W; return; }
     if (!std::strcmp(e, "tile32x32w")) { variant = GN_TILE_32x32W; return; }
-    if (!std::strcmp(e, "band")) { variant = GN_BAND4; return; }
+    if (!std::strcmp(e, "band")) { variant = GN_BAND4; tile_h = 0; return; }
   }
   if (h->forced_variant >= 0) {
     variant = h->forced_variant;
     if (h->forced_tile_h > 0) tile_h = h->forced_tile_h;
+    else if (variant == GN_BAND4) tile_h = 0;
     return;
   }
   auto it = h->tuned.find(key);
@@ -288,20 +289,19 @@ void pick_gn_choice(const ofv_ctx* h, const ofv_ctx::TuneKey& key, int64_t strip
     return;
   }
   variant = pixels >= (int64_t{3} << 20) ? (key.kr >= 8 ? GN_BAND4 : GN_MARCH) : GN_TILE_64x16;
+  if (variant == GN_BAND4) tile_h = 0;
 }
 
-// pick_gn_choice, then for the band decomposition the tile height that gives
-// one round of resident workgroups (unless a tile height was forced).
+// pick_gn_choice, then for the band decomposition without a tile height of
+// its own (forced or tuned; 0 = none) the one from the occupancy query over
+// the jobs of one launch (job j: band_strips[j] strips of band_rows[j] rows).
 void pick_gn(const ofv_ctx* h, const ofv_ctx::TuneKey& key, int64_t strips, int64_t rows_max, int64_t pixels,
-             bool degenerate, int& variant, int& tile_h) {
+             bool degenerate, int& variant, int& tile_h, const int64_t* band_strips, const int64_t* band_rows,
+             int band_jobs) {
   pick_gn_choice(h, key, strips, rows_max, pixels, degenerate, variant, tile_h);
-  if (variant != GN_BAND4) return;
-  if (h->forced_variant == GN_BAND4 && h->forced_tile_h > 0) {
-    tile_h = h->forced_tile_h;
-    return;
-  }
+  if (variant != GN_BAND4 || tile_h > 0) return;
   const int per_cu = std::max(1, gn_band_per_cu(key.kr, key.storage, key.mode));
-  tile_h = gn_band_tile_h(strips, rows_max, static_cast<int64_t>(per_cu) * h->num_cus, key.kr);
+  tile_h = gn_band_tile_h(band_strips, band_rows, band_jobs, static_cast<int64_t>(per_cu) * h->num_cus, key.kr);
 }
 
 hipEvent_t next_event(ofv_ctx* h) {
@@ -546,7 +546,14 @@ ofv_status run_pipeline(ofv_ctx* h, int n, PairPlan* pp, const ofv_params* p, fl
         int variant = 0, tile_h = 0, tw = 0, th = 0;
         int64_t pixels = 0;
         for (int j : group) pixels += static_cast<int64_t>(pp[j].lw[l]) * pp[j].lh[l];
-        pick_gn(h, key, strips, rows_max, pixels, thin, variant, tile_h);
+        // the band's tile height from the jobs of the group's largest launch (the first kMaxJobs)
+        int64_t bs[kMaxJobs], br[kMaxJobs];
+        const int bj = std::min<int>(kMaxJobs, static_cast<int>(group.size()));
+        for (int gi = 0; gi < bj; ++gi) {
+          bs[gi] = (pp[group[gi]].lw[l] + tx - 1) / tx;
+          br[gi] = pp[group[gi]].lh[l];
+        }
+        pick_gn(h, key, strips, rows_max, pixels, thin, variant, tile_h, bs, br, bj);
         if (generic && variant == GN_BAND4) {  // the band has no generic-estimator build: the strip march
           variant = GN_MARCH;
           tile_h = choose_tile_h(strips, rows_max);
@@ -1725,11 +1732,14 @@ ofv_status autotune_impl(ofv_handle h, int n, const ofv_image* frame0, const ofv
   struct Cand {
     int variant, tile_h;
   };
-  // tile variants ignore tile_h (their tile height is fixed); it is recorded as their height
+  // tile variants ignore tile_h (their tile height is fixed); it is recorded as their height.  The band
+  // takes the occupancy-derived height (0) and three fixed ones: taller tiles than one round of resident
+  // workgroups gives halve the vertical halo at the cost of idle slots
   const Cand cands[] = {{GN_TILE_16x16, 16},  {GN_TILE_16x16W, 16}, {GN_TILE_32x16, 16}, {GN_TILE_32x16W, 16},
                         {GN_TILE_64x16, 16},  {GN_TILE_64x32, 32},  {GN_TILE_64x16W, 16}, {GN_TILE_64x32W, 32},
                         {GN_TILE_32x32W, 32}, {GN_TILE_64x64, 64},  {GN_MARCH, 16},       {GN_MARCH, 32},
-                        {GN_MARCH, 64},       {GN_BAND4, 0}};
+                        {GN_MARCH, 64},       {GN_BAND4, 0},       {GN_BAND4, 64},      {GN_BAND4, 128},
+                        {GN_BAND4, 256}};
   constexpr int nc = static_cast<int>(sizeof(cands) / sizeof(cands[0]));
   // launch times per (level key, candidate); the candidates take turns within every
   // repeat, so that slow drifts of the clock affect them alike
@@ -1811,18 +1821,24 @@ ofv_status ofv_tuning_import(ofv_handle h, const char* text) {
   if (!text) return fail(h, OFV_ERR_INVALID_ARG, "text is NULL");
   std::istringstream is(text);
   std::map<ofv_ctx::TuneKey, ofv_ctx::Choice> add;
-  ofv_ctx::TuneKey k{};
-  ofv_ctx::Choice c{};
+  std::string row;
   int line = 0;
-  while (is >> k.kr >> k.storage >> k.mode >> k.w >> k.hgt >> k.n >> c.variant >> c.tile_h) {
+  while (std::getline(is, row)) {
     ++line;
-    // band entries record tile height 0: it is sized at every launch
+    if (row.find_first_not_of(" \t\r") == std::string::npos) continue;   // blank line
+    std::istringstream ls(row);
+    ofv_ctx::TuneKey k{};
+    ofv_ctx::Choice c{};
+    std::string rest;
+    // eight integers and nothing after them
+    if (!(ls >> k.kr >> k.storage >> k.mode >> k.w >> k.hgt >> k.n >> c.variant >> c.tile_h) || (ls >> rest))
+      return fail(h, OFV_ERR_INVALID_ARG, "tuning line %d is malformed", line);
+    // band entries record tile height 0 (sized at every launch from the occupancy) or 4..1024
     if (c.variant < GN_MARCH || c.variant >= kGnVariants ||
-        (c.variant == GN_BAND4 ? c.tile_h != 0 : (c.tile_h < 4 || c.tile_h > 1024)))
-      return fail(h, OFV_ERR_INVALID_ARG, "tuning entry %d is invalid", line);
+        ((c.tile_h < 4 || c.tile_h > 1024) && !(c.variant == GN_BAND4 && c.tile_h == 0)))
+      return fail(h, OFV_ERR_INVALID_ARG, "tuning line %d is invalid", line);
     add[k] = c;
   }
-  if (!is.eof()) return fail(h, OFV_ERR_INVALID_ARG, "tuning text is malformed after %d entries", line);
   for (const auto& kv : add) h->tuned[kv.first] = kv.second;
   return OFV_OK;
 }
@@ -2024,8 +2040,9 @@ ofv_status ofv_stage_gn_iteration(ofv_handle h, int storage, const void* p0, con
   ga.reg_abs = reg_abs;
   const int tx = gn_tile_w(kernel_radius);
   int variant = 0, tw = 0, th = 0;
-  pick_gn(h, ofv_ctx::TuneKey{kernel_radius, storage, mode, width, height, 1}, (width + tx - 1) / tx, height,
-          static_cast<int64_t>(width) * height, width < 2 || height < 2, variant, ga.tile_h);
+  const int64_t strips = (width + tx - 1) / tx, rows = height;
+  pick_gn(h, ofv_ctx::TuneKey{kernel_radius, storage, mode, width, height, 1}, strips, rows,
+          static_cast<int64_t>(width) * height, width < 2 || height < 2, variant, ga.tile_h, &strips, &rows, 1);
   gn_tile_dims(variant, kernel_radius, ga.tile_h, tw, th);
   GnJob& J = ga.job[0];
   J.p0 = p0;

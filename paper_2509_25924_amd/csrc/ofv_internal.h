@@ -188,25 +188,28 @@ inline void gn_tile_dims(int variant, int kr, int tile_h, int& tw, int& th) {
 // storage and input-flow mode that fit on one compute unit at once (0 if
 // the runtime cannot tell).
 int gn_band_per_cu(int kr, int storage, int mode);
-// Output rows per band tile.  A tile of th rows marches th + 2 kr + 2 product
-// rows one after another, and the launch runs ceil(tiles / slots) rounds of
-// resident workgroups: th is the one of rows_max / k (k = 1, 2, ...) that
+// Output rows per band tile for the jobs of one launch, job j covering
+// strips[j] strips of rows[j] rows.  A tile of th rows marches th + 2 kr + 2
+// product rows one after another, and the launch runs ceil(tiles / slots)
+// rounds of resident workgroups, tiles = sum over jobs of strips[j] x
+// ceil(rows[j] / th): th is the one of rows_max / k (k = 1, 2, ...) that
 // minimises rounds x (th + 2 kr + 2), no smaller than keeps the vertical
-// halo below about a third of the rows computed (4 kr + 8), unless the level
-// is lower than that.  One round when every strip fits in the slots (the
-// smallest tiles that still fit); when there are more strips than slots,
-// enough tiles per strip that the last round is not mostly idle.
-inline int gn_band_tile_h(int64_t strips, int64_t rows_max, int64_t slots, int kr) {
-  if (strips < 1) strips = 1;
+// halo below about a third of the rows computed (4 kr + 8), unless the
+// tallest level is lower than that.  One round when every strip fits in the
+// slots (the smallest tiles that still fit); when there are more strips than
+// slots, enough tiles per strip that the last round is not mostly idle.
+inline int gn_band_tile_h(const int64_t* strips, const int64_t* rows, int njobs, int64_t slots, int kr) {
   if (slots < 1) slots = 1;
-  if (rows_max < 1) rows_max = 1;
+  int64_t rows_max = 1;
+  for (int j = 0; j < njobs; ++j) rows_max = rows[j] > rows_max ? rows[j] : rows_max;
   const int64_t lo = 4 * kr + 8 < rows_max ? 4 * kr + 8 : rows_max;
   const int64_t halo = 2 * kr + 2;
   int64_t best = rows_max, best_cost = -1;
   for (int64_t k = 1; k <= rows_max; ++k) {
     const int64_t th = (rows_max + k - 1) / k;
     if (th < lo) break;
-    const int64_t tiles = strips * ((rows_max + th - 1) / th);
+    int64_t tiles = 0;
+    for (int j = 0; j < njobs; ++j) tiles += (strips[j] > 1 ? strips[j] : 1) * ((rows[j] + th - 1) / th);
     const int64_t cost = (tiles + slots - 1) / slots * (th + halo);
     if (best_cost < 0 || cost < best_cost) {
       best_cost = cost;

@@ -434,3 +434,20 @@ def test_save_iterates_validation(lib, vhandle):
     q = _params(flags=_lib.FLAG_SAVED_FORWARD)
     assert lib.ofv_compute_flow_backward(vhandle, byref(img0), byref(img1), byref(q), None, c_void_p(OUT),
                                          c_void_p(OUT + (1 << 20)), None, None) == _lib.OFV_ERR_CAPACITY
+
+
+def test_tuning_import_validation(lib, vhandle):
+    """Tile heights 4..1024 for every decomposition, and 0 (sized from the occupancy at every launch) for the
+    band only; a malformed entry merges nothing."""
+    for ok in (b"10 0 1 5120 4096 1 11 0\n", b"10 0 1 5120 4096 1 11 128\n", b"5 0 1 1024 1024 1 7 64\n"):
+        assert lib.ofv_tuning_import(vhandle, ok) == _lib.OFV_OK, ok
+    for bad in (b"10 0 1 5120 4096 1 11 2\n", b"5 0 1 1024 1024 1 7 0\n", b"10 0 1 2560 2048 1 12 0\n",
+                b"10 0 1 2560 2048 1 11 2048\n", b"10 0 1 2560 2048 1 11\n"):
+        assert lib.ofv_tuning_import(vhandle, b"4 0 1 256 256 1 4 16\n" + bad) == _lib.OFV_ERR_INVALID_ARG, bad
+    need = c_size_t(0)
+    assert lib.ofv_tuning_export(vhandle, None, 0, byref(need)) == _lib.OFV_OK
+    buf = ctypes.create_string_buffer(need.value)
+    assert lib.ofv_tuning_export(vhandle, buf, need.value, byref(need)) == _lib.OFV_OK
+    lines = set(buf.value.decode().split("\n"))
+    assert "10 0 1 5120 4096 1 11 128" in lines and "5 0 1 1024 1024 1 7 64" in lines
+    assert not any(l.startswith("4 0 1 256 256") for l in lines)        # the rejected texts merged nothing
