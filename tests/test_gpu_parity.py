@@ -179,8 +179,21 @@ def test_band_every_ring_layout(ofv, kr, mode, storage):
     one block ahead), a ring split into a run-time and a compile-time indexed part (KR 10, 12), a
     padded ring without taps in flight (KR 9, 11).  150x300 with 24-row tiles: two strips, seven
     tiles per strip, every tile's ring wrapping at least once."""
-    say("band stage", kr, mode, storage)
-    h, w = 150, 300
+    _band_stage_vs_oracle(ofv, kr, mode, storage, 150, 300)
+
+
+@pytest.mark.parametrize("kr,mode,storage,shape", [(3, "zero", "bf16", (151, 301)), (5, "zero", "f16", (151, 301)),
+                                                    (10, "direct", "bf16", (151, 301)), (3, "zero", "bf16", (150, 300))])
+def test_band_16bit_taps_at_the_plane_end(ofv, kr, mode, storage, shape):
+    """16-bit planes without row padding (pitch = width), of an odd (151 x 301) and an even (150 x 300)
+    number of elements: with the zero field the bottom-right pixel's bilinear pair on the second tap row
+    is the plane's last two elements, read as one 4-byte load at a 2-byte boundary that ends with the
+    plane."""
+    _band_stage_vs_oracle(ofv, kr, mode, storage, *shape)
+
+
+def _band_stage_vs_oracle(ofv, kr, mode, storage, h, w):
+    say("band stage", kr, mode, storage, f"{w}x{h}")
     dt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[storage]
     n0, n1, gt = _level_pair(h, w, seed=40 + kr, storage_dtype=dt)
     rng = np.random.default_rng(100 + kr)
