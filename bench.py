@@ -157,6 +157,15 @@ def _sweep_bytes(levels, w, h, iters, s_bytes, in_bytes, npairs=1):
     return b * npairs
 
 
+def _step_models(per_sweep, fused, sec):
+    """A whole step's bytes over its time under both algorithmic models, as fractions of HBM peak:
+    per_sweep (_sweep_bytes: every iteration streams its level's planes and field) and fused_iterations
+    (the bound if all iterations of a level ran on chip: the first iteration's traffic only, i.e.
+    _sweep_bytes with one iteration)."""
+    return {m: {"bytes": int(b), "GBps": round(b / sec / 1e9, 1), "frac_of_8TBps": round(b / sec / 8e12, 4)}
+            for m, b in (("per_sweep", per_sweep), ("fused_iterations", fused))}
+
+
 def suite_batch4mp(args, dev):
     """64 time-resolved 2048x2048 12-bit turbulence pairs in one call, FP16 storage."""
     import torch
@@ -241,7 +250,8 @@ def suite_batch4mp(args, dev):
             "decomposition": best[1], "seconds_per_batch": {k: round(v, 5) for k, v in res.items()},
             "fp32_single_pair_fields_per_s": round(n / sec1, 1),
             "speedup_vs_fp32_single_pair": round(sec1 / best[0], 2),
-            "step_algorithmic_GBps": round(byts / best[0] / 1e9, 1), "accuracy": acc,
+            "step_algorithmic_GBps": round(byts / best[0] / 1e9, 1),
+            "step_bytes_models": _step_models(byts, _sweep_bytes(5, 2048, 2048, 1, 2, 2, n), best[0]), "accuracy": acc,
             "data": "synthetic: 8 distinct time steps of a 256-mode k^-5/3 field tiled to 64 pairs"}
 
 
@@ -381,8 +391,9 @@ def suite_live21mp(args, dev):
         ring[0].copy_(host[0], non_blocking=True)
     torch.cuda.synchronize()
     h2d = 20 * ring[0].numel() * 2 / (time.perf_counter() - t0) / 1e9
-    byts = (_sweep_bytes(4, W, H, 3, 2 if storage != "f32" else 4, 2) + _sweep_bytes(4, 2048, 2048, 3, 2 if storage != "f32" else 4, 2)
-            + _sweep_bytes(4, 1024, 1024, 3, 2 if storage != "f32" else 4, 2))
+    sb = 2 if best_key.startswith("bf16") else 4      # planes of the fastest configuration
+    byts, byts_fused = (sum(_sweep_bytes(4, sw, sh, its, sb, 2) for sw, sh in ((W, H), (2048, 2048), (1024, 1024)))
+                        for its in (3, 1))
 
     # live derived quantities of the 21 Mp field in every step (vorticity plane, recirculation area
     # outside the cylinder, 64 probes along the wake centre line), captured in the same graph
@@ -458,6 +469,7 @@ def suite_live21mp(args, dev):
             "gvectors_per_s": round(vec / best / 1e9, 3), "steps_per_s_by_config": per,
             "fields_per_s_each_size": round(1.0 / best, 1),
             "step_algorithmic_GBps": round(byts / best / 1e9, 1),
+            "step_bytes_models": _step_models(byts, byts_fused, best),
             "streaming_steps_per_s": round(1.0 / sec_stream, 1),
             "two_stream_steps_per_s": round(1.0 / sec_two, 1),
             "streaming": "one new 12-bit 5120x4096 frame (42 MB) per step, pinned host ring -> 3 device slots, "
@@ -831,10 +843,12 @@ def suite_paper(args, dev):
                     k[0] += 1
                 sec = _timed(one, 40 if w * h > 4 << 20 else 200, 5)
                 byts = _sweep_bytes(levels, w, h, 3, 4 if storage == "f32" else 2, 1)
+                fused = _sweep_bytes(levels, w, h, 1, 4 if storage == "f32" else 2, 1)
                 rows.append({"size": f"{w}x{h}", "psl": levels - 1, "storage": storage,
                              "fields_per_s": round(1.0 / sec, 1), "mvectors_per_s": round(w * h / sec / 1e6, 1),
                              "algorithmic_GBps": round(byts / sec / 1e9, 1),
-                             "frac_of_8TBps": round(byts / sec / 8e12, 4)})
+                             "frac_of_8TBps": round(byts / sec / 8e12, 4),
+                             "frac_of_8TBps_fused_iterations": round(fused / sec / 8e12, 4)})
         hd.close()
     return {"metric": "fields/s at the paper's throughput setting (NR 2, KR 10, IT 3)", "rows": rows,
             "paper_rtx5090_offline_fields_per_s": {"1Mp": [1100, 1800], "4Mp": [400, 500], "21Mp": [80, 99]},
@@ -1262,19 +1276,11 @@ def main():
     algo_bytes = bytes_per_px * w * h
     achieved = algo_bytes / kern_s / 1e9
 
-    # whole-step algorithmic bytes (per-sweep model) for context
+    # whole-step algorithmic bytes for context: the per-sweep model and the fused-iteration lower bound
     L, it = prm["num_levels"], prm["iterations"]
     in_bytes = {8: 1, 12: 2, 16: 2}.get(bits, 4)
-    lw, lh = [w], [h]
-    for _ in range(L - 1):
-        lw.append((lw[-1] + 1) // 2)
-        lh.append((lh[-1] + 1) // 2)
-    npx = [a * b for a, b in zip(lw, lh)]
-    step_bytes = 2 * in_bytes * npx[0] + 2 * s_bytes * npx[0]
-    step_bytes += sum(2 * s_bytes * (npx[l - 1] + npx[l]) for l in range(1, L))
-    for l in range(L):
-        first = (2 * s_bytes + 10) if l < L - 1 else (2 * s_bytes + 8)
-        step_bytes += npx[l] * (first + (it - 1) * (2 * s_bytes + 16))
+    step_bytes = _sweep_bytes(L, w, h, it, s_bytes, in_bytes)
+    step_fused = _sweep_bytes(L, w, h, 1, s_bytes, in_bytes)
 
     result = {
         "metric": "dense-flow Mvectors/s (fields/s at 1/4/21 Mp), % HBM roofline, bwd/fwd time",
@@ -1298,6 +1304,7 @@ def main():
         "fields_per_s": round(1.0 / sec, 1),
         "two_stream_pipeline": two_stream,
         "step_algorithmic_GBps": round(step_bytes / sec / 1e9, 1),
+        "step_bytes_models": _step_models(step_bytes, step_fused, sec),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(args.workload, args.storage, decomp),
