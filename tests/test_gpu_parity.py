@@ -61,6 +61,19 @@ def test_normalize_stage(ofv, kind, bits, nr, shape):
     assert torch.max(torch.abs(o64(got) - ref)).item() < 2e-5
 
 
+@pytest.mark.parametrize("nr", [1, 2, 3])
+def test_normalize_stage_particle_frame(ofv, nr):
+    """12-bit particle frames (bright blobs on a dark, slightly noisy background): windows whose mean sits
+    far from some of their pixels, the hard case for a variance formed from sums of squares."""
+    say("normalize particles", nr)
+    pair = synth.make_pair(200, 300, synth.Rankine(150, 100, 40, 2.5), fwhm=2.5, ppp=0.1, seed=31 + nr,
+                           bit_depth=12, noise=0.01 * 4095)
+    f = pair.frame0
+    got = ofv.stage_normalize(dev_tensor(f), nr, 1e-4, "f32", bit_depth=12)
+    ref = oracle.normalize(oracle.intensity(f, 12), nr, 1e-4)
+    assert torch.max(torch.abs(o64(got) - ref)).item() < 2e-5
+
+
 @pytest.mark.parametrize("storage,dt", [("f16", torch.float16), ("bf16", torch.bfloat16)])
 def test_normalize_stage_reduced_storage(ofv, storage, dt):
     say("normalize storage", storage)
