@@ -182,6 +182,41 @@ __global__ __launch_bounds__(256) void normalize_kernel(const NormArgs a) {
     // block-uniform: every window of the tile lies inside the frame
     if (x0 >= R && y0 >= R && x0 + kNormTW + R <= J.w && y0 + kNormTH + R <= J.h) {
       constexpr float rn = 1.0f / static_cast<float>(NC * NC);
+      if (R >= 2) {
+        // A window's squared deviations, row by row: those from the row's own
+        // mean m_r (shared by the lane's kNormPX windows) plus NC (m_r - mu)^2.
+        // Every term is a square of a deviation, as in the second-pass form,
+        // with NC + 1 instead of NC * NC (subtract, multiply-add) pairs per output.
+        float mr[NRW], dr[NRW];
+#pragma unroll
+        for (int r = 0; r < NRW; ++r) {
+          mr[r] = hs[r] * (1.0f / static_cast<float>(NC));
+          float acc = 0.0f;
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            const float d = pv[r][c] - mr[r];
+            acc = fmaf(d, d, acc);
+          }
+          dr[r] = acc;
+        }
+#pragma unroll
+        for (int k = 0; k < kNormPX; ++k) {
+          float sm = 0.0f;
+#pragma unroll
+          for (int r = 0; r < NC; ++r) sm += hs[k + r];
+          const float mu = sm * rn;
+          float q1 = 0.0f, q2 = 0.0f;
+#pragma unroll
+          for (int r = 0; r < NC; ++r) {
+            q1 += dr[k + r];
+            const float d = mr[k + r] - mu;
+            q2 = fmaf(d, d, q2);
+          }
+          const float q = fmaf(static_cast<float>(NC), q2, q1);
+          Px<TS>::st(out + k * J.out_pitch, (pv[k + R][R] - mu) * __builtin_amdgcn_rsqf(fmaf(q, rn, a.eps)));
+        }
+        return;
+      }
 #pragma unroll
       for (int k = 0; k < kNormPX; ++k) {
         float sm = 0.0f;
