@@ -103,7 +103,7 @@ def parse():
                     help="particle fields per image of the accuracy sweep (the paper uses 10)")
     ap.add_argument("--suite", default=None,
                     choices=["batch4mp", "live21mp", "stream21mp", "sweep", "estimators", "adjoint512", "paper",
-                             "oracle", "preprocess", "all"],
+                             "oracle", "preprocess", "livestep", "all"],
                     help="run an additional measurement instead of the default workload (one JSON line each)")
     return ap.parse_args()
 
@@ -855,6 +855,50 @@ def suite_paper(args, dev):
             "data": "synthetic 8-bit particle pairs (translation + shear), pre-loaded in device memory"}
 
 
+def suite_livestep(args, dev):
+    """One live step's launches for a kernel trace: the 5120x4096 frame with its 2048^2 and 1024^2 crops as
+    one uneven batch (L 4, KR 10, IT 3, NR 2, FP32 planes, default decompositions), captured in a hipGraph
+    and replayed 30 times after 5 warm-up replays."""
+    import torch
+    import paper_2509_25924_amd as ofv
+    import synth
+    from synth.gpu_render import make_pair_device
+    W, H = 5120, 4096
+    flow = synth.CylinderWake(H, W, t=0.0, dmax=10.0)
+    a, b, _ = make_pair_device(H, W, flow, fwhm=2.5, ppp=0.1, seed=4000, bit_depth=12, noise=0.01 * 4095,
+                               device=dev, max_disp=10.0, with_gt=False)
+    prm = {"num_levels": 4, "kernel_radius": 10, "iterations": 3, "norm_radius": 2, "storage": "f32"}
+    hb = ofv.Handle(W, H, 3)
+    outs = [torch.empty((2, H, W), device=dev), torch.empty((2, 2048, 2048), device=dev),
+            torch.empty((2, 1024, 1024), device=dev)]
+    c2 = (slice(1024, 3072), slice(1536, 3584))
+    c1 = (slice(1536, 2560), slice(2048, 3072))
+
+    def step():
+        ofv.compute_flow_batch([a, a[c2], a[c1]], [b, b[c2], b[c1]], prm, bit_depth=12, outs=outs, handle=hb)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step()
+    torch.cuda.current_stream().wait_stream(s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    hb.bind_stream()
+    for _ in range(5):
+        g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(30):
+        g.replay()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / 30
+    del g
+    hb.close()
+    return {"metric": "live step (5120x4096 + 2048^2 + 1024^2 uneven batch, FP32, default decompositions)",
+            "value": round(1.0 / sec, 1), "unit": "steps/s", "steps": 30, "data": "synthetic cylinder-wake pair"}
+
+
 def suite_preprocess(args, dev):
     """Normalisation (NR 1, 12-bit input, FP32 planes) and the three-level pyramid of one frame at 1, 4 and
     21 Mp through the stage entry points.  Host-timed averages over back-to-back calls: at 1 Mp the Python
@@ -893,7 +937,8 @@ def run_suite(args):
              else [args.suite])
     fns = {"batch4mp": suite_batch4mp, "live21mp": suite_live21mp, "stream21mp": suite_stream21mp,
            "sweep": suite_sweep, "estimators": suite_estimators, "oracle": suite_oracle,
-           "adjoint512": suite_adjoint512, "paper": suite_paper, "preprocess": suite_preprocess}
+           "adjoint512": suite_adjoint512, "paper": suite_paper, "preprocess": suite_preprocess,
+           "livestep": suite_livestep}
     for nm in names:
         print(f"# suite {nm} ...", file=sys.stderr, flush=True)
         r = fns[nm](args, dev)
