@@ -424,7 +424,7 @@ ofv_status run_pipeline(ofv_ctx* h, int n, PairPlan* pp, const ofv_params* p, fl
         J.out_pitch = h->lpitch[l];
         J.w = q.lw[l - 1];
         J.h = q.lh[l - 1];
-        return ((q.lw[l] + 63) / 64) * ((q.lh[l] + 3) / 4);
+        return static_cast<int>(reduce_blocks(q.lw[l], q.lh[l]));
       };
       r = run_chunked(h, nf, ra, fill, [&](const ReduceArgs& a, int b) { return launch_reduce(a, b, s); },
                       "reduce");
@@ -496,7 +496,7 @@ ofv_status run_pipeline(ofv_ctx* h, int n, PairPlan* pp, const ofv_params* p, fl
           J.out_pitch = h->lpitch[l];
           J.w = q.lw[l - 1];
           J.h = q.lh[l - 1];
-          return ((q.lw[l] + 63) / 64) * ((q.lh[l] + 3) / 4);
+          return static_cast<int>(reduce_blocks(q.lw[l], q.lh[l]));
         };
         ofv_status r = run_chunked(h, 2 * ni, ra, fill,
                                    [&](const ReduceArgs& a, int b) { return launch_reduce(a, b, s); },
@@ -1911,7 +1911,7 @@ static ofv_status reduce_common(ofv_ctx* h, int storage, const void* in, int w, 
     J.w = w;
     J.h = hgt;
     J.tile_start = blocks;
-    blocks += (((w + 1) / 2 + 63) / 64) * (((hgt + 1) / 2 + 3) / 4);
+    blocks += static_cast<int>(reduce_blocks((w + 1) / 2, (hgt + 1) / 2));
   }
   hipError_t e = launch_reduce(ra, blocks, h->stream);
   return e == hipSuccess ? OFV_OK : device_error(h, e, "reduce");

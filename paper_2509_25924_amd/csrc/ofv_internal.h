@@ -46,6 +46,9 @@ struct ReduceJob {
   int tile_start;
   int pad_;
 };
+// Output tile of the single-level REDUCE kernel: kRedTW x kRedTH outputs per 256-lane workgroup.
+constexpr int kRedTW = 64, kRedTH = 8;
+inline int64_t reduce_blocks(int64_t wn, int64_t hn) { return ((wn + kRedTW - 1) / kRedTW) * ((hn + kRedTH - 1) / kRedTH); }
 struct ReduceArgs {
   int njobs;
   int storage;         // element type of in/out (flows use ST_F32)

@@ -314,17 +314,16 @@ hipError_t launch_normalize(const NormArgs& a, int nblocks, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// Step 2: REDUCE.  64 x 4 outputs per 256-lane workgroup:
+// Step 2: REDUCE.  64 x 8 outputs per 256-lane workgroup (kRedTW x kRedTH):
 //   out(x, y) = scale * sum_j w_j sum_i w_i in(clamp(2x+i), clamp(2y+j)),
-// w = [1, 4, 6, 4, 1] / 16, i, j = -2..2.  The 131 x 11 input tile (indices
+// w = [1, 4, 6, 4, 1] / 16, i, j = -2..2.  The 131 x 19 input tile (indices
 // clamped into the plane) is staged in LDS with coalesced row loads, the
-// horizontal 5-tap pass writes 11 x 64 row sums to LDS and the vertical
-// pass combines 5 of them per output.
+// horizontal 5-tap pass writes 19 x 64 row sums to LDS and the vertical
+// pass combines 5 of them per output, two outputs per lane (the input tile
+// is 2.4 input rows per output row instead of 2.75 with 4-row tiles).
 // ---------------------------------------------------------------------------
-constexpr int kRedTW = 64;
-constexpr int kRedTH = 4;
 constexpr int kRedInW = 2 * kRedTW + 3;  // 131 input columns
-constexpr int kRedInH = 2 * kRedTH + 3;  // 11 input rows
+constexpr int kRedInH = 2 * kRedTH + 3;  // 19 input rows
 
 template <typename TS>
 __global__ __launch_bounds__(256) void reduce_kernel(const ReduceArgs a) {
@@ -376,16 +375,20 @@ __global__ __launch_bounds__(256) void reduce_kernel(const ReduceArgs a) {
   }
   __syncthreads();
   const int lx = threadIdx.x & 63;
-  const int ly = threadIdx.x >> 6;
   const int x = x0 + lx;
-  const int y = y0 + ly;
-  if (x >= wn || y >= hn) return;
-  float acc = w0 * th[2 * ly][lx];
-  acc += w1 * th[2 * ly + 1][lx];
-  acc += w2 * th[2 * ly + 2][lx];
-  acc += w1 * th[2 * ly + 3][lx];
-  acc += w0 * th[2 * ly + 4][lx];
-  Px<TS>::st(static_cast<TS*>(J.out) + static_cast<int64_t>(y) * J.out_pitch + x, a.scale * acc);
+  if (x >= wn) return;
+#pragma unroll
+  for (int ly = threadIdx.x >> 6; ly < kRedTH; ly += 4) {
+    const int y = y0 + ly;
+    if (y < hn) {
+      float acc = w0 * th[2 * ly][lx];
+      acc += w1 * th[2 * ly + 1][lx];
+      acc += w2 * th[2 * ly + 2][lx];
+      acc += w1 * th[2 * ly + 3][lx];
+      acc += w0 * th[2 * ly + 4][lx];
+      Px<TS>::st(static_cast<TS*>(J.out) + static_cast<int64_t>(y) * J.out_pitch + x, a.scale * acc);
+    }
+  }
 }
 
 hipError_t launch_reduce(const ReduceArgs& a, int nblocks, hipStream_t s) {
