@@ -38,7 +38,8 @@ ofv_status ofv_stage_reduce(ofv_handle h, int storage, const void* in, int width
                             int64_t in_pitch, void* out, int64_t out_pitch);
 
 /* Pipeline step 2 as the estimator runs it: `levels` (1..3) successive
- * REDUCE levels of `in` in one launch.  out[k] receives level k + 1
+ * REDUCE levels of `in` in one launch (one launch per level from 16 Mi
+ * input pixels on).  out[k] receives level k + 1
  * (ceil(width / 2^(k+1)) x ceil(height / 2^(k+1)), pitch out_pitch[k]);
  * each level is rounded to `storage` before the next is formed, so the
  * result equals `levels` chained ofv_stage_reduce calls bit for bit.  The

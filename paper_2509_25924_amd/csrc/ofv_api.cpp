@@ -410,7 +410,7 @@ ofv_status run_pipeline(ofv_ctx* h, int n, PairPlan* pp, const ofv_params* p, fl
   for (int l = 1; l < L;) {
     int64_t lpx = 0;  // input pixels of this launch
     for (const auto& f : fj) lpx += static_cast<int64_t>(pp[f.first].lw[l - 1]) * pp[f.first].lh[l - 1];
-    const int nlev = lpx >= (int64_t{16} << 20) ? 1 : std::min(kMaxReduceLevels, L - l);
+    const int nlev = lpx >= kReduceSingleLevelPixels ? 1 : std::min(kMaxReduceLevels, L - l);
     ofv_status r = OFV_OK;
     if (nlev == 1) {
       ReduceArgs ra{};
@@ -1941,6 +1941,21 @@ ofv_status ofv_stage_pyramid(ofv_handle h, int storage, const void* in, int widt
     if (out_pitch[k] < w) return fail(h, OFV_ERR_INVALID_ARG, "out_pitch[%d] < %d", k, w);
   }
   if (levels == 1) return reduce_common(h, storage, in, width, height, in_pitch, out[0], out_pitch[0], 1.0f, 1, 0, 0);
+  if (static_cast<int64_t>(width) * height >= kReduceSingleLevelPixels) {
+    // as the estimator builds pyramids of this size: one launch per level
+    const void* src = in;
+    int64_t sp = in_pitch;
+    int sw = width, sh = height;
+    for (int k = 0; k < levels; ++k) {
+      const ofv_status rk = reduce_common(h, storage, src, sw, sh, sp, out[k], out_pitch[k], 1.0f, 1, 0, 0);
+      if (rk != OFV_OK) return rk;
+      src = out[k];
+      sp = out_pitch[k];
+      sw = (sw + 1) / 2;
+      sh = (sh + 1) / 2;
+    }
+    return OFV_OK;
+  }
   ofv_status r = stage_device(h);
   if (r != OFV_OK) return r;
   DeviceGuard g(h->device);

@@ -81,6 +81,9 @@ struct ReduceMArgs {
 // of another), smaller launches 16 x 8 tiles with 1024 lanes (the smallest
 // halo; 90 KB, one workgroup per compute unit).
 constexpr int64_t kReduceMSmallPixels = int64_t{4} << 20;
+// Launches over at least this many input pixels build one level per launch
+// instead (the single-level kernel, wider spread over the compute units).
+constexpr int64_t kReduceSingleLevelPixels = int64_t{16} << 20;
 inline bool reduce_multi_small(int nlev, int64_t pixels) { return nlev == 3 && pixels >= kReduceMSmallPixels; }
 constexpr int reduce_multi_tw(int nlev, bool small) { return nlev == 3 ? (small ? 8 : 16) : 32; }
 constexpr int reduce_multi_th(int, bool) { return 8; }
